@@ -1,0 +1,86 @@
+/*
+ * CPU oracle for the coupled lattice Boltzmann hot path -- TEST INFRASTRUCTURE.
+ *
+ * A plain, slow, FP64 implementation of what the GPU library computes, written
+ * from the paper (Werner, Rettinger, Ruede: coupling fully resolved light
+ * particles with the LBM on adaptively refined grids).  Only the test suite,
+ * the smoke check and the benchmark's CPU-baseline leg load it.  It shares no
+ * code, header, table or helper with the GPU library.
+ *
+ * Conventions: lattice units of the finest level; cell (i,j,k) has its centre
+ * at (i+1/2, j+1/2, k+1/2); population arrays are [19][nz][ny][nx] C order.
+ * All functions return 0 on success and a negative value on error.
+ */
+#ifndef VMLBM_ORACLE_H
+#define VMLBM_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int n[3];                 /* cells in x, y, z */
+  int periodic[3];          /* 1 periodic, 0 halfway no-slip wall at both ends */
+  double wall_velocity[2][3]; /* low/high wall of the first non-periodic axis */
+  double omega;             /* s_nu (= s+ of TRT) */
+  double magic;             /* Lambda */
+  double body_force[3];     /* fluid force density (Guo forcing) */
+  double gravity[3];        /* acts on particles only */
+} ora_config;
+
+typedef struct {
+  double x[3], u[3], w[3];
+  double radius, density_ratio, cv, cv_omega;
+  int fixed;
+} ora_sphere;
+
+/* lattice tables in the oracle's order */
+void ora_lattice(int c[19][3], double w[19], int opp[19]);
+
+/* single-cell TRT collision with Guo forcing on full populations f[19] */
+void ora_collide_cell(const double f[19], double omega, double magic,
+                      const double F[3], double out[19]);
+/* incompressible equilibrium f^eq(rho, u) */
+void ora_equilibrium(double rho, const double u[3], double out[19]);
+/* boundary distance ratio along c from a fluid point at offset d from a
+ * sphere centre; returns -1 if the segment does not enter the sphere */
+double ora_link_delta(const double d[3], const int c[3], double radius);
+
+/* ---- uniform grid ---- */
+void* ora_create(const ora_config* cfg);
+int ora_add_sphere(void* h, const ora_sphere* s);
+int ora_init(void* h, double rho, const double* u0 /* [3][nz][ny][nx] or NULL */);
+int ora_step(void* h, int nsteps);
+int ora_post_collision(void* h, double* out);  /* f~(n), solid cells = 0 */
+int ora_pre_collision(void* h, double* out);   /* f(n), solid cells = 0 */
+int ora_owner(void* h, int* out);              /* -1 fluid, else sphere id */
+int ora_force_torque(void* h, int id, double F[3], double T[3]); /* raw F^n of last step */
+int ora_particle(void* h, int id, double x[3], double u[3], double w[3]);
+int ora_fields(void* h, double* rho, double* u /* [3][cells] */);
+int ora_steps_done(void* h);
+void ora_destroy(void* h);
+
+/* total mass and momentum over fluid cells of the pre-collision state */
+int ora_totals(void* h, double* mass, double mom[3]);
+
+/* Exact derivative of the time-averaged drag
+ *   J = 1/(n_steps-avg_from) * sum_{n=avg_from}^{n_steps-1} F_z^n
+ * with respect to (body force magnitude along +z, omega), magic held fixed,
+ * by forward propagation of dual numbers.  Fixed spheres only, start f = w. */
+int ora_drag_gradient(const ora_config* cfg, const ora_sphere* spheres, int nspheres,
+                      int n_steps, int avg_from, double* J, double grad[2]);
+/* Same forward map, value only (for finite differences) */
+int ora_drag_value(const ora_config* cfg, const ora_sphere* spheres, int nspheres,
+                   int n_steps, int avg_from, double* J);
+
+/* particle update alone (no fluid): nsteps updates with constant raw
+ * hydrodynamic F, T; out[nsteps][15] = x, u, w, a, beta after each step */
+int ora_vm_trajectory(const ora_sphere* s, const double F[3], const double T[3], const double g[3],
+                      int nsteps, double* out);
+
+int ora_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,169 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds workload parameters and random draws only.  It contains none
+of the lattice Boltzmann / coupling arithmetic: both the CPU oracle and the GPU
+library receive what is produced here as plain inputs.
+
+Workloads (lattice units of the finest level, cell (i,j,k) has its centre at
+(i+1/2, j+1/2, k+1/2)):
+
+* ``tiny``      periodic 32^3 box, fixed sphere r=6 in the centre, body force
+                1e-5 along z, equilibrium start perturbed by U(-1e-3, 1e-3).
+* ``rising``    256^3, x/y periodic, no-slip walls at z=0 and z=256, one light
+                sphere (density ratio 0.5, r=12, C_v=0.5) released at rest at
+                (128,128,64); Galileo number 150 (Eq. 13 with u_g=0.01).
+* ``refined``   3-level block grid (16^3 blocks), coarse 128x128x512, periodic,
+                sphere r=16 finest cells, density ratio 0.1, C_v=0.5, Ga=250.
+* ``precision`` 512^3 periodic, 8 fixed spheres r=20 at seeded positions,
+                body force 1e-5 along z.
+* ``adjoint``   128^3 periodic, fixed sphere r=10 in the centre, body force
+                1e-5 along z, omega=1.6; drag averaged over steps 1500..1999.
+
+Galileo-number parameterisation (Eq. 13): u_g = sqrt(|pi_p-1| g d_p) = 0.01,
+Ga = u_g d_p / nu, and nu = (1/omega - 1/2)/3 in lattice units.  The derived
+numbers are written out below next to the inputs they come from.
+"""
+import numpy as np
+
+U_G = 0.01          # gravitational velocity in lattice units (Sec. 3.1)
+MAGIC = 3.0 / 16.0  # TRT magic parameter (Sec. 2.1)
+
+
+def _ga_params(ga, density_ratio, d_p):
+    """Viscosity, omega and gravity for a Galileo number (Eq. 13)."""
+    nu = U_G * d_p / ga
+    omega = 1.0 / (3.0 * nu + 0.5)
+    g = U_G * U_G / (abs(density_ratio - 1.0) * d_p)
+    return nu, omega, g
+
+
+def base_config(n, periodic=(1, 1, 1), omega=1.6, body_force=(0.0, 0.0, 0.0),
+                gravity=(0.0, 0.0, 0.0), wall_velocity=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))):
+    return {
+        "n": tuple(int(v) for v in n),
+        "periodic": tuple(int(v) for v in periodic),
+        "omega": float(omega),
+        "magic": MAGIC,
+        "body_force": tuple(float(v) for v in body_force),
+        "gravity": tuple(float(v) for v in gravity),
+        "wall_velocity": tuple(tuple(float(v) for v in w) for w in wall_velocity),
+    }
+
+
+def sphere(x, radius, density_ratio=1.0, cv=0.0, cv_omega=None, fixed=True,
+           u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0)):
+    return {
+        "x": tuple(float(v) for v in x),
+        "u": tuple(float(v) for v in u),
+        "w": tuple(float(v) for v in w),
+        "radius": float(radius),
+        "density_ratio": float(density_ratio),
+        "cv": float(cv),
+        "cv_omega": float(cv if cv_omega is None else cv_omega),
+        "fixed": int(bool(fixed)),
+    }
+
+
+def velocity_perturbation(n, seed=0, amplitude=1e-3):
+    """One draw of U(-a, a) for the full C-order [3][nz][ny][nx] array."""
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-amplitude, amplitude, size=(3, nz, ny, nx))
+
+
+def place_spheres(n, count, radius, gap, seed=0):
+    """Centres uniform in the periodic box, rejected when the minimum-image
+    centre distance to an accepted one is below 2r + gap; accepted in draw
+    order."""
+    rng = np.random.default_rng(seed)
+    box = np.array(n, dtype=np.float64)
+    out = []
+    min_d = 2.0 * radius + gap
+    tries = 0
+    while len(out) < count:
+        tries += 1
+        if tries > 100000:
+            raise RuntimeError("sphere placement did not converge")
+        c = rng.uniform(0.0, 1.0, size=3) * box
+        ok = True
+        for o in out:
+            d = c - o
+            d -= box * np.round(d / box)
+            if np.sqrt(np.dot(d, d)) < min_d:
+                ok = False
+                break
+        if ok:
+            out.append(c)
+    return [tuple(float(v) for v in c) for c in out]
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+
+def tiny(n=32, radius=6.0):
+    c = n / 2.0
+    cfg = base_config((n, n, n), omega=1.6, body_force=(0.0, 0.0, 1e-5))
+    return {
+        "name": f"tiny{n}",
+        "config": cfg,
+        "spheres": [sphere((c, c, c), radius, fixed=True)],
+        "u0": velocity_perturbation((n, n, n), seed=0),
+        "steps": 200,
+    }
+
+
+def rising(n=(256, 256, 256), radius=12.0, height=64.0, ga=150.0, density_ratio=0.5, cv=0.5):
+    _, omega, g = _ga_params(ga, density_ratio, 2.0 * radius)
+    cfg = base_config(n, periodic=(1, 1, 0), omega=omega, gravity=(0.0, 0.0, -g))
+    return {
+        "name": "rising%dx%dx%d" % tuple(n),
+        "config": cfg,
+        "spheres": [sphere((n[0] / 2.0, n[1] / 2.0, height), radius, density_ratio=density_ratio,
+                           cv=cv, fixed=False)],
+        "u0": None,
+        "steps": 2000,
+    }
+
+
+def precision(n=512, count=8, radius=20.0, seed=0):
+    cfg = base_config((n, n, n), omega=1.6, body_force=(0.0, 0.0, 1e-5))
+    centres = place_spheres((n, n, n), count, radius, gap=4.0, seed=seed)
+    return {
+        "name": f"precision{n}",
+        "config": cfg,
+        "spheres": [sphere(c, radius, fixed=True) for c in centres],
+        "u0": None,
+        "steps": 1000,
+    }
+
+
+def adjoint(n=128, radius=10.0, steps=2000, avg_from=1500, ckpt_every=50):
+    c = n / 2.0
+    cfg = base_config((n, n, n), omega=1.6, body_force=(0.0, 0.0, 1e-5))
+    return {
+        "name": f"adjoint{n}",
+        "config": cfg,
+        "spheres": [sphere((c, c, c), radius, fixed=True)],
+        "u0": None,
+        "steps": steps,
+        "avg_from": avg_from,
+        "ckpt_every": ckpt_every,
+    }
+
+
+def refined(coarse=(128, 128, 512), levels=3, block=16, radius=16.0, ga=250.0,
+            density_ratio=0.1, cv=0.5, centre_coarse=(64.0, 64.0, 64.0)):
+    _, omega_f, g = _ga_params(ga, density_ratio, 2.0 * radius)
+    scale = 2 ** (levels - 1)
+    cfg = base_config(coarse, omega=omega_f, gravity=(0.0, 0.0, -g))
+    cfg["levels"] = levels
+    cfg["block"] = block
+    return {
+        "name": "refined%dx%dx%d_L%d" % (coarse + (levels,)),
+        "config": cfg,
+        "spheres": [sphere(tuple(v * scale for v in centre_coarse), radius,
+                           density_ratio=density_ratio, cv=cv, fixed=False)],
+        "u0": None,
+        "steps": 500,
+    }

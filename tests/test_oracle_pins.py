@@ -1,0 +1,353 @@
+"""Pins of the CPU oracle against facts the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: exact
+lattice identities, conservation laws, closed-form flows, symmetry, brute
+force on tiny inputs, or a closed-form particle recursion.  A plausible slip
+in the oracle (a dropped term, a wrong sign or index, a swapped operand)
+breaks at least one of them.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import synth
+
+
+# --------------------------------------------------------------------------
+# lattice (Sec. 2.1, D3Q19): exact rational moment identities
+# --------------------------------------------------------------------------
+def test_lattice_moments_exact(ora):
+    c, w, opp = ora.lattice()
+    W = [Fraction(1, 3) if (c[q] ** 2).sum() == 0 else Fraction(1, 18) if (c[q] ** 2).sum() == 1
+         else Fraction(1, 36) for q in range(19)]
+    assert np.allclose(w, [float(x) for x in W], rtol=0, atol=0)
+    assert sum(W) == 1
+    for a in range(3):
+        assert sum(W[q] * int(c[q, a]) for q in range(19)) == 0
+        for b in range(3):
+            m2 = sum(W[q] * int(c[q, a]) * int(c[q, b]) for q in range(19))
+            assert m2 == (Fraction(1, 3) if a == b else 0)
+            for g in range(3):
+                assert sum(W[q] * int(c[q, a] * c[q, b] * c[q, g]) for q in range(19)) == 0
+                for d in range(3):
+                    m4 = sum(W[q] * int(c[q, a] * c[q, b] * c[q, g] * c[q, d]) for q in range(19))
+                    iso = Fraction((a == b) * (g == d) + (a == g) * (b == d) + (a == d) * (b == g), 9)
+                    assert m4 == iso
+    # 19 distinct velocities, |c|^2 <= 2, opposites
+    assert len({tuple(v) for v in c}) == 19
+    for q in range(19):
+        assert (c[opp[q]] == -c[q]).all()
+
+
+# --------------------------------------------------------------------------
+# equilibrium and collision (Sec. 2.1): conservation, fixed point, TRT
+# --------------------------------------------------------------------------
+def test_equilibrium_moments(ora):
+    c, _, _ = ora.lattice()
+    rho, u = 1.013, np.array([0.021, -0.013, 0.007])
+    feq = ora.equilibrium(rho, u)
+    assert abs(feq.sum() - rho) < 1e-15
+    assert np.abs(feq @ c - u).max() < 1e-16          # rho0 = 1: sum f c = u
+    P = np.einsum("q,qa,qb->ab", feq, c, c)
+    assert np.abs(P - (rho / 3.0 * np.eye(3) + np.outer(u, u))).max() < 1e-15
+
+
+def test_s_minus_from_magic(ora):
+    # Lambda = (1/s+ - 1/2)(1/s- - 1/2) = 3/16 at s+ = 1.6 gives s- = 1/2:
+    # check through the collision: odd non-equilibrium decays by (1 - s-).
+    c, _, opp = ora.lattice()
+    feq = ora.equilibrium(1.0, np.zeros(3))
+    d = np.zeros(19)
+    d[1], d[2] = 1e-4, -1e-4                          # pure odd perturbation, zero momentum change
+    d[3], d[4] = -1e-4, 1e-4
+    f = feq + d
+    # momentum is not zero here, so compare against the post-collision
+    # equilibrium of the same moments
+    out = ora.collide_cell(f, 1.6, 3.0 / 16.0, np.zeros(3))
+    rho = f.sum()
+    u = f @ c
+    e = ora.equilibrium(rho, u)
+    neq_in = f - e
+    neq_out = out - e
+    odd_in = 0.5 * (neq_in - neq_in[opp])
+    odd_out = 0.5 * (neq_out - neq_out[opp])
+    assert np.abs(odd_out - 0.5 * odd_in).max() < 2e-17
+
+
+@pytest.mark.parametrize("omega", [1.6, 1.98, 0.7])
+def test_collision_invariants(ora, omega):
+    c, _, opp = ora.lattice()
+    rng = np.random.default_rng(7)
+    F = np.array([1e-5, -2e-5, 3e-5])
+    magic = 3.0 / 16.0
+    for _ in range(20):
+        u = rng.uniform(-0.05, 0.05, 3)
+        f = ora.equilibrium(1.0 + rng.uniform(-0.02, 0.02), u) + rng.normal(0, 1e-3, 19)
+        out = ora.collide_cell(f, omega, magic, F)
+        # mass conserved, momentum changed by exactly F
+        assert abs(math.fsum(out) - math.fsum(f)) < 1e-15
+        for a in range(3):
+            assert abs(math.fsum(np.concatenate([out * c[:, a], -f * c[:, a]])) - F[a]) < 1e-15
+    # without force the equilibrium is a fixed point
+    f = ora.equilibrium(1.02, [0.03, -0.01, 0.02])
+    assert np.abs(ora.collide_cell(f, omega, magic, np.zeros(3)) - f).max() < 5e-16
+    # even and odd non-equilibrium parts relax by (1 - s+) and (1 - s-)
+    sp = omega
+    sm = 1.0 / (0.5 + magic / (1.0 / omega - 0.5))
+    f = ora.equilibrium(1.0, [0.02, 0.01, -0.03]) + rng.normal(0, 1e-3, 19)
+    rho, u = f.sum(), f @ c
+    e = ora.equilibrium(rho, u)
+    out = ora.collide_cell(f, omega, magic, np.zeros(3))
+    ni, no = f - e, out - e
+    assert np.abs(0.5 * (no + no[opp]) - (1 - sp) * 0.5 * (ni + ni[opp])).max() < 5e-16
+    assert np.abs(0.5 * (no - no[opp]) - (1 - sm) * 0.5 * (ni - ni[opp])).max() < 5e-16
+
+
+# --------------------------------------------------------------------------
+# streaming and walls: closed-form flows
+# --------------------------------------------------------------------------
+def test_poiseuille_exact_trt(ora):
+    """TRT with Lambda = 3/16 and halfway bounce-back reproduces the discrete
+    parabola u(y) = F y (H - y) / (2 nu) exactly (Ginzburg 2008)."""
+    H, Fx = 16, 1e-6
+    cfg = synth.base_config((1, H, 1), periodic=(1, 0, 1), omega=1.6, body_force=(Fx, 0, 0))
+    o = ora.Uniform(cfg)
+    o.init()
+    o.step(20000)
+    _, u = o.fields()
+    nu = (1 / 1.6 - 0.5) / 3
+    y = np.arange(H) + 0.5
+    ua = Fx * y * (H - y) / (2 * nu)
+    assert np.abs(u[0, 0, :, 0] - ua).max() / ua.max() < 1e-9
+    assert np.abs(u[1:]).max() < 1e-14
+    m, _ = o.totals()
+    assert abs(m - H) < 20000 * H * 1e-15            # repeated round-off only
+
+
+def test_couette_linear(ora):
+    H, U = 12, 0.01
+    cfg = synth.base_config((1, H, 1), periodic=(1, 0, 1), omega=1.2,
+                            wall_velocity=((0, 0, 0), (U, 0, 0)))
+    o = ora.Uniform(cfg)
+    o.init()
+    o.step(6000)
+    _, u = o.fields()
+    y = np.arange(H) + 0.5
+    assert np.abs(u[0, 0, :, 0] - U * y / H).max() < 1e-12
+
+
+@pytest.mark.parametrize("zb", [3.3, 3.5, 3.8, 4.05])
+def test_cli_couette_off_lattice(ora, zb):
+    """Eq. 10 (CLI) is exact for a linear profile: Couette flow between a
+    moving halfway wall at z = H and a stationary near-planar wall at the
+    fractional height zb (the cap of a sphere of radius 1e6) follows
+    u = U (z - zb) / (H - zb); the residual is the cap's curvature, ~1/R."""
+    H, U, R = 16, 0.01, 1e6
+    cfg = synth.base_config((1, 1, H), periodic=(1, 1, 0), omega=1.2,
+                            wall_velocity=((0, 0, 0), (U, 0, 0)))
+    o = ora.Uniform(cfg, [synth.sphere((0.5, 0.5, zb - R), R)])
+    o.init()
+    o.step(8000)
+    _, u = o.fields()
+    fl = o.owner()[:, 0, 0] < 0
+    z = np.arange(H) + 0.5
+    err = np.abs(u[0, fl, 0, 0] - U * (z[fl] - zb) / (H - zb)).max() / U
+    assert err < 1e-7
+
+
+def test_periodic_momentum_growth(ora):
+    """Obstacle-free periodic box: mass constant, momentum grows by N F."""
+    cfg = synth.base_config((8, 6, 5), omega=1.3, body_force=(1e-5, -2e-5, 3e-5))
+    o = ora.Uniform(cfg)
+    u0 = synth.velocity_perturbation((8, 6, 5), seed=3)
+    o.init(1.0, u0)
+    m0, j0 = o.totals()
+    o.step(37)
+    m, j = o.totals()
+    N = 8 * 6 * 5
+    assert abs(m - m0) < 1e-12
+    assert np.abs(j - j0 - 37 * N * np.array([1e-5, -2e-5, 3e-5])).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# sphere geometry (Sec. 2.3): mapping and boundary distance by brute force
+# --------------------------------------------------------------------------
+def test_mapping_brute_force(ora):
+    n = (14, 13, 12)
+    sph = [synth.sphere((3.3, 6.1, 11.6), 3.7), synth.sphere((10.2, 1.4, 4.0), 2.6)]
+    o = ora.Uniform(synth.base_config(n), sph)
+    o.init()
+    own = o.owner()
+    exp = -np.ones((n[2], n[1], n[0]), dtype=int)
+    for k in range(n[2]):
+        for j in range(n[1]):
+            for i in range(n[0]):
+                for p, s in enumerate(sph):
+                    d = np.array([i + 0.5, j + 0.5, k + 0.5]) - np.array(s["x"])
+                    d -= np.array(n) * np.round(d / np.array(n))   # periodic image
+                    if d @ d <= s["radius"] ** 2:
+                        exp[k, j, i] = p
+                        break
+    assert (own == exp).all()
+    assert (own >= 0).sum() > 0
+
+
+def test_link_delta_bisection(ora):
+    c, _, _ = ora.lattice()
+    rng = np.random.default_rng(5)
+    r = 4.3
+    checked = 0
+    for _ in range(4000):
+        d = rng.uniform(-6, 6, 3)
+        q = rng.integers(1, 19)
+        if d @ d <= r * r or (d + c[q]) @ (d + c[q]) > r * r:
+            continue
+        lo, hi = 0.0, 1.0
+        for _ in range(80):
+            mid = 0.5 * (lo + hi)
+            p = d + mid * c[q]
+            if p @ p > r * r:
+                lo = mid
+            else:
+                hi = mid
+        assert abs(ora.link_delta(d, c[q], r) - hi) < 1e-13
+        checked += 1
+    assert checked > 100
+
+
+# --------------------------------------------------------------------------
+# coupling (Eqs. 10-12): momentum exchange identity, symmetry, invariance
+# --------------------------------------------------------------------------
+def test_fixed_sphere_momentum_identity(ora):
+    """Fluid momentum changes by N_f F minus the MEM force, exactly (fixed
+    obstacle, Eq. 11 with v = 0): sum j(n+1) = sum j(n) + N_f F - F^n."""
+    n = (20, 18, 22)
+    F = np.array([2e-5, -1e-5, 1e-5])
+    cfg = synth.base_config(n, omega=1.7, body_force=tuple(F))
+    o = ora.Uniform(cfg, [synth.sphere((9.3, 8.8, 11.4), 4.6)])
+    o.init(1.0, synth.velocity_perturbation(n, seed=1))
+    Nf = (o.owner() < 0).sum()
+    for _ in range(5):
+        _, j0 = o.totals()
+        o.step(1)
+        _, j1 = o.totals()
+        Fh, _ = o.force_torque(0)
+        assert np.abs(Fh).max() > 1e-4
+        assert np.abs(j1 - j0 - Nf * F + Fh).max() < 1e-13
+
+
+def test_symmetric_sphere_zero_torque(ora):
+    """Config-1 geometry without perturbation: mirror symmetry gives T = 0 and
+    F along z only."""
+    w = synth.tiny()
+    o = ora.Uniform(w["config"], w["spheres"])
+    o.init()
+    o.step(10)
+    F, T = o.force_torque(0)
+    assert F[2] > 0
+    assert abs(F[0]) < 1e-13 and abs(F[1]) < 1e-13
+    assert np.abs(T).max() < 1e-12
+
+
+def test_comoving_uniform_flow_invariant(ora):
+    """A sphere translating with a uniform flow of the same velocity: the
+    moving-wall CLI term, the Galilean-invariant link force, re-mapping and
+    refill must leave f = f^eq(1, U) untouched and the sphere unaccelerated.
+    (A factor 3 too large in the wall term, a missing -v in Eq. 11 or a
+    non-equilibrium refill all break it.)  The sphere is made very heavy: on
+    an off-lattice staircase the Galilean term of Eq. 11 leaves a small
+    torque of order U^2 from the direction dependence of the chord lengths,
+    which must not spin it up during the test."""
+    n = (20, 20, 20)
+    U = np.array([0.03, -0.02, 0.025])
+    cfg = synth.base_config(n, omega=1.4)
+    sph = synth.sphere((9.7, 10.2, 10.45), 4.3, density_ratio=1e9, cv=0.0, fixed=False, u=tuple(U))
+    o = ora.Uniform(cfg, [sph])
+    u0 = np.broadcast_to(U[:, None, None, None], (3, 20, 20, 20)).copy()
+    o.init(1.0, u0)
+    own0 = o.owner()
+    x0, _, _ = o.particle(0)
+    nsteps = 60
+    o.step(nsteps)
+    own = o.owner()
+    assert (own != own0).sum() > 50                    # cells were covered and uncovered
+    feq = ora.equilibrium(1.0, U)
+    f = o.pre_collision()
+    fluid = own < 0
+    assert np.abs(f[:, fluid] - feq[:, None]).max() < 1e-13
+    x, u, w = o.particle(0)
+    assert np.abs(u - U).max() < 1e-13 and np.abs(w).max() < 1e-12
+    assert np.abs(x - (x0 + nsteps * U)).max() < 1e-11
+    F, T = o.force_torque(0)
+    assert np.abs(F).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# particle update (Sec. 2.2, Sec. 3.3, Algorithm 1): closed forms
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("rho_p,cv", [(0.5, 0.5), (0.1, 1.0), (2.0, 0.0)])
+def test_vm_update_closed_form(ora, rho_p, cv):
+    """Constant force, no fluid: a_n = (F/m_p)(1 - r^(n+1)), r = C_v/(pi_p+C_v),
+    u and x follow the velocity-Verlet sums of that sequence."""
+    r_p = 3.0
+    V = 4.0 / 3.0 * np.pi * r_p ** 3
+    Fh = np.array([1e-4, -2e-4, 5e-5])
+    Th = np.array([3e-4, 1e-4, -2e-4])
+    g = np.array([0.0, 0.0, -1e-5])
+    s = synth.sphere((0.0, 0.0, 0.0), r_p, density_ratio=rho_p, cv=cv, fixed=False, u=(1e-3, 0, 0))
+    n = 40
+    out = ora.vm_trajectory(s, Fh, Th, g, n)
+    Ftot = Fh + (rho_p - 1.0) * g * V
+    A = Ftot / (rho_p * V)                      # physical acceleration
+    rr = cv / (rho_p + cv)
+    k = np.arange(n)
+    a_exp = A[None, :] * (1 - rr ** (k + 1))[:, None]
+    assert np.abs(out[:, 9:12] - a_exp).max() < 1e-15
+    I = 0.4 * rho_p * V * r_p ** 2
+    b_exp = (Th / I)[None, :] * (1 - rr ** (k + 1))[:, None]
+    assert np.abs(out[:, 12:15] - b_exp).max() < 1e-15
+    # velocity: u_n = u_-1 + sum_{k<=n} a_k - a_n / 2 (a_-1 = 0)
+    S = A[None, :] * ((k + 1) - rr * (1 - rr ** (k + 1)) / (1 - rr))[:, None]
+    u_exp = np.array([1e-3, 0, 0])[None, :] + S - 0.5 * a_exp
+    assert np.abs(out[:, 3:6] - u_exp).max() < 1e-14
+    # position: x_{n+1} = x_n + u_n + a_n / 2
+    x_exp = np.cumsum(u_exp + 0.5 * a_exp, axis=0)
+    assert np.abs(out[:, 0:3] - x_exp).max() < 1e-12
+
+
+def test_galileo_parameterisation():
+    """Eq. 13 with u_g = 0.01 for the rising-sphere workload."""
+    w = synth.rising()
+    cfg, s = w["config"], w["spheres"][0]
+    nu = (1.0 / cfg["omega"] - 0.5) / 3.0
+    d = 2 * s["radius"]
+    g = -cfg["gravity"][2]
+    ug = np.sqrt(abs(s["density_ratio"] - 1.0) * g * d)
+    assert abs(ug - 0.01) < 1e-14
+    assert abs(ug * d / nu - 150.0) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# differentiation: dual-number gradient vs central differences
+# --------------------------------------------------------------------------
+def test_drag_gradient_vs_finite_difference(ora):
+    n = 12
+    cfg = synth.base_config((n, n, n), omega=1.6, body_force=(0, 0, 1e-5))
+    sph = [synth.sphere((6.0, 6.0, 6.0), 2.7)]
+    steps, avg = 60, 40
+    J, g = ora.drag_gradient(cfg, sph, steps, avg)
+    J0 = ora.drag_value(cfg, sph, steps, avg)
+    assert abs(J - J0) <= 1e-11 * abs(J0)
+    # body force: J is linear in F (Stokes-like at these amplitudes) up to O(F^2)
+    hF = 1e-4 * 1e-5
+    cp = dict(cfg, body_force=(0, 0, 1e-5 + hF))
+    cm = dict(cfg, body_force=(0, 0, 1e-5 - hF))
+    fd = (ora.drag_value(cp, sph, steps, avg) - ora.drag_value(cm, sph, steps, avg)) / (2 * hF)
+    assert abs(fd - g[0]) <= 1e-6 * abs(g[0])
+    hw = 1e-4 * 1.6
+    cp = dict(cfg, omega=1.6 + hw)
+    cm = dict(cfg, omega=1.6 - hw)
+    fd = (ora.drag_value(cp, sph, steps, avg) - ora.drag_value(cm, sph, steps, avg)) / (2 * hw)
+    assert abs(fd - g[1]) <= 1e-5 * abs(g[1])
