@@ -1,0 +1,181 @@
+/*
+ * vmlbm -- MI355X (gfx950) library for the coupled lattice Boltzmann hot path
+ * of Werner, Rettinger & Ruede, "Coupling fully resolved light particles with
+ * the lattice Boltzmann method on adaptively refined grids":
+ *
+ *   D3Q19 TRT stream-collide (Sec. 2.1), moving-wall CLI boundary on particle
+ *   links (Sec. 2.3, Eq. 10), momentum-exchange link forces and their
+ *   per-particle sums (Eqs. 11-12), virtual-mass particle update (Sec. 2.2,
+ *   Sec. 3.3, Algorithm 1), cell re-mapping and refill of uncovered cells
+ *   (Sec. 2.3), a 2:1 block-refined grid with explosion, coalescence and
+ *   sub-cycling (Sec. 4.1-4.2), populations stored as FP64/FP32/FP16
+ *   deviations from the lattice weights, and the adjoint of the
+ *   fixed-sphere drag with respect to body force and relaxation rate.
+ *
+ * Units: lattice units of the FINEST level (cell size 1, time step 1,
+ * rho0 = 1).  Cell (i,j,k) has its centre at (i+1/2, j+1/2, k+1/2).
+ *
+ * Every function returns an int status: VMLBM_OK (0) or a negative error.
+ * No exception crosses the boundary.  vmlbm_last_error() returns a message
+ * owned by the context, valid until its next call.  A context is used from
+ * one host thread at a time.
+ *
+ * Memory: the caller owns the device workspace (vmlbm_required_bytes, then
+ * vmlbm_bind_workspace with a device pointer that outlives the context) and
+ * every host buffer.  The library never allocates or frees device memory
+ * except a few bytes of pinned host memory for status read-back.
+ * All device work is enqueued on the bound stream; read functions
+ * synchronise that stream.
+ */
+#ifndef VMLBM_H
+#define VMLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+#pragma GCC visibility push(default)
+
+#define VMLBM_OK 0
+#define VMLBM_EINVAL (-1)     /* bad argument */
+#define VMLBM_ENOMEM (-2)     /* workspace too small / host allocation failed */
+#define VMLBM_EDEVICE (-3)    /* HIP runtime error */
+#define VMLBM_ESTATE (-4)     /* call out of order */
+#define VMLBM_EUNSTABLE (-5)  /* non-finite population, force or torque seen */
+#define VMLBM_ERANGE (-6)     /* geometry outside the supported range */
+
+typedef struct vmlbm_ctx vmlbm_ctx;
+
+typedef enum { VMLBM_F64 = 0, VMLBM_F32 = 1, VMLBM_F16 = 2 } vmlbm_storage;
+
+typedef struct {
+  int n[3];                   /* uniform grid: cells in x, y, z.
+                                 refined grid: COARSEST-level cells */
+  int block;                  /* 0 = one uniform grid; else cells per block edge
+                                 (16) of the block-structured grid (Sec. 4.1) */
+  int levels;                 /* refinement levels, 1..4 (block > 0) */
+  int periodic[3];            /* 1 periodic, 0 halfway no-slip walls at both ends */
+  double wall_velocity[2][3]; /* velocity of the low/high wall of the first
+                                 non-periodic axis (other walls rest) */
+  double omega;               /* s_nu = s+ of TRT on the finest level (Sec. 2.1);
+                                 coarser levels follow acoustic scaling */
+  double magic;               /* Lambda of Sec. 2.1 (3/16) */
+  double body_force[3];       /* fluid force density, finest-level units */
+  double gravity[3];          /* acts on particles only (Sec. 2.2) */
+  int storage;                /* vmlbm_storage of the populations */
+  int check_every;            /* refinement check period in coarse steps */
+  int history;                /* per-step F/T/x/u ring buffer length (>= 1) */
+  int adjoint_steps;          /* > 0: reserve workspace for vmlbm_forward_ckpt
+                                 with this many steps */
+  int ckpt_every;             /* checkpoint period of the adjoint forward pass */
+} vmlbm_config;
+
+typedef struct {
+  double x[3], u[3], w[3];    /* centre, velocity, angular velocity */
+  double radius;              /* r_p in cells */
+  double density_ratio;       /* pi_p = rho_p / rho_f */
+  double cv, cv_omega;        /* virtual mass coefficients C_v, C_v,omega (Sec. 3.3) */
+  int fixed;                  /* 1: held in place, surface velocity 0 */
+} vmlbm_sphere;
+
+/* Create a context from a configuration (copied).  *out receives it. */
+int vmlbm_create(const vmlbm_config* cfg, vmlbm_ctx** out);
+
+/* Register a sphere (Sec. 2.2) before the workspace is bound.  *id receives
+ * its index.  Spheres must lie at least 3 cells apart. */
+int vmlbm_add_sphere(vmlbm_ctx* ctx, const vmlbm_sphere* s, int* id);
+
+/* Device workspace size in bytes for the current configuration and spheres. */
+int vmlbm_required_bytes(const vmlbm_ctx* ctx, size_t* bytes);
+
+/* Bind caller-owned device memory of at least vmlbm_required_bytes (256-byte
+ * aligned).  It must outlive the context; the library never frees it. */
+int vmlbm_bind_workspace(vmlbm_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* HIP stream (hipStream_t) for all device work; NULL = default stream. */
+int vmlbm_set_stream(vmlbm_ctx* ctx, void* hip_stream);
+
+/* Map the spheres (Sec. 2.3) and set f(0) = f^eq(rho, u0) on fluid cells
+ * (Sec. 2.1 moments).  u0 is a host array [3][nz][ny][nx] of the finest
+ * (uniform) grid, or NULL for rest. */
+int vmlbm_init_equilibrium(vmlbm_ctx* ctx, double rho, const double* u0);
+
+/* Advance n steps (coarse steps on a refined grid) following Algorithm 1.
+ * Asynchronous on the bound stream. */
+int vmlbm_step(vmlbm_ctx* ctx, int n);
+
+/* Wait for the stream; returns VMLBM_EUNSTABLE if a non-finite density,
+ * force or torque was flagged, VMLBM_ERANGE if a particle left its range. */
+int vmlbm_sync(vmlbm_ctx* ctx);
+
+/* Particle state after the last step. */
+int vmlbm_get_particle(vmlbm_ctx* ctx, int id, double x[3], double u[3], double w[3]);
+
+/* Raw hydrodynamic force and torque F^n, T^n (Eq. 12) of the last (finest)
+ * step, before the two-step average of Algorithm 1. */
+int vmlbm_get_force_torque(vmlbm_ctx* ctx, int id, double F[3], double T[3]);
+
+/* Last n history records of sphere id, oldest first: out[n][12] =
+ * F^n, T^n, x, u after each step.  n <= history and <= steps done. */
+int vmlbm_get_history(vmlbm_ctx* ctx, int id, int n, double* out);
+
+/* Post-collision populations f~(n) of a level (uniform grid: level 0),
+ * FP64, host array [19][cells] in the canonical D3Q19 order
+ * (rest; +x,-x,+y,-y,+z,-z; xy, xz, yz diagonals).  Uniform grid: cells in
+ * [nz][ny][nx] order.  Refined grid: [block][16][16][16] in the order of
+ * vmlbm_level_blocks.  Solid cells read 0. */
+int vmlbm_read_populations(vmlbm_ctx* ctx, int level, double* out);
+
+/* Overwrite the post-collision populations of a level (same layout), rounded
+ * to the storage precision.  For tests and fault injection. */
+int vmlbm_write_populations(vmlbm_ctx* ctx, int level, const double* in);
+
+/* Particle owner per cell of a level: -1 fluid, else sphere id. */
+int vmlbm_read_owner(vmlbm_ctx* ctx, int level, int* out);
+
+/* Density and velocity (with the forcing shift) per cell of a level;
+ * rho [cells], u [3][cells]; solid cells read 0. */
+int vmlbm_read_fields(vmlbm_ctx* ctx, int level, double* rho, double* u);
+
+/* Cell updates performed and device seconds measured so far by vmlbm_step. */
+int vmlbm_stats(vmlbm_ctx* ctx, double* cell_updates, double* seconds);
+
+/* Kernel timing: when enabled, HIP events on the bound stream bracket every
+ * stream-collide sweep launch; vmlbm_sweep_time returns the summed sweep
+ * duration and launch count (synchronises). */
+int vmlbm_profile(vmlbm_ctx* ctx, int enable);
+int vmlbm_sweep_time(vmlbm_ctx* ctx, double* seconds, long long* launches);
+
+/* Block list of a refined level: *count blocks; if origin != NULL it gets
+ * [count][3] block origins in that level's cell units. */
+int vmlbm_level_blocks(vmlbm_ctx* ctx, int level, int* count, int* origin);
+
+/* Number of re-refinements performed so far (Sec. 4.2). */
+int vmlbm_refinements(vmlbm_ctx* ctx, int* count);
+
+/* Set the differentiable parameters: body force magnitude along +z and
+ * omega (Lambda held fixed, so s- follows omega). */
+int vmlbm_set_params(vmlbm_ctx* ctx, double body_force_z, double omega);
+
+/* Forward pass for the time-averaged drag of a fixed sphere:
+ *   J = 1/(n_steps - avg_from) * sum_{n=avg_from}^{n_steps-1} F_z^n
+ * from f(0) = w, storing a checkpoint every ckpt_every steps.  Requires
+ * config.adjoint_steps >= n_steps and ckpt_every == config.ckpt_every. */
+int vmlbm_forward_ckpt(vmlbm_ctx* ctx, int sphere, int n_steps, int avg_from, int ckpt_every,
+                       double* J);
+
+/* Reverse pass of the last vmlbm_forward_ckpt: grad = dJ * (dJ/dF_z, dJ/domega)
+ * by the discrete adjoint with segment recomputation. */
+int vmlbm_adjoint(vmlbm_ctx* ctx, double dJ, double grad[2]);
+
+/* Destroy the context (the workspace stays the caller's). */
+int vmlbm_destroy(vmlbm_ctx* ctx);
+
+const char* vmlbm_last_error(const vmlbm_ctx* ctx);
+
+#pragma GCC visibility pop
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,284 @@
+"""Python binding of libvmlbm (gfx950 HIP library of the coupled LBM hot path).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies the device workspace (a uint8 tensor) and the stream.
+The library must have been built (``paper_2103_10882_amd.build.build()``);
+there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmlbm.so")
+
+F64, F32, F16 = 0, 1, 2
+STORAGE = {"f64": F64, "f32": F32, "f16": F16}
+BYTES = {F64: 8, F32: 4, F16: 2}
+
+ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSTABLE", -6: "ERANGE"}
+
+EXPORTS = [
+    "vmlbm_create", "vmlbm_add_sphere", "vmlbm_required_bytes", "vmlbm_bind_workspace",
+    "vmlbm_set_stream", "vmlbm_init_equilibrium", "vmlbm_step", "vmlbm_sync", "vmlbm_get_particle",
+    "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
+    "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
+    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_level_blocks", "vmlbm_refinements",
+    "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
+]
+
+
+class VmlbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("block", ctypes.c_int), ("levels", ctypes.c_int),
+                ("periodic", ctypes.c_int * 3), ("wall_velocity", (ctypes.c_double * 3) * 2),
+                ("omega", ctypes.c_double), ("magic", ctypes.c_double),
+                ("body_force", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
+                ("storage", ctypes.c_int), ("check_every", ctypes.c_int), ("history", ctypes.c_int),
+                ("adjoint_steps", ctypes.c_int), ("ckpt_every", ctypes.c_int)]
+
+
+class Sphere(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double * 3), ("u", ctypes.c_double * 3), ("w", ctypes.c_double * 3),
+                ("radius", ctypes.c_double), ("density_ratio", ctypes.c_double),
+                ("cv", ctypes.c_double), ("cv_omega", ctypes.c_double), ("fixed", ctypes.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libvmlbm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2103_10882_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        sig = {
+            "vmlbm_create": [ctypes.POINTER(Config), ctypes.POINTER(vp)],
+            "vmlbm_add_sphere": [vp, ctypes.POINTER(Sphere), ctypes.POINTER(ctypes.c_int)],
+            "vmlbm_required_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
+            "vmlbm_bind_workspace": [vp, vp, ctypes.c_size_t],
+            "vmlbm_set_stream": [vp, vp],
+            "vmlbm_init_equilibrium": [vp, ctypes.c_double, vp],
+            "vmlbm_step": [vp, ctypes.c_int],
+            "vmlbm_sync": [vp],
+            "vmlbm_get_particle": [vp, ctypes.c_int, vp, vp, vp],
+            "vmlbm_get_force_torque": [vp, ctypes.c_int, vp, vp],
+            "vmlbm_get_history": [vp, ctypes.c_int, ctypes.c_int, vp],
+            "vmlbm_read_populations": [vp, ctypes.c_int, vp],
+            "vmlbm_write_populations": [vp, ctypes.c_int, vp],
+            "vmlbm_read_owner": [vp, ctypes.c_int, vp],
+            "vmlbm_read_fields": [vp, ctypes.c_int, vp, vp],
+            "vmlbm_stats": [vp, vp, vp],
+            "vmlbm_profile": [vp, ctypes.c_int],
+            "vmlbm_sweep_time": [vp, vp, vp],
+            "vmlbm_level_blocks": [vp, ctypes.c_int, vp, vp],
+            "vmlbm_refinements": [vp, vp],
+            "vmlbm_set_params": [vp, ctypes.c_double, ctypes.c_double],
+            "vmlbm_forward_ckpt": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
+            "vmlbm_adjoint": [vp, ctypes.c_double, vp],
+            "vmlbm_destroy": [vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        L.vmlbm_last_error.argtypes = [vp]
+        L.vmlbm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def make_config(cfg, storage="f64", history=4, adjoint_steps=0, ckpt_every=0, check_every=4):
+    c = Config()
+    for a in range(3):
+        c.n[a] = int(cfg["n"][a])
+        c.periodic[a] = int(cfg["periodic"][a])
+        c.body_force[a] = float(cfg["body_force"][a])
+        c.gravity[a] = float(cfg["gravity"][a])
+        for s in range(2):
+            c.wall_velocity[s][a] = float(cfg["wall_velocity"][s][a])
+    c.block = int(cfg.get("block", 0))
+    c.levels = int(cfg.get("levels", 1))
+    c.omega = float(cfg["omega"])
+    c.magic = float(cfg["magic"])
+    c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    c.check_every = int(cfg.get("check_every", check_every))
+    c.history = int(history)
+    c.adjoint_steps = int(adjoint_steps)
+    c.ckpt_every = int(ckpt_every)
+    return c
+
+
+def make_sphere(s):
+    o = Sphere()
+    for a in range(3):
+        o.x[a] = s["x"][a]
+        o.u[a] = s["u"][a]
+        o.w[a] = s["w"][a]
+    o.radius = s["radius"]
+    o.density_ratio = s["density_ratio"]
+    o.cv = s["cv"]
+    o.cv_omega = s["cv_omega"]
+    o.fixed = int(s["fixed"])
+    return o
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+class Sim:
+    """One simulation context on the current CUDA (HIP) device."""
+
+    def __init__(self, cfg, spheres=(), storage="f64", history=4, adjoint_steps=0, ckpt_every=0,
+                 device="cuda"):
+        import torch
+        self.L = lib()
+        self.cfg = cfg
+        self._c = make_config(cfg, storage, history, adjoint_steps, ckpt_every)
+        self.h = ctypes.c_void_p()
+        self._check(self.L.vmlbm_create(ctypes.byref(self._c), ctypes.byref(self.h)), "create")
+        for s in spheres:
+            o = make_sphere(s)
+            i = ctypes.c_int()
+            self._check(self.L.vmlbm_add_sphere(self.h, ctypes.byref(o), ctypes.byref(i)), "add_sphere")
+        self.nsph = len(spheres)
+        nb = ctypes.c_size_t()
+        self._check(self.L.vmlbm_required_bytes(self.h, ctypes.byref(nb)), "required_bytes")
+        self.ws_bytes = nb.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) & ~255
+        self._check(self.L.vmlbm_bind_workspace(self.h, ctypes.c_void_p(aligned), self.ws_bytes), "bind")
+        self.stream = torch.cuda.current_stream(self.ws.device)
+        self._check(self.L.vmlbm_set_stream(self.h, ctypes.c_void_p(self.stream.cuda_stream)), "set_stream")
+        self.block = int(cfg.get("block", 0))
+        self.n = tuple(int(v) for v in cfg["n"])
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.L.vmlbm_last_error(self.h) if self.h else b""
+            raise VmlbmError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value:
+            self.L.vmlbm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # --- stepping -----------------------------------------------------------
+    def init(self, rho=1.0, u0=None):
+        if u0 is not None:
+            u0 = np.ascontiguousarray(u0, dtype=np.float64)
+            self._check(self.L.vmlbm_init_equilibrium(self.h, float(rho), _ptr(u0)), "init")
+        else:
+            self._check(self.L.vmlbm_init_equilibrium(self.h, float(rho), None), "init")
+
+    def step(self, n=1):
+        self._check(self.L.vmlbm_step(self.h, int(n)), "step")
+
+    def sync(self):
+        self._check(self.L.vmlbm_sync(self.h), "sync")
+
+    # --- read-back ----------------------------------------------------------
+    def cells(self, level=0):
+        if self.block:
+            return self.level_blocks(level).shape[0] * self.block ** 3
+        return self.n[0] * self.n[1] * self.n[2]
+
+    def _shape(self, level):
+        if self.block:
+            return (19, self.cells(level))
+        nx, ny, nz = self.n
+        return (19, nz, ny, nx)
+
+    def populations(self, level=0):
+        out = np.zeros(self._shape(level))
+        self._check(self.L.vmlbm_read_populations(self.h, level, _ptr(out)), "read_populations")
+        return out
+
+    def write_populations(self, f, level=0):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        self._check(self.L.vmlbm_write_populations(self.h, level, _ptr(f)), "write_populations")
+
+    def owner(self, level=0):
+        shp = self._shape(level)[1:]
+        out = np.zeros(shp, dtype=np.int32)
+        self._check(self.L.vmlbm_read_owner(self.h, level, _ptr(out)), "read_owner")
+        return out
+
+    def fields(self, level=0):
+        shp = self._shape(level)[1:]
+        rho = np.zeros(shp)
+        u = np.zeros((3,) + shp)
+        self._check(self.L.vmlbm_read_fields(self.h, level, _ptr(rho), _ptr(u)), "read_fields")
+        return rho, u
+
+    def force_torque(self, i=0):
+        F, T = np.zeros(3), np.zeros(3)
+        self._check(self.L.vmlbm_get_force_torque(self.h, i, _ptr(F), _ptr(T)), "force_torque")
+        return F, T
+
+    def particle(self, i=0):
+        x, u, w = np.zeros(3), np.zeros(3), np.zeros(3)
+        self._check(self.L.vmlbm_get_particle(self.h, i, _ptr(x), _ptr(u), _ptr(w)), "particle")
+        return x, u, w
+
+    def history(self, i, n):
+        out = np.zeros((n, 12))
+        self._check(self.L.vmlbm_get_history(self.h, i, n, _ptr(out)), "history")
+        return out
+
+    def stats(self):
+        cu, sec = ctypes.c_double(), ctypes.c_double()
+        self._check(self.L.vmlbm_stats(self.h, ctypes.byref(cu), ctypes.byref(sec)), "stats")
+        return cu.value, sec.value
+
+    def profile(self, enable=True):
+        self._check(self.L.vmlbm_profile(self.h, int(enable)), "profile")
+
+    def sweep_time(self):
+        s, n = ctypes.c_double(), ctypes.c_longlong()
+        self._check(self.L.vmlbm_sweep_time(self.h, ctypes.byref(s), ctypes.byref(n)), "sweep_time")
+        return s.value, n.value
+
+    def level_blocks(self, level):
+        cnt = ctypes.c_int()
+        self._check(self.L.vmlbm_level_blocks(self.h, level, ctypes.byref(cnt), None), "level_blocks")
+        org = np.zeros((cnt.value, 3), dtype=np.int32)
+        self._check(self.L.vmlbm_level_blocks(self.h, level, ctypes.byref(cnt), _ptr(org)), "level_blocks")
+        return org
+
+    def refinements(self):
+        c = ctypes.c_int()
+        self._check(self.L.vmlbm_refinements(self.h, ctypes.byref(c)), "refinements")
+        return c.value
+
+    # --- differentiation ------------------------------------------------------
+    def set_params(self, body_force_z, omega):
+        self._check(self.L.vmlbm_set_params(self.h, float(body_force_z), float(omega)), "set_params")
+
+    def forward_ckpt(self, sphere, n_steps, avg_from, ckpt_every):
+        J = np.zeros(1)
+        self._check(self.L.vmlbm_forward_ckpt(self.h, sphere, n_steps, avg_from, ckpt_every, _ptr(J)),
+                    "forward_ckpt")
+        return float(J[0])
+
+    def adjoint(self, dJ=1.0):
+        g = np.zeros(2)
+        self._check(self.L.vmlbm_adjoint(self.h, float(dJ), _ptr(g)), "adjoint")
+        return g

@@ -1,0 +1,534 @@
+// C-ABI of the vmlbm library: context, workspace carving, stepping in the
+// order of Algorithm 1, and synchronous read-back for tests.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "vmlbm.h"
+#include "common.hpp"
+#include "uniform.hpp"
+#include "context.hpp"
+
+using namespace vm;
+
+namespace {
+
+int fail(vmlbm_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(ctx, VMLBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t storage_bytes(int storage) { return storage == VMLBM_F64 ? 8 : storage == VMLBM_F32 ? 4 : 2; }
+
+// uniform-grid workspace layout
+void plan_uniform(vmlbm_ctx* c) {
+  const vmlbm_config& g = c->cfg;
+  const size_t N = (size_t)g.n[0] * g.n[1] * g.n[2];
+  const size_t S = storage_bytes(g.storage);
+  const int np = (int)c->spheres.size();
+  int box = 0;
+  for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
+  c->box = box;
+  c->slot_wx = (box + 62) / 64 + 1;
+  c->nwx = (g.n[0] + 63) / 64;
+  c->slot_stride = (size_t)box * box * c->slot_wx * 6;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+  c->off_status = take(kStatusWords * sizeof(int));
+  c->off_pdf[0] = take(19 * N * S);
+  c->off_pdf[1] = take(19 * N * S);
+  c->off_flags = take(N);
+  c->off_owner = take(2 * N);
+  c->off_parts = take(std::max(np, 1) * sizeof(DevParticle));
+  c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
+  c->off_hist = take((size_t)std::max(g.history, 1) * std::max(np, 1) * 12 * sizeof(double));
+  adjoint_plan(c, take);
+  c->ws_needed = off;
+}
+
+SweepParams sweep_params(const vmlbm_ctx* c) {
+  const vmlbm_config& g = c->cfg;
+  SweepParams p{};
+  p.nx = g.n[0]; p.ny = g.n[1]; p.nz = g.n[2];
+  for (int a = 0; a < 3; ++a) p.per[a] = g.periodic[a];
+  p.wall_axis = c->wall_axis;
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < 3; ++a) p.wall_v[s][a] = g.wall_velocity[s][a];
+  p.sp = c->sp;
+  p.sm = c->sm;
+  for (int a = 0; a < 3; ++a) p.F[a] = c->F[a];
+  p.N = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
+  p.box = c->box;
+  p.slot_wx = c->slot_wx;
+  p.nwx = c->nwx;
+  p.slot_stride = c->slot_stride;
+  return p;
+}
+
+template <typename F>
+int dispatch(int storage, F&& f) {
+  if (storage == VMLBM_F64) return f((double*)nullptr);
+  if (storage == VMLBM_F32) return f((float*)nullptr);
+  return f((__half*)nullptr);
+}
+
+double dev_to_double(const void* buf, int storage, size_t i) {
+  if (storage == VMLBM_F64) return ((const double*)buf)[i];
+  if (storage == VMLBM_F32) return (double)((const float*)buf)[i];
+  return (double)__half2float(((const __half*)buf)[i]);
+}
+
+void double_to_dev(void* buf, int storage, size_t i, double v) {
+  if (storage == VMLBM_F64) ((double*)buf)[i] = v;
+  else if (storage == VMLBM_F32) ((float*)buf)[i] = (float)v;
+  else ((__half*)buf)[i] = __float2half_rn((float)v);
+}
+
+int check_ready(vmlbm_ctx* c) {
+  if (!c) return VMLBM_EINVAL;
+  if (!c->ws) return fail(c, VMLBM_ESTATE, "workspace not bound");
+  if (!c->initialized) return fail(c, VMLBM_ESTATE, "vmlbm_init_equilibrium not called");
+  return VMLBM_OK;
+}
+
+int read_status(vmlbm_ctx* c) {
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int st[kStatusWords];
+  HIP_TRY(c, hipMemcpy(st, c->ws + c->off_status, sizeof(st), hipMemcpyDeviceToHost));
+  if (st[kStatusUnstable]) return fail(c, VMLBM_EUNSTABLE, "non-finite state flagged (code %d)", st[kStatusUnstable]);
+  if (st[kStatusRange]) return fail(c, VMLBM_ERANGE, "particle geometry out of range (code %d)", st[kStatusRange]);
+  return VMLBM_OK;
+}
+
+void fold_timing(vmlbm_ctx* c) {
+  for (auto& ev : c->sweep_events) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev.first, ev.second) == hipSuccess) c->sweep_seconds += ms * 1e-3;
+    c->sweep_launches += 1;
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  c->sweep_events.clear();
+  if (c->step_pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_start, c->ev_end) == hipSuccess) c->seconds += ms * 1e-3;
+    c->step_pending = false;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// uniform-grid stepping (Algorithm 1): sweep (LBM step + link forces) ->
+// reduction, averaging, virtual-mass update -> refill -> re-mapping
+// ---------------------------------------------------------------------------
+namespace vm {
+
+int uniform_step(vmlbm_ctx* c, int nsteps) {
+  const SweepParams p = sweep_params(c);
+  const int np = (int)c->spheres.size();
+  const bool flags = c->use_flags;
+  for (int s = 0; s < nsteps; ++s) {
+    void* src = c->ws + c->off_pdf[c->cur];
+    void* dst = c->ws + c->off_pdf[1 - c->cur];
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->profile) {
+      HIP_TRY(c, hipEventCreate(&e0));
+      HIP_TRY(c, hipEventCreate(&e1));
+      HIP_TRY(c, hipEventRecord(e0, c->stream));
+    }
+    int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+      using S = std::remove_pointer_t<decltype(tag)>;
+      HIP_TRY(c, launch_sweep<S>(src, dst, c->flags(), c->owner(), c->parts(), c->slots(), c->status(), p,
+                                 flags, c->stream));
+      return VMLBM_OK;
+    });
+    if (rc) return rc;
+    if (c->profile) {
+      HIP_TRY(c, hipEventRecord(e1, c->stream));
+      c->sweep_events.emplace_back(e0, e1);
+    }
+    if (np > 0) {
+      UpdateParams u{};
+      for (int a = 0; a < 3; ++a) u.g[a] = c->cfg.gravity[a];
+      u.step = (int)(c->steps_done % std::max(c->cfg.history, 1));
+      u.hist_len = std::max(c->cfg.history, 1);
+      u.np = np;
+      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, u, c->stream));
+      if (c->moving) {
+        rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+          using S = std::remove_pointer_t<decltype(tag)>;
+          HIP_TRY(c, launch_refill_remap<S>(dst, c->flags(), c->owner(), c->parts(), np, p, c->stream));
+          return VMLBM_OK;
+        });
+        if (rc) return rc;
+      }
+    }
+    c->cur = 1 - c->cur;
+    c->steps_done += 1;
+    c->cell_updates += (double)p.N;
+  }
+  return VMLBM_OK;
+}
+
+}  // namespace vm
+
+// ---------------------------------------------------------------------------
+// C API
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int vmlbm_create(const vmlbm_config* cfg, vmlbm_ctx** out) {
+  if (!cfg || !out) return VMLBM_EINVAL;
+  *out = nullptr;
+  for (int a = 0; a < 3; ++a)
+    if (cfg->n[a] <= 0) return VMLBM_EINVAL;
+  if (cfg->storage < VMLBM_F64 || cfg->storage > VMLBM_F16) return VMLBM_EINVAL;
+  if (!(cfg->omega > 0.0 && cfg->omega < 2.0) || !(cfg->magic > 0.0)) return VMLBM_EINVAL;
+  if (cfg->block < 0) return VMLBM_EINVAL;
+  if (cfg->block == 0) {
+    const double N = (double)cfg->n[0] * cfg->n[1] * cfg->n[2];
+    if (N >= 2147483648.0) return VMLBM_ERANGE;
+  }
+  auto* c = new (std::nothrow) vmlbm_ctx();
+  if (!c) return VMLBM_ENOMEM;
+  c->cfg = *cfg;
+  if (c->cfg.history < 1) c->cfg.history = 1;
+  c->wall_axis = -1;
+  for (int a = 0; a < 3; ++a)
+    if (!cfg->periodic[a]) { c->wall_axis = a; break; }
+  c->sp = cfg->omega;
+  c->sm = s_minus_of(c->sp, cfg->magic);
+  for (int a = 0; a < 3; ++a) c->F[a] = cfg->body_force[a];
+  if (cfg->block > 0) {
+    int rc = refine_create(c);
+    if (rc) { delete c; return rc; }
+  }
+  *out = c;
+  return VMLBM_OK;
+}
+
+int vmlbm_add_sphere(vmlbm_ctx* c, const vmlbm_sphere* s, int* id) {
+  if (!c || !s) return VMLBM_EINVAL;
+  if (c->ws) return fail(c, VMLBM_ESTATE, "spheres must be added before the workspace is bound");
+  if (!(s->radius > 0.0) || !(s->density_ratio > 0.0) || s->cv < 0.0 || s->cv_omega < 0.0)
+    return fail(c, VMLBM_EINVAL, "bad sphere parameters");
+  if (c->spheres.size() >= 65535) return fail(c, VMLBM_ERANGE, "too many spheres");
+  const int box = (int)std::ceil(2.0 * s->radius) + 8;
+  const int* n = c->cfg.n;
+  const int scale = c->cfg.block > 0 ? (1 << (c->cfg.levels - 1)) : 1;
+  for (int a = 0; a < 3; ++a)
+    if (box > n[a] * scale) return fail(c, VMLBM_ERANGE, "sphere larger than the domain");
+  for (const auto& o : c->spheres) {
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      double d = s->x[a] - o.x[a];
+      const double L = (double)n[a] * scale;
+      if (c->cfg.periodic[a]) d -= L * std::round(d / L);
+      d2 += d * d;
+    }
+    if (std::sqrt(d2) < s->radius + o.radius + 3.0)
+      return fail(c, VMLBM_ERANGE, "spheres closer than 3 cells");
+  }
+  c->spheres.push_back(*s);
+  if (!s->fixed) c->moving = true;
+  if (id) *id = (int)c->spheres.size() - 1;
+  return VMLBM_OK;
+}
+
+int vmlbm_required_bytes(const vmlbm_ctx* cc, size_t* bytes) {
+  auto* c = const_cast<vmlbm_ctx*>(cc);
+  if (!c || !bytes) return VMLBM_EINVAL;
+  if (c->cfg.block > 0) {
+    int rc = refine_plan(c);
+    if (rc) return rc;
+  } else {
+    plan_uniform(c);
+  }
+  *bytes = c->ws_needed;
+  return VMLBM_OK;
+}
+
+int vmlbm_bind_workspace(vmlbm_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c || !dev_ptr) return VMLBM_EINVAL;
+  if (((uintptr_t)dev_ptr) & 255) return fail(c, VMLBM_EINVAL, "workspace must be 256-byte aligned");
+  size_t need = 0;
+  int rc = vmlbm_required_bytes(c, &need);
+  if (rc) return rc;
+  if (bytes < need) return fail(c, VMLBM_ENOMEM, "workspace %zu < required %zu bytes", bytes, need);
+  c->ws = (char*)dev_ptr;
+  c->ws_bytes = bytes;
+  c->use_flags = !c->spheres.empty() || c->wall_axis >= 0;
+  return VMLBM_OK;
+}
+
+int vmlbm_set_stream(vmlbm_ctx* c, void* stream) {
+  if (!c) return VMLBM_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return VMLBM_OK;
+}
+
+int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
+  if (!c) return VMLBM_EINVAL;
+  if (!c->ws) return fail(c, VMLBM_ESTATE, "workspace not bound");
+  if (c->cfg.block > 0) return refine_init(c, rho, u0);
+  const SweepParams p0 = sweep_params(c);
+  const int np = (int)c->spheres.size();
+  HIP_TRY(c, hipMemsetAsync(c->status(), 0, kStatusWords * sizeof(int), c->stream));
+  // particle records
+  std::vector<DevParticle> hp(np);
+  for (int i = 0; i < np; ++i) {
+    const vmlbm_sphere& s = c->spheres[i];
+    DevParticle& P = hp[i];
+    memset(&P, 0, sizeof(P));
+    for (int a = 0; a < 3; ++a) {
+      P.x[a] = s.x[a];
+      P.u[a] = s.fixed ? 0.0 : s.u[a];
+      P.w[a] = s.fixed ? 0.0 : s.w[a];
+    }
+    P.r = s.radius; P.rho = s.density_ratio; P.cv = s.cv; P.cvw = s.cv_omega;
+    P.fixed = s.fixed; P.have_prev = 0;
+    for (int a = 0; a < 3; ++a) {
+      int lo = (int)std::floor(s.x[a] - s.radius) - 3;
+      if (c->cfg.periodic[a]) lo = ((lo % c->cfg.n[a]) + c->cfg.n[a]) % c->cfg.n[a];
+      P.box_lo[a] = lo;
+      P.remap_lo[a] = lo;
+    }
+  }
+  if (np) HIP_TRY(c, hipMemcpyAsync(c->parts(), hp.data(), np * sizeof(DevParticle), hipMemcpyHostToDevice, c->stream));
+  if (np) HIP_TRY(c, hipMemsetAsync(c->slots(), 0, np * c->slot_stride * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * 12 * sizeof(double), c->stream));
+  if (c->use_flags) HIP_TRY(c, launch_map_all(c->flags(), c->owner(), c->parts(), np, p0, c->stream));
+  double* u0d = nullptr;
+  if (u0) {
+    u0d = (double*)(c->ws + c->off_pdf[1]);   // staging in the second population buffer
+    HIP_TRY(c, hipMemcpyAsync(u0d, u0, 3 * (size_t)p0.N * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
+  int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    HIP_TRY(c, launch_init<S>(c->ws + c->off_pdf[0], c->use_flags ? c->flags() : nullptr, u0d, rho - 1.0, p0,
+                              c->stream));
+    return VMLBM_OK;
+  });
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->cur = 0;
+  c->steps_done = 0;
+  c->initialized = true;
+  return VMLBM_OK;
+}
+
+int vmlbm_step(vmlbm_ctx* c, int n) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (n < 0) return fail(c, VMLBM_EINVAL, "negative step count");
+  if (n == 0) return VMLBM_OK;
+  if (!c->step_pending) {
+    if (!c->ev_start) { HIP_TRY(c, hipEventCreate(&c->ev_start)); HIP_TRY(c, hipEventCreate(&c->ev_end)); }
+    HIP_TRY(c, hipEventRecord(c->ev_start, c->stream));
+  }
+  rc = c->cfg.block > 0 ? refine_step(c, n) : uniform_step(c, n);
+  if (rc) return rc;
+  HIP_TRY(c, hipEventRecord(c->ev_end, c->stream));
+  c->step_pending = true;
+  return VMLBM_OK;
+}
+
+int vmlbm_sync(vmlbm_ctx* c) {
+  if (!c) return VMLBM_EINVAL;
+  if (!c->ws) return fail(c, VMLBM_ESTATE, "workspace not bound");
+  int rc = read_status(c);
+  fold_timing(c);
+  return rc;
+}
+
+int vmlbm_get_particle(vmlbm_ctx* c, int id, double x[3], double u[3], double w[3]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (id < 0 || id >= (int)c->spheres.size()) return fail(c, VMLBM_EINVAL, "bad sphere id");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  DevParticle P;
+  HIP_TRY(c, hipMemcpy(&P, c->parts() + id, sizeof(P), hipMemcpyDeviceToHost));
+  for (int a = 0; a < 3; ++a) {
+    if (x) x[a] = P.x[a];
+    if (u) u[a] = P.u[a];
+    if (w) w[a] = P.w[a];
+  }
+  return VMLBM_OK;
+}
+
+int vmlbm_get_force_torque(vmlbm_ctx* c, int id, double F[3], double T[3]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (id < 0 || id >= (int)c->spheres.size()) return fail(c, VMLBM_EINVAL, "bad sphere id");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  DevParticle P;
+  HIP_TRY(c, hipMemcpy(&P, c->parts() + id, sizeof(P), hipMemcpyDeviceToHost));
+  for (int a = 0; a < 3; ++a) {
+    if (F) F[a] = P.F[a];
+    if (T) T[a] = P.T[a];
+  }
+  return VMLBM_OK;
+}
+
+int vmlbm_get_history(vmlbm_ctx* c, int id, int n, double* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  const int np = (int)c->spheres.size();
+  const int H = c->cfg.history;
+  if (id < 0 || id >= np || !out) return fail(c, VMLBM_EINVAL, "bad argument");
+  const long long done = c->particle_steps();
+  if (n < 0 || n > H || n > done) return fail(c, VMLBM_EINVAL, "history holds %d of %lld steps", H, done);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<double> h((size_t)H * np * 12);
+  HIP_TRY(c, hipMemcpy(h.data(), c->hist(), h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) {
+    const long long step = done - n + i;
+    const double* src = h.data() + ((size_t)(step % H) * np + id) * 12;
+    memcpy(out + 12 * i, src, 12 * sizeof(double));
+  }
+  return VMLBM_OK;
+}
+
+int vmlbm_read_populations(vmlbm_ctx* c, int level, double* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!out) return VMLBM_EINVAL;
+  if (c->cfg.block > 0) return refine_read_populations(c, level, out);
+  if (level != 0) return fail(c, VMLBM_EINVAL, "uniform grid has level 0 only");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t N = (size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
+  const size_t S = storage_bytes(c->cfg.storage);
+  std::vector<char> raw(19 * N * S);
+  HIP_TRY(c, hipMemcpy(raw.data(), c->ws + c->off_pdf[c->cur], raw.size(), hipMemcpyDeviceToHost));
+  std::vector<uint8_t> fl(N, 0);
+  if (c->use_flags) HIP_TRY(c, hipMemcpy(fl.data(), c->flags(), N, hipMemcpyDeviceToHost));
+  for (int q = 0; q < 19; ++q)
+    for (size_t i = 0; i < N; ++i)
+      out[q * N + i] = (fl[i] & kSolid) ? 0.0 : w_of(q) + dev_to_double(raw.data(), c->cfg.storage, q * N + i);
+  return VMLBM_OK;
+}
+
+int vmlbm_write_populations(vmlbm_ctx* c, int level, const double* in) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!in) return VMLBM_EINVAL;
+  if (c->cfg.block > 0) return refine_write_populations(c, level, in);
+  if (level != 0) return fail(c, VMLBM_EINVAL, "uniform grid has level 0 only");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t N = (size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
+  const size_t S = storage_bytes(c->cfg.storage);
+  std::vector<char> raw(19 * N * S);
+  for (int q = 0; q < 19; ++q)
+    for (size_t i = 0; i < N; ++i) double_to_dev(raw.data(), c->cfg.storage, q * N + i, in[q * N + i] - w_of(q));
+  HIP_TRY(c, hipMemcpy(c->ws + c->off_pdf[c->cur], raw.data(), raw.size(), hipMemcpyHostToDevice));
+  return VMLBM_OK;
+}
+
+int vmlbm_read_owner(vmlbm_ctx* c, int level, int* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!out) return VMLBM_EINVAL;
+  if (c->cfg.block > 0) return refine_read_owner(c, level, out);
+  if (level != 0) return fail(c, VMLBM_EINVAL, "uniform grid has level 0 only");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t N = (size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
+  std::vector<uint8_t> fl(N, 0);
+  std::vector<uint16_t> ow(N, 0);
+  if (c->use_flags) {
+    HIP_TRY(c, hipMemcpy(fl.data(), c->flags(), N, hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(ow.data(), c->owner(), 2 * N, hipMemcpyDeviceToHost));
+  }
+  for (size_t i = 0; i < N; ++i) out[i] = (fl[i] & kSolid) ? (int)ow[i] : -1;
+  return VMLBM_OK;
+}
+
+int vmlbm_read_fields(vmlbm_ctx* c, int level, double* rho, double* u) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  size_t N = 0;
+  if (c->cfg.block > 0) {
+    rc = refine_level_cells(c, level, &N);
+    if (rc) return rc;
+  } else {
+    if (level != 0) return fail(c, VMLBM_EINVAL, "uniform grid has level 0 only");
+    N = (size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
+  }
+  std::vector<double> f(19 * N);
+  rc = vmlbm_read_populations(c, level, f.data());
+  if (rc) return rc;
+  double Fl[3];
+  level_force(c, level, Fl);
+  for (size_t i = 0; i < N; ++i) {
+    double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 19; ++q) {
+      const double v = f[q * N + i];
+      r += v; j[0] += cx_of(q) * v; j[1] += cy_of(q) * v; j[2] += cz_of(q) * v;
+    }
+    const bool fluid = r != 0.0;
+    if (rho) rho[i] = r;
+    // post-collision momentum minus F/2 is the macroscopic velocity
+    if (u)
+      for (int a = 0; a < 3; ++a) u[a * N + i] = fluid ? j[a] - 0.5 * Fl[a] : 0.0;
+  }
+  return VMLBM_OK;
+}
+
+int vmlbm_stats(vmlbm_ctx* c, double* cell_updates, double* seconds) {
+  if (!c) return VMLBM_EINVAL;
+  if (c->ws) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    fold_timing(c);
+  }
+  if (cell_updates) *cell_updates = c->cell_updates;
+  if (seconds) *seconds = c->seconds;
+  return VMLBM_OK;
+}
+
+int vmlbm_profile(vmlbm_ctx* c, int enable) {
+  if (!c) return VMLBM_EINVAL;
+  c->profile = enable != 0;
+  return VMLBM_OK;
+}
+
+int vmlbm_sweep_time(vmlbm_ctx* c, double* seconds, long long* launches) {
+  if (!c) return VMLBM_EINVAL;
+  if (c->ws) {
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    fold_timing(c);
+  }
+  if (seconds) *seconds = c->sweep_seconds;
+  if (launches) *launches = c->sweep_launches;
+  return VMLBM_OK;
+}
+
+int vmlbm_destroy(vmlbm_ctx* c) {
+  if (!c) return VMLBM_EINVAL;
+  if (c->ws) (void)hipStreamSynchronize(c->stream);
+  fold_timing(c);
+  if (c->ev_start) (void)hipEventDestroy(c->ev_start);
+  if (c->ev_end) (void)hipEventDestroy(c->ev_end);
+  refine_destroy(c);
+  delete c;
+  return VMLBM_OK;
+}
+
+const char* vmlbm_last_error(const vmlbm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+}  // extern "C"

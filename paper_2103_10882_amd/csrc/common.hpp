@@ -1,0 +1,176 @@
+// Shared device definitions for the vmlbm kernels (gfx950, wave64).
+//
+// Populations are stored as deviations d = f - w_q from the lattice weights
+// (rho0 = 1), in FP64, FP32 or FP16; collision arithmetic runs in FP64 for
+// FP64 storage and in FP32 otherwise.  Forces, torques and particle state are
+// always FP64.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <cstdint>
+
+namespace vm {
+
+// D3Q19 in the library's canonical order (Sec. 2.1 names D3Q19 without
+// printing it): rest; +x,-x,+y,-y,+z,-z; (1,1,0),(1,-1,0),(-1,1,0),(-1,-1,0);
+// (1,0,1),(1,0,-1),(-1,0,1),(-1,0,-1); (0,1,1),(0,1,-1),(0,-1,1),(0,-1,-1).
+constexpr int kQ = 19;
+__device__ __host__ constexpr int cx_of(int q) {
+  return (q == 1 || q == 7 || q == 8 || q == 11 || q == 12) ? 1
+       : (q == 2 || q == 9 || q == 10 || q == 13 || q == 14) ? -1 : 0;
+}
+__device__ __host__ constexpr int cy_of(int q) {
+  return (q == 3 || q == 7 || q == 9 || q == 15 || q == 16) ? 1
+       : (q == 4 || q == 8 || q == 10 || q == 17 || q == 18) ? -1 : 0;
+}
+__device__ __host__ constexpr int cz_of(int q) {
+  return (q == 5 || q == 11 || q == 13 || q == 15 || q == 17) ? 1
+       : (q == 6 || q == 12 || q == 14 || q == 16 || q == 18) ? -1 : 0;
+}
+__device__ __host__ constexpr int opp_of(int q) {
+  return q == 0 ? 0 : (q <= 6 ? (q & 1 ? q + 1 : q - 1)
+       : (q == 7 ? 10 : q == 10 ? 7 : q == 8 ? 9 : q == 9 ? 8
+       : q == 11 ? 14 : q == 14 ? 11 : q == 12 ? 13 : q == 13 ? 12
+       : q == 15 ? 18 : q == 18 ? 15 : q == 16 ? 17 : 16));
+}
+__device__ __host__ constexpr double w_of(int q) {
+  return q == 0 ? 1.0 / 3.0 : (q <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// the nine (q, opp(q)) pairs with q the member of positive orientation
+constexpr int kPairs = 9;
+__device__ __host__ constexpr int pair_q(int k) {
+  return k == 0 ? 1 : k == 1 ? 3 : k == 2 ? 5 : k == 3 ? 7 : k == 4 ? 8 : k == 5 ? 11 : k == 6 ? 12 : k == 7 ? 15 : 16;
+}
+
+// cell flags (uint8 per cell)
+constexpr uint8_t kSolid = 0x80;   // covered by a particle (owner array holds which)
+constexpr uint8_t kNear = 0x40;    // fluid cell with at least one wall or particle link
+
+// status words in device memory
+constexpr int kStatusUnstable = 0;  // non-finite density / force / torque
+constexpr int kStatusRange = 1;     // particle left its box / two particles on one cell
+constexpr int kStatusWords = 16;
+
+// ---------------------------------------------------------------------------
+// storage precision: load/store of deviations
+// ---------------------------------------------------------------------------
+template <typename S> struct Store;
+template <> struct Store<double> {
+  using T = double;
+  static __device__ __forceinline__ double load(double v) { return v; }
+  static __device__ __forceinline__ double store(double v) { return v; }
+};
+template <> struct Store<float> {
+  using T = float;
+  static __device__ __forceinline__ float load(float v) { return v; }
+  static __device__ __forceinline__ float store(float v) { return v; }
+};
+template <> struct Store<__half> {
+  using T = float;
+  static __device__ __forceinline__ float load(__half v) { return __half2float(v); }
+  static __device__ __forceinline__ __half store(float v) { return __float2half_rn(v); }
+};
+
+// ---------------------------------------------------------------------------
+// particle record (FP64), one per sphere, in device memory
+// ---------------------------------------------------------------------------
+struct DevParticle {
+  double x[3], u[3], w[3];
+  double a[3], b[3];           // translational / angular acceleration of the previous step
+  double F[3], T[3];           // raw hydrodynamic F^n, T^n of the last step
+  double Fprev[3], Tprev[3];   // of the step before
+  double r, rho, cv, cvw;
+  int fixed, have_prev;
+  int box_lo[3];               // force-slot box origin for the coming sweep
+  int remap_lo[3];             // re-mapping region origin (old and new position)
+};
+
+// ---------------------------------------------------------------------------
+// TRT collision (Sec. 2.1 with Lambda_b = 1) on deviations, incompressible
+// equilibrium (rho0 = 1), forcing after Guo with the velocity shifted by F/2.
+// d[] holds pre-collision deviations on entry and post-collision on exit.
+// Returns the density deviation.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T trt_collide(T (&d)[kQ], T sp, T sm, T Fx, T Fy, T Fz) {
+  T drho = d[0];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) drho += d[q];
+  const T jx = (d[1] - d[2]) + (d[7] - d[10]) + (d[8] - d[9]) + (d[11] - d[14]) + (d[12] - d[13]);
+  const T jy = (d[3] - d[4]) + (d[7] - d[10]) + (d[9] - d[8]) + (d[15] - d[18]) + (d[16] - d[17]);
+  const T jz = (d[5] - d[6]) + (d[11] - d[14]) + (d[13] - d[12]) + (d[15] - d[18]) + (d[17] - d[16]);
+  const T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
+  const T usq = ux * ux + uy * uy + uz * uz;
+  const T uF = ux * Fx + uy * Fy + uz * Fz;
+  const T kp = T(1) - T(0.5) * sp, km = T(1) - T(0.5) * sm;
+  // rest population: purely even
+  {
+    const T w = T(w_of(0));
+    const T eq = w * (drho - T(1.5) * usq);
+    d[0] = d[0] - sp * (d[0] - eq) + kp * (w * (T(-3) * uF));
+  }
+#pragma unroll
+  for (int k = 0; k < kPairs; ++k) {
+    const int q = pair_q(k), qb = opp_of(q);
+    const T w = T(w_of(q));
+    const T cu = T(cx_of(q)) * ux + T(cy_of(q)) * uy + T(cz_of(q)) * uz;
+    const T cF = T(cx_of(q)) * Fx + T(cy_of(q)) * Fy + T(cz_of(q)) * Fz;
+    const T ep = w * (drho + T(4.5) * cu * cu - T(1.5) * usq);
+    const T em = T(3) * w * cu;
+    const T Sp = w * (T(9) * cu * cF - T(3) * uF);
+    const T Sm = T(3) * w * cF;
+    const T fp = T(0.5) * (d[q] + d[qb]);
+    const T fm = T(0.5) * (d[q] - d[qb]);
+    const T np = fp - sp * (fp - ep) + kp * Sp;
+    const T nm = fm - sm * (fm - em) + km * Sm;
+    d[q] = np + nm;
+    d[qb] = np - nm;
+  }
+  return drho;
+}
+
+// s- from s+ and the magic parameter Lambda = (1/s+ - 1/2)(1/s- - 1/2)
+__host__ __device__ inline double s_minus_of(double sp, double magic) {
+  return 1.0 / (0.5 + magic / (1.0 / sp - 0.5));
+}
+
+// ---------------------------------------------------------------------------
+// sphere geometry, FP64 without contraction so that the solid/fluid decision
+// is reproducible: a cell is solid iff |x_c - x_p|^2 <= r^2 (minimum image).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double min_image(double d, int n, int periodic) {
+  if (periodic) {
+    if (d > 0.5 * n) d = __dadd_rn(d, -(double)n);
+    else if (d < -0.5 * n) d = __dadd_rn(d, (double)n);
+  }
+  return d;
+}
+
+__device__ __forceinline__ void sphere_offset(const double* xp, double px, double py, double pz,
+                                              int nx, int ny, int nz, const int* per, double* d) {
+  d[0] = min_image(__dadd_rn(px, -xp[0]), nx, per[0]);
+  d[1] = min_image(__dadd_rn(py, -xp[1]), ny, per[1]);
+  d[2] = min_image(__dadd_rn(pz, -xp[2]), nz, per[2]);
+}
+
+__device__ __forceinline__ bool inside_sphere(const double* d, double r) {
+  double dd = __dmul_rn(d[0], d[0]);
+  dd = __dadd_rn(dd, __dmul_rn(d[1], d[1]));
+  dd = __dadd_rn(dd, __dmul_rn(d[2], d[2]));
+  return dd <= __dmul_rn(r, r);
+}
+
+// boundary distance ratio along integer direction c from offset d (Sec. 2.3):
+// smallest root of |d + delta c|^2 = r^2
+__device__ __forceinline__ double ray_delta(const double* d, int cx, int cy, int cz, double r) {
+  const double cc = cx * cx + cy * cy + cz * cz;
+  const double dc = d[0] * cx + d[1] * cy + d[2] * cz;
+  const double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  double disc = dc * dc - cc * (dd - r * r);
+  disc = disc > 0.0 ? disc : 0.0;
+  double delta = (-dc - sqrt(disc)) / cc;
+  return delta < 0.0 ? 0.0 : (delta > 1.0 ? 1.0 : delta);
+}
+
+}  // namespace vm

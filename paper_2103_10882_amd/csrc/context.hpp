@@ -1,0 +1,84 @@
+// Host-side context of the vmlbm library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <functional>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "vmlbm.h"
+#include "common.hpp"
+
+namespace vm {
+struct Forest;     // block-structured grid state (refine.hip)
+struct AdjState;   // adjoint bookkeeping (adjoint.hip)
+}
+
+struct vmlbm_ctx {
+  vmlbm_config cfg{};
+  std::vector<vmlbm_sphere> spheres;
+  bool moving = false;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_needed = 0;
+  bool initialized = false;
+  bool use_flags = false;
+  int wall_axis = -1;
+  double sp = 0.0, sm = 0.0, F[3] = {0.0, 0.0, 0.0};
+  std::string err;
+
+  // uniform-grid workspace carving
+  size_t off_status = 0, off_pdf[2] = {0, 0}, off_flags = 0, off_owner = 0, off_parts = 0, off_slots = 0,
+         off_hist = 0;
+  int cur = 0;
+  int box = 0, slot_wx = 0, nwx = 0;
+  size_t slot_stride = 0;
+
+  // progress and timing
+  long long steps_done = 0;          // steps of the uniform grid / coarse steps
+  long long fine_steps_done = 0;     // finest-level steps (refined grid)
+  double cell_updates = 0.0;
+  double seconds = 0.0;
+  hipEvent_t ev_start = nullptr, ev_end = nullptr;
+  bool step_pending = false;
+  bool profile = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_events;
+  double sweep_seconds = 0.0;
+  long long sweep_launches = 0;
+
+  std::unique_ptr<vm::Forest, void (*)(vm::Forest*)> forest{nullptr, nullptr};
+  std::unique_ptr<vm::AdjState, void (*)(vm::AdjState*)> adj{nullptr, nullptr};
+
+  int* status() { return (int*)(ws + off_status); }
+  uint8_t* flags() { return (uint8_t*)(ws + off_flags); }
+  uint16_t* owner() { return (uint16_t*)(ws + off_owner); }
+  vm::DevParticle* parts() { return (vm::DevParticle*)(ws + off_parts); }
+  double* slots() { return (double*)(ws + off_slots); }
+  double* hist() { return (double*)(ws + off_hist); }
+  long long particle_steps() const { return cfg.block > 0 ? fine_steps_done : steps_done; }
+};
+
+namespace vm {
+using Take = std::function<size_t(size_t)>;
+
+int uniform_step(vmlbm_ctx* c, int nsteps);
+
+// adjoint (adjoint.hip)
+void adjoint_plan(vmlbm_ctx* c, const Take& take);
+
+// block-structured refined grid (refine.hip)
+int refine_create(vmlbm_ctx* c);
+int refine_plan(vmlbm_ctx* c);
+int refine_init(vmlbm_ctx* c, double rho, const double* u0);
+int refine_step(vmlbm_ctx* c, int n);
+int refine_read_populations(vmlbm_ctx* c, int level, double* out);
+int refine_write_populations(vmlbm_ctx* c, int level, const double* in);
+int refine_read_owner(vmlbm_ctx* c, int level, int* out);
+int refine_level_cells(vmlbm_ctx* c, int level, size_t* cells);
+void refine_destroy(vmlbm_ctx* c);
+// body force of a level in that level's lattice units
+void level_force(const vmlbm_ctx* c, int level, double F[3]);
+}  // namespace vm

@@ -1,0 +1,584 @@
+// Uniform-grid kernels: fused pull stream-collide sweep with the moving-wall
+// CLI boundary and momentum-exchange link forces on particle links, the
+// per-particle force/torque reduction fused with the virtual-mass particle
+// update, refill of uncovered cells, and re-mapping.
+//
+// Layout: populations SoA [q][z][y][x] as deviations in storage type S, two
+// buffers (pull from src, write dst); flags uint8 [z][y][x]; owner uint16
+// [z][y][x] (read only for solid cells).  One thread per cell, one wave per
+// 64 consecutive x cells of a row, so every population load and store of a
+// wave is a contiguous run shifted by at most one element.
+#include <utility>
+
+#include "common.hpp"
+#include "uniform.hpp"
+
+namespace vm {
+
+namespace {
+
+struct Idx {
+  int xm, xp;            // x-1, x+1 wrapped
+  uint32_t rm, r0, rp;   // row offsets of y-1, y, y+1 (wrapped) within a plane
+  uint32_t pm, p0, pp;   // plane offsets of z-1, z, z+1 (wrapped)
+};
+
+__device__ __forceinline__ Idx make_idx(int x, int y, int z, int nx, int ny, int nz) {
+  Idx I;
+  I.xm = x == 0 ? nx - 1 : x - 1;
+  I.xp = x + 1 == nx ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y + 1 == ny ? 0 : y + 1;
+  const int zm = z == 0 ? nz - 1 : z - 1, zp = z + 1 == nz ? 0 : z + 1;
+  I.rm = (uint32_t)ym * nx; I.r0 = (uint32_t)y * nx; I.rp = (uint32_t)yp * nx;
+  const uint32_t plane = (uint32_t)nx * ny;
+  I.pm = (uint32_t)zm * plane; I.p0 = (uint32_t)z * plane; I.pp = (uint32_t)zp * plane;
+  return I;
+}
+
+// index of the pull source x - c_q (periodic wrap; walls handled elsewhere)
+template <int Q>
+__device__ __forceinline__ uint32_t pull_index(const Idx& I, int x) {
+  constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
+  const uint32_t xs = cx == 1 ? I.xm : (cx == -1 ? I.xp : x);
+  const uint32_t ys = cy == 1 ? I.rm : (cy == -1 ? I.rp : I.r0);
+  const uint32_t zs = cz == 1 ? I.pm : (cz == -1 ? I.pp : I.p0);
+  return zs + ys + xs;
+}
+
+template <typename S, int Q>
+__device__ __forceinline__ void load_pull(const S* __restrict__ src, uint32_t N, const Idx& I, int x,
+                                          typename Store<S>::T (&d)[kQ]) {
+  d[Q] = Store<S>::load(src[(size_t)Q * N + pull_index<Q>(I, x)]);
+}
+
+template <typename S, int... Qs>
+__device__ __forceinline__ void load_all(const S* __restrict__ src, uint32_t N, const Idx& I, int x,
+                                         typename Store<S>::T (&d)[kQ], std::integer_sequence<int, Qs...>) {
+  (load_pull<S, Qs>(src, N, I, x, d), ...);
+}
+
+// Slow path for a fluid cell with wall or particle links: builds the 19
+// incoming populations with Eq. 10 (CLI) on particle links and halfway
+// bounce-back on walls, and accumulates the link forces of Eq. 11 and their
+// torques (Eq. 12) in FP64.  The constant part 2 w_q c_q of each link force
+// is left out: summed over the closed surface of a body it vanishes exactly
+// (every lattice line enters and leaves the body equally often), and so does
+// its torque (entry and exit points of a line differ by a multiple of c_q).
+template <typename S>
+__device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restrict__ flags,
+                              const uint16_t* __restrict__ owner, const DevParticle* __restrict__ parts,
+                              const SweepParams& p, int x, int y, int z, uint32_t c,
+                              typename Store<S>::T (&d)[kQ], int& pid, double (&Fl)[3], double (&Tl)[3],
+                              int* __restrict__ status) {
+  using T = typename Store<S>::T;
+  const uint32_t N = p.N;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  d[0] = Store<S>::load(src[c]);
+  for (int q = 1; q < kQ; ++q) {
+    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+    const int qq = opp_of(q);
+    const double w = w_of(q);
+    // pull source x - c_q
+    int s[3] = {x - cq[0], y - cq[1], z - cq[2]};
+    int wall_axis = -1, wall_side = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (s[a] < 0 || s[a] >= n[a]) {
+        if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+        else if (wall_axis < 0) { wall_axis = a; wall_side = s[a] < 0 ? 0 : 1; }
+      }
+    }
+    const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
+    if (wall_axis >= 0) {
+      // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
+      double cv = 0.0;
+      if (wall_axis == p.wall_axis)
+        cv = -(cq[0] * p.wall_v[wall_side][0] + cq[1] * p.wall_v[wall_side][1] + cq[2] * p.wall_v[wall_side][2]);
+      d[q] = own_qq - T(6.0 * w * cv);
+      continue;
+    }
+    const uint32_t sidx = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
+    if (!(flags[sidx] & kSolid)) {
+      d[q] = Store<S>::load(src[(size_t)q * N + sidx]);
+      continue;
+    }
+    // particle link in direction qq (c_qq = -c_q points into the solid)
+    const int pi = owner[sidx];
+    const DevParticle& P = parts[pi];
+    double off[3];
+    sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
+    const double delta = ray_delta(off, -cq[0], -cq[1], -cq[2], P.r);
+    double rb[3] = {off[0] - delta * cq[0], off[1] - delta * cq[1], off[2] - delta * cq[2]};
+    double v[3] = {P.u[0] + (P.w[1] * rb[2] - P.w[2] * rb[1]),
+                   P.u[1] + (P.w[2] * rb[0] - P.w[0] * rb[2]),
+                   P.u[2] + (P.w[0] * rb[1] - P.w[1] * rb[0])};
+    double kappa = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
+    double alpha = 4.0 / (1.0 + 2.0 * delta);
+    // second node x - c_qq = x + c_q
+    int t[3] = {x + cq[0], y + cq[1], z + cq[2]};
+    bool second_ok = true;
+    for (int a = 0; a < 3; ++a) {
+      if (t[a] < 0 || t[a] >= n[a]) {
+        if (p.per[a]) t[a] = t[a] < 0 ? t[a] + n[a] : t[a] - n[a];
+        else second_ok = false;
+      }
+    }
+    uint32_t tidx = 0;
+    if (second_ok) {
+      tidx = ((uint32_t)t[2] * n[1] + t[1]) * n[0] + t[0];
+      if (flags[tidx] & kSolid) second_ok = false;
+    }
+    if (!second_ok) { kappa = 0.0; alpha = 2.0; }
+    // c_qq . v with c_qq = -c_q
+    const double cqv = -(cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2]);
+    T val = own_qq - T(3.0 * alpha * w * cqv);
+    if (second_ok) {
+      const T sec = Store<S>::load(src[(size_t)qq * N + tidx]);
+      const T own_q = Store<S>::load(src[(size_t)q * N + c]);
+      val = val + T(kappa) * (sec - own_q);
+    }
+    d[q] = val;
+    // link force: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
+    const double a0 = (double)own_qq, a1 = (double)val;
+    double Fq[3];
+    for (int a = 0; a < 3; ++a) Fq[a] = (-cq[a] - v[a]) * a0 + (-cq[a] + v[a]) * a1;
+    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
+    pid = pi;
+    Fl[0] += Fq[0]; Fl[1] += Fq[1]; Fl[2] += Fq[2];
+    Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
+    Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
+    Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
+  }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// per-wave partial sums of the link forces into the sphere's slot box
+__device__ void wave_force_partials(int pid, const double (&Fl)[3], const double (&Tl)[3],
+                                    const DevParticle* __restrict__ parts, double* __restrict__ slots,
+                                    const SweepParams& p, int x, int y, int z, int* __restrict__ status) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(pid >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int tp = __shfl(pid, leader, 64);
+    const bool mine = pid == tp;
+    double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(mine ? v[k] : 0.0);
+    if (lane == leader) {
+      const DevParticle& P = parts[tp];
+      const int wx = x >> 6;
+      int ox = wx - (P.box_lo[0] >> 6);
+      if (p.per[0]) ox = (ox % p.nwx + p.nwx) % p.nwx;
+      int oy = y - P.box_lo[1];
+      if (p.per[1]) oy = (oy % p.ny + p.ny) % p.ny;
+      int oz = z - P.box_lo[2];
+      if (p.per[2]) oz = (oz % p.nz + p.nz) % p.nz;
+      if (ox < 0 || ox >= p.slot_wx || oy < 0 || oy >= p.box || oz < 0 || oz >= p.box) {
+        status[kStatusRange] = 1;
+      } else {
+        double* s = slots + (size_t)tp * p.slot_stride + (size_t)(((oz * p.box) + oy) * p.slot_wx + ox) * 6;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) s[k] += v[k];
+      }
+    }
+    pending &= ~__ballot(mine);
+  }
+}
+
+template <typename S, bool FLAGS>
+__global__ __launch_bounds__(256) void k_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                               const uint8_t* __restrict__ flags,
+                                               const uint16_t* __restrict__ owner,
+                                               const DevParticle* __restrict__ parts,
+                                               double* __restrict__ slots, int* __restrict__ status,
+                                               SweepParams p) {
+  using T = typename Store<S>::T;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y, z = blockIdx.z;
+  const bool active = x < p.nx;
+  const uint32_t N = p.N;
+  const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
+  uint8_t fl = 0;
+  if (FLAGS && active) fl = flags[c];
+  int pid = -1;
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  if (active && !(fl & kSolid)) {
+    T d[kQ];
+    if (!FLAGS || !(fl & kNear)) {
+      const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz);
+      load_all<S>(src, N, I, x, d, std::make_integer_sequence<int, kQ>{});
+    } else {
+      boundary_cell<S>(src, flags, owner, parts, p, x, y, z, c, d, pid, Fl, Tl, status);
+    }
+    const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+    if (!(drho == drho)) status[kStatusUnstable] = 1;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store(d[q]);
+  }
+  if (FLAGS) wave_force_partials(pid, Fl, Tl, parts, slots, p, x, y, z, status);
+}
+
+// ---------------------------------------------------------------------------
+// f~(0) = collide(f^eq(rho, u0)) on fluid cells (Sec. 2.1)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_init(S* __restrict__ dst, const uint8_t* __restrict__ flags,
+                                              const double* __restrict__ u0, double drho, SweepParams p) {
+  using T = typename Store<S>::T;
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= p.N) return;
+  if (flags && (flags[c] & kSolid)) return;
+  double u[3] = {0.0, 0.0, 0.0};
+  if (u0) { u[0] = u0[c]; u[1] = u0[p.N + c]; u[2] = u0[2 * (size_t)p.N + c]; }
+  const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  T d[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    const double cu = cx_of(q) * u[0] + cy_of(q) * u[1] + cz_of(q) * u[2];
+    d[q] = T(w_of(q) * (drho + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+  }
+  trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
+}
+
+// ---------------------------------------------------------------------------
+// mapping (Sec. 2.3): flags and owner of the cells of a region, from the
+// particle positions; region = whole grid (init) or a sphere's re-mapping box
+// ---------------------------------------------------------------------------
+__device__ int cell_owner(int x, int y, int z, const DevParticle* __restrict__ parts, int np,
+                          const SweepParams& p) {
+  for (int i = 0; i < np; ++i) {
+    double off[3];
+    sphere_offset(parts[i].x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
+    if (inside_sphere(off, parts[i].r)) return i;
+  }
+  return -1;
+}
+
+__device__ void map_cell(int x, int y, int z, uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
+                         const DevParticle* __restrict__ parts, int np, const SweepParams& p) {
+  const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
+  const int o = cell_owner(x, y, z, parts, np, p);
+  uint8_t f = 0;
+  if (o >= 0) {
+    f = kSolid;
+    owner[c] = (uint16_t)o;
+  } else {
+    const int n[3] = {p.nx, p.ny, p.nz};
+    for (int q = 1; q < kQ && !f; ++q) {
+      int s[3] = {x + cx_of(q), y + cy_of(q), z + cz_of(q)};
+      bool wall = false;
+      for (int a = 0; a < 3; ++a)
+        if (s[a] < 0 || s[a] >= n[a]) {
+          if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+          else wall = true;
+        }
+      if (wall || cell_owner(s[0], s[1], s[2], parts, np, p) >= 0) f = kNear;
+    }
+  }
+  flags[c] = f;
+}
+
+__global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
+                                                 const DevParticle* __restrict__ parts, int np, SweepParams p) {
+  const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= p.N) return;
+  const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / ((uint32_t)p.nx * p.ny);
+  map_cell(x, y, z, flags, owner, parts, np, p);
+}
+
+// region cell k of the re-mapping box of particle pi -> grid cell, or false
+__device__ __forceinline__ bool region_cell(const DevParticle& P, int k, int rb, const SweepParams& p,
+                                            int& x, int& y, int& z) {
+  const int i = k % rb, j = (k / rb) % rb, l = k / (rb * rb);
+  int s[3] = {P.remap_lo[0] + i, P.remap_lo[1] + j, P.remap_lo[2] + l};
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (p.per[a]) s[a] = ((s[a] % n[a]) + n[a]) % n[a];
+    else if (s[a] < 0 || s[a] >= n[a]) return false;
+  }
+  x = s[0]; y = s[1]; z = s[2];
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
+                                               const DevParticle* __restrict__ parts, int np, SweepParams p) {
+  const int pi = blockIdx.y;
+  const DevParticle& P = parts[pi];
+  if (P.fixed) return;
+  const int rb = p.box + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= rb * rb * rb) return;
+  int x, y, z;
+  if (!region_cell(P, k, rb, p, x, y, z)) return;
+  map_cell(x, y, z, flags, owner, parts, np, p);
+}
+
+// ---------------------------------------------------------------------------
+// refill of cells uncovered by a moving sphere (Sec. 2.3, after Dorschner):
+// rho = mean density of the D3Q19 neighbours that held fluid before the
+// re-mapping; v = rigid-body velocity; strain rate S from central differences
+// over the axis neighbours (fluid velocity where the neighbour held fluid,
+// rigid-body velocity of its sphere or the wall velocity otherwise);
+// f = f^eq(rho, v) - 3 w_q / s+ (c c - I/3) : S, then collided.  Runs before
+// the flags are updated, so flags/owner still describe the old mapping.
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uint8_t* __restrict__ flags,
+                                                const uint16_t* __restrict__ owner,
+                                                const DevParticle* __restrict__ parts, int np, SweepParams p) {
+  using T = typename Store<S>::T;
+  const int pi = blockIdx.y;
+  const DevParticle& P = parts[pi];
+  if (P.fixed) return;
+  const int rb = p.box + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= rb * rb * rb) return;
+  int x, y, z;
+  if (!region_cell(P, k, rb, p, x, y, z)) return;
+  const uint32_t N = p.N;
+  const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
+  if (!(flags[c] & kSolid) || owner[c] != pi) return;
+  if (cell_owner(x, y, z, parts, np, p) >= 0) return;   // still covered
+  const int n[3] = {p.nx, p.ny, p.nz};
+  // density from old-fluid neighbours
+  double rsum = 0.0;
+  int cnt = 0;
+  for (int q = 1; q < kQ; ++q) {
+    int s[3] = {x + cx_of(q), y + cy_of(q), z + cz_of(q)};
+    bool out = false;
+    for (int a = 0; a < 3; ++a)
+      if (s[a] < 0 || s[a] >= n[a]) {
+        if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+        else out = true;
+      }
+    if (out) continue;
+    const uint32_t sc = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
+    if (flags[sc] & kSolid) continue;
+    double r = 0.0;
+    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + sc]);
+    rsum += 1.0 + r;
+    ++cnt;
+  }
+  const double rho = cnt ? rsum / cnt : 1.0;
+  double off[3];
+  sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
+  const double v[3] = {P.u[0] + (P.w[1] * off[2] - P.w[2] * off[1]),
+                       P.u[1] + (P.w[2] * off[0] - P.w[0] * off[2]),
+                       P.u[2] + (P.w[0] * off[1] - P.w[1] * off[0])};
+  // velocity at the six axis neighbours
+  double Vn[3][2][3];
+  for (int a = 0; a < 3; ++a)
+    for (int side = 0; side < 2; ++side) {
+      int s[3] = {x, y, z};
+      s[a] += side ? 1 : -1;
+      double* V = Vn[a][side];
+      if (s[a] < 0 || s[a] >= n[a]) {
+        if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+        else {
+          for (int b = 0; b < 3; ++b) V[b] = (a == p.wall_axis) ? p.wall_v[side][b] : 0.0;
+          continue;
+        }
+      }
+      const uint32_t sc = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
+      if (!(flags[sc] & kSolid)) {
+        double j[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < kQ; ++q) {
+          const double dq = (double)Store<S>::load(state[(size_t)q * N + sc]);
+          j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
+        }
+        // post-collision momentum minus F/2 is the macroscopic velocity
+        for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
+      } else {
+        const DevParticle& Q = parts[owner[sc]];
+        double o2[3];
+        sphere_offset(Q.x, x + 0.5 + (a == 0 ? (side ? 1 : -1) : 0), y + 0.5 + (a == 1 ? (side ? 1 : -1) : 0),
+                      z + 0.5 + (a == 2 ? (side ? 1 : -1) : 0), n[0], n[1], n[2], p.per, o2);
+        V[0] = Q.u[0] + (Q.w[1] * o2[2] - Q.w[2] * o2[1]);
+        V[1] = Q.u[1] + (Q.w[2] * o2[0] - Q.w[0] * o2[2]);
+        V[2] = Q.u[2] + (Q.w[0] * o2[1] - Q.w[1] * o2[0]);
+      }
+    }
+  double Sab[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      Sab[a][b] = 0.25 * ((Vn[a][1][b] - Vn[a][0][b]) + (Vn[b][1][a] - Vn[b][0][a]));
+  const double trS = Sab[0][0] + Sab[1][1] + Sab[2][2];
+  const double usq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  T d[kQ];
+  for (int q = 0; q < kQ; ++q) {
+    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+    const double cu = cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2];
+    double QS = -trS / 3.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) QS += cq[a] * cq[b] * Sab[a][b];
+    const double w = w_of(q);
+    d[q] = T(w * (rho - 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) - 3.0 * w / p.sp * QS);
+  }
+  trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store(d[q]);
+}
+
+// ---------------------------------------------------------------------------
+// per-particle force/torque reduction (fixed order, FP64) fused with the
+// two-step average and the virtual-mass velocity-Verlet update (Sec. 2.2,
+// Sec. 3.3, Algorithm 1).  One workgroup per particle.
+// ---------------------------------------------------------------------------
+__device__ void particle_update(DevParticle& P, const double (&F)[3], const double (&T)[3], int* __restrict__ status,
+                                const SweepParams& p, const UpdateParams& u) {
+#pragma clang fp contract(off)
+  bool finite = true;
+  for (int a = 0; a < 3; ++a) finite = finite && isfinite(F[a]) && isfinite(T[a]);
+  if (!finite) status[kStatusUnstable] = 2;
+  for (int a = 0; a < 3; ++a) { P.F[a] = F[a]; P.T[a] = T[a]; }
+  double xold[3] = {P.x[0], P.x[1], P.x[2]};
+  if (!P.fixed) {
+    const double PI = 3.14159265358979323846;
+    const double V = 4.0 / 3.0 * PI * P.r * P.r * P.r;
+    const double m = (P.rho + P.cv) * V;
+    const double I = 0.4 * (P.rho + P.cvw) * V * P.r * P.r;
+    for (int a = 0; a < 3; ++a) {
+      const double Fav = P.have_prev ? 0.5 * (F[a] + P.Fprev[a]) : F[a];
+      const double Tav = P.have_prev ? 0.5 * (T[a] + P.Tprev[a]) : T[a];
+      const double Fg = (P.rho - 1.0) * u.g[a] * V;
+      const double an = (Fav + Fg + P.cv * V * P.a[a]) / m;
+      const double bn = (Tav + 0.4 * P.cvw * V * P.r * P.r * P.b[a]) / I;
+      P.u[a] = P.u[a] + 0.5 * (P.a[a] + an);
+      P.w[a] = P.w[a] + 0.5 * (P.b[a] + bn);
+      double xn = P.x[a] + P.u[a] + 0.5 * an;
+      if (p.per[a]) {
+        const double na = a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
+        if (xn < 0.0) xn += na;
+        else if (xn >= na) xn -= na;
+      }
+      P.x[a] = xn;
+      P.a[a] = an;
+      P.b[a] = bn;
+    }
+    double speed = P.u[0] * P.u[0] + P.u[1] * P.u[1] + P.u[2] * P.u[2];
+    if (!(speed < 0.25)) status[kStatusUnstable] = 3;
+    // new boxes: force slots around the new position, re-mapping region
+    // covering old and new position
+    for (int a = 0; a < 3; ++a) {
+      const int na = a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
+      int lo_new = (int)floor(P.x[a] - P.r) - 3;
+      int lo_old = (int)floor(xold[a] - P.r) - 3;
+      double dx = P.x[a] - xold[a];
+      if (p.per[a]) {
+        if (dx > 0.5 * na) dx -= na;
+        else if (dx < -0.5 * na) dx += na;
+      }
+      if (!(fabs(dx) < 0.5)) status[kStatusRange] = 3;
+      int lo = dx >= 0.0 ? lo_old : lo_new;
+      if (p.per[a]) { lo = ((lo % na) + na) % na; lo_new = ((lo_new % na) + na) % na; }
+      P.remap_lo[a] = lo;
+      P.box_lo[a] = lo_new;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__ parts, double* __restrict__ slots,
+                                                       double* __restrict__ hist, int* __restrict__ status,
+                                                       SweepParams p, UpdateParams u) {
+  const int pi = blockIdx.x;
+  __shared__ double red[6][256];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  double* s = slots + (size_t)pi * p.slot_stride;
+  const int nslots = p.box * p.box * p.slot_wx;
+  for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) { acc[j] += s[(size_t)k * 6 + j]; s[(size_t)k * 6 + j] = 0.0; }
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
+  __syncthreads();
+  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  DevParticle& P = parts[pi];
+  double F[3] = {red[0][0], red[1][0], red[2][0]}, T[3] = {red[3][0], red[4][0], red[5][0]};
+  particle_update(P, F, T, status, p, u);
+  for (int a = 0; a < 3; ++a) { P.Fprev[a] = F[a]; P.Tprev[a] = T[a]; }
+  P.have_prev = 1;
+  double* h = hist + ((size_t)(u.step % u.hist_len) * u.np + pi) * 12;
+  for (int a = 0; a < 3; ++a) { h[a] = F[a]; h[3 + a] = T[a]; h[6 + a] = P.x[a]; h[9 + a] = P.u[a]; }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename S>
+hipError_t launch_sweep(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
+                        const DevParticle* parts, double* slots, int* status, const SweepParams& p,
+                        bool with_flags, hipStream_t st) {
+  const int bx = p.nx >= 256 ? 256 : 64;
+  dim3 grid((p.nx + bx - 1) / bx, p.ny, p.nz), block(bx);
+  if (with_flags)
+    k_sweep<S, true><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, owner, parts, slots, status, p);
+  else
+    k_sweep<S, false><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, owner, parts, slots, status, p);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double drho, const SweepParams& p,
+                       hipStream_t st) {
+  dim3 grid((p.N + 255) / 256), block(256);
+  k_init<S><<<grid, block, 0, st>>>((S*)dst, flags, u0, drho, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np, const SweepParams& p,
+                          hipStream_t st) {
+  dim3 grid((p.N + 255) / 256), block(256);
+  k_map_all<<<grid, block, 0, st>>>(flags, owner, parts, np, p);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
+                               const SweepParams& p, hipStream_t st) {
+  const int rb = p.box + 1;
+  dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
+  k_refill<S><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_remap<<<grid, block, 0, st>>>(flags, owner, parts, np, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
+                                const SweepParams& p, const UpdateParams& u, hipStream_t st) {
+  k_reduce_update<<<dim3(np), dim3(256), 0, st>>>(parts, slots, hist, status, p, u);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sweep<double>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
+                                         double*, int*, const SweepParams&, bool, hipStream_t);
+template hipError_t launch_sweep<float>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
+                                        double*, int*, const SweepParams&, bool, hipStream_t);
+template hipError_t launch_sweep<__half>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
+                                         double*, int*, const SweepParams&, bool, hipStream_t);
+template hipError_t launch_init<double>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
+template hipError_t launch_init<float>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
+template hipError_t launch_init<__half>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
+template hipError_t launch_refill_remap<double>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
+                                                const SweepParams&, hipStream_t);
+template hipError_t launch_refill_remap<float>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
+                                               const SweepParams&, hipStream_t);
+template hipError_t launch_refill_remap<__half>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
+                                                const SweepParams&, hipStream_t);
+
+}  // namespace vm

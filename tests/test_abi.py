@@ -1,0 +1,69 @@
+"""The C-ABI library loads and exports every entry point of include/vmlbm.h;
+host-only calls (no device work) behave as documented."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2103_10882_amd as p
+    if not os.path.exists(p.LIB_PATH):
+        from paper_2103_10882_amd import build
+        build.build()
+    return p
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "vmlbm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(vmlbm_\w+)\s*\(", txt, re.M)))
+
+
+def test_exports_every_declared_symbol(pkg):
+    syms = header_symbols()
+    assert len(syms) >= 25
+    L = ctypes.CDLL(pkg.LIB_PATH)
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(pkg.EXPORTS)
+
+
+def test_host_only_calls(pkg):
+    L = pkg.lib()
+    w = synth.tiny()
+    c = pkg.make_config(w["config"], "f32")
+    h = ctypes.c_void_p()
+    assert L.vmlbm_create(ctypes.byref(c), ctypes.byref(h)) == 0
+    s = pkg.make_sphere(w["spheres"][0])
+    i = ctypes.c_int()
+    assert L.vmlbm_add_sphere(h, ctypes.byref(s), ctypes.byref(i)) == 0 and i.value == 0
+    # a second sphere overlapping the first is rejected
+    assert L.vmlbm_add_sphere(h, ctypes.byref(s), ctypes.byref(i)) == -6
+    nb = ctypes.c_size_t()
+    assert L.vmlbm_required_bytes(h, ctypes.byref(nb)) == 0
+    N = 32 ** 3
+    assert nb.value >= 2 * 19 * N * 4 + 3 * N
+    # stepping before a workspace is bound is an ordering error
+    assert L.vmlbm_step(h, 1) == -4
+    assert b"workspace" in L.vmlbm_last_error(h)
+    assert L.vmlbm_destroy(h) == 0
+
+
+def test_bad_config_rejected(pkg):
+    L = pkg.lib()
+    w = synth.tiny()
+    c = pkg.make_config(w["config"], "f64")
+    c.omega = 2.5
+    h = ctypes.c_void_p()
+    assert L.vmlbm_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    c = pkg.make_config(w["config"], "f64")
+    c.storage = 7
+    assert L.vmlbm_create(ctypes.byref(c), ctypes.byref(h)) == -1
+    c = pkg.make_config(synth.base_config((2048, 2048, 1024)), "f16")
+    assert L.vmlbm_create(ctypes.byref(c), ctypes.byref(h)) == -6

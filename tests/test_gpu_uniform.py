@@ -1,0 +1,211 @@
+"""GPU parity of the uniform-grid hot path against the CPU oracle.
+
+FP64 storage must match the oracle to 1e-12 (relative, populations) and
+1e-10 (force; torque relative to max(|T|, r|F|)) since only summation order
+differs.  Reduced-precision storage is compared by drag error.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import oracle
+    import paper_2103_10882_amd as pkg
+    assert torch.cuda.is_available()
+    pkg.lib()
+    oracle.lib()
+    return pkg, oracle
+
+
+def pop_rel(fg, fo):
+    return np.abs(fg - fo).max() / np.abs(fo).max()
+
+
+def check_ft(sim, ref, nsph, radius, tol=1e-10, where=""):
+    for i in range(nsph):
+        Fg, Tg = sim.force_torque(i)
+        Fo, To = ref.force_torque(i)
+        fs = np.abs(Fo).max()
+        assert np.abs(Fg - Fo).max() <= tol * max(fs, 1e-30), (where, i, Fg, Fo)
+        ts = max(np.abs(To).max(), radius * fs)
+        assert np.abs(Tg - To).max() <= tol * ts, (where, i, Tg, To)
+
+
+def test_tiny_fixed_sphere_parity(env):
+    """32^3 periodic, fixed sphere r=6, body force, perturbed start: F/T every
+    step for 200 steps, populations at 100 and 200."""
+    pkg, oracle = env
+    w = synth.tiny()
+    say("case tiny32 f64")
+    sim = pkg.Sim(w["config"], w["spheres"], storage="f64")
+    sim.init(1.0, w["u0"])
+    ref = oracle.Uniform(w["config"], w["spheres"])
+    ref.init(1.0, w["u0"])
+    assert (sim.owner() == ref.owner()).all()
+    for n in range(1, 201):
+        sim.step(1)
+        ref.step(1)
+        check_ft(sim, ref, 1, 6.0, where=f"step {n}")
+        if n in (100, 200):
+            sim.sync()
+            rel = pop_rel(sim.populations(), ref.post_collision())
+            say(f"  step {n}: population rel err {rel:.2e}")
+            assert rel <= 1e-12
+
+
+def test_periodic_box_no_obstacles(env):
+    """Obstacle-free periodic box with forcing: the flag-free sweep."""
+    pkg, oracle = env
+    n = (70, 20, 28)
+    cfg = synth.base_config(n, omega=1.3, body_force=(1e-5, -2e-5, 3e-5))
+    u0 = synth.velocity_perturbation(n, seed=4)
+    say("case periodic70x20x28 f64")
+    sim = pkg.Sim(cfg, [], storage="f64")
+    sim.init(1.0, u0)
+    ref = oracle.Uniform(cfg)
+    ref.init(1.0, u0)
+    sim.step(30)
+    ref.step(30)
+    sim.sync()
+    rel = pop_rel(sim.populations(), ref.post_collision())
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-12
+    rho_g, u_g = sim.fields()
+    rho_o, u_o = ref.fields()
+    assert np.abs(rho_g - rho_o).max() < 1e-13
+    assert np.abs(u_g - u_o).max() < 1e-14
+
+
+@pytest.mark.parametrize("kind", ["poiseuille", "couette"])
+def test_walls(env, kind):
+    pkg, oracle = env
+    if kind == "poiseuille":
+        cfg = synth.base_config((3, 16, 2), periodic=(1, 0, 1), omega=1.6, body_force=(1e-6, 0, 0))
+    else:
+        cfg = synth.base_config((2, 2, 12), periodic=(1, 1, 0), omega=1.2,
+                                wall_velocity=((0, 0, 0), (0.01, -0.005, 0)))
+    say(f"case walls {kind} f64")
+    sim = pkg.Sim(cfg, [], storage="f64")
+    sim.init()
+    ref = oracle.Uniform(cfg)
+    ref.init()
+    sim.step(500)
+    ref.step(500)
+    sim.sync()
+    rel = pop_rel(sim.populations(), ref.post_collision())
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-12
+
+
+def test_moving_sphere_walls_parity(env):
+    """Reduced rising-sphere case: moving, rotating light sphere between
+    no-slip walls with virtual mass; re-mapping and refill every step.
+    Owner maps must agree every step; F/T per step; state at the end."""
+    pkg, oracle = env
+    n = (40, 36, 48)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.7, gravity=(1e-5, 0.0, -4e-4))
+    s = synth.sphere((20.3, 17.8, 16.2), 5.2, density_ratio=0.5, cv=0.5, fixed=False,
+                     u=(0.004, -0.003, 0.0), w=(0.0, 0.002, -0.001))
+    say("case moving40x36x48 f64")
+    sim = pkg.Sim(cfg, [s], storage="f64", history=16)
+    sim.init()
+    ref = oracle.Uniform(cfg, [s])
+    ref.init()
+    changed = 0
+    prev = ref.owner()
+    for k in range(1, 161):
+        sim.step(1)
+        ref.step(1)
+        og, oo = sim.owner(), ref.owner()
+        flips = int((og != oo).sum())
+        assert flips == 0, f"step {k}: {flips} mapping differences"
+        changed += int((oo != prev).sum())
+        prev = oo
+        check_ft(sim, ref, 1, 5.2, tol=1e-9, where=f"step {k}")
+    sim.sync()
+    xg, ug, wg = sim.particle(0)
+    xo, uo, wo = ref.particle(0)
+    say(f"  cells re-mapped {changed}; x {xg} vs {xo}")
+    assert changed > 100
+    assert np.abs(xg - xo).max() < 1e-11
+    assert np.abs(ug - uo).max() < 1e-12 * max(1.0, np.abs(uo).max() * 1e3)
+    assert np.abs(wg - wo).max() < 1e-12
+    rel = pop_rel(sim.populations(), ref.post_collision())
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-11
+    h = sim.history(0, 16)
+    assert np.abs(h[-1, 6:9] - xg).max() == 0.0
+
+
+def test_several_fixed_spheres(env):
+    """Reduced precision-sweep geometry: seeded fixed spheres, body force."""
+    pkg, oracle = env
+    n = 72
+    w = synth.precision(n=n, count=3, radius=8.0, seed=0)
+    say("case spheres72x3 f64")
+    sim = pkg.Sim(w["config"], w["spheres"], storage="f64")
+    sim.init()
+    ref = oracle.Uniform(w["config"], w["spheres"])
+    ref.init()
+    for k in range(1, 41):
+        sim.step(1)
+        ref.step(1)
+        check_ft(sim, ref, 3, 8.0, where=f"step {k}")
+    sim.sync()
+    rel = pop_rel(sim.populations(), ref.post_collision())
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-12
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-4), ("f16", 5e-2)])
+def test_reduced_storage_drag(env, storage, tol):
+    """FP32 / FP16 deviation storage with FP32 collision: drag against the
+    FP64 oracle, mean over the last 50 of 200 steps."""
+    pkg, oracle = env
+    w = synth.tiny()
+    say(f"case tiny32 {storage}")
+    sim = pkg.Sim(w["config"], w["spheres"], storage=storage, history=50)
+    sim.init()
+    ref = oracle.Uniform(w["config"], w["spheres"])
+    ref.init()
+    Fo = []
+    for k in range(200):
+        ref.step(1)
+        if k >= 150:
+            Fo.append(ref.force_torque(0)[0][2])
+    sim.step(200)
+    sim.sync()
+    Fg = sim.history(0, 50)[:, 2]
+    err = abs(Fg.mean() - np.mean(Fo)) / abs(np.mean(Fo))
+    say(f"  drag rel err {err:.2e}")
+    assert err < tol
+
+
+def test_nan_injection_flags_unstable(env):
+    pkg, _ = env
+    w = synth.tiny(n=24, radius=5.0)
+    say("case nan-injection")
+    sim = pkg.Sim(w["config"], w["spheres"], storage="f32")
+    sim.init()
+    sim.step(2)
+    sim.sync()
+    f = sim.populations()
+    f[3, 2, 2, 2] = np.nan
+    sim.write_populations(f)
+    sim.step(1)
+    with pytest.raises(pkg.VmlbmError) as e:
+        sim.sync()
+    assert e.value.code == -5
