@@ -142,10 +142,14 @@ int vmlbm_read_fields(vmlbm_ctx* ctx, int level, double* rho, double* u);
 int vmlbm_stats(vmlbm_ctx* ctx, double* cell_updates, double* seconds);
 
 /* Kernel timing: when enabled, HIP events on the bound stream bracket every
- * stream-collide sweep launch; vmlbm_sweep_time returns the summed sweep
- * duration and launch count (synchronises). */
+ * launch of the interior stream-collide sweep kernel; vmlbm_sweep_time
+ * returns their summed duration and launch count (synchronises). */
 int vmlbm_profile(vmlbm_ctx* ctx, int enable);
 int vmlbm_sweep_time(vmlbm_ctx* ctx, double* seconds, long long* launches);
+
+/* Cells of a level that are fluid, and fluid cells without any wall or
+ * particle link (those the interior sweep updates). */
+int vmlbm_cell_counts(vmlbm_ctx* ctx, int level, long long* fluid, long long* interior);
 
 /* Block list of a refined level: *count blocks; if origin != NULL it gets
  * [count][3] block origins in that level's cell units. */

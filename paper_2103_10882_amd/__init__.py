@@ -24,7 +24,7 @@ EXPORTS = [
     "vmlbm_set_stream", "vmlbm_init_equilibrium", "vmlbm_step", "vmlbm_sync", "vmlbm_get_particle",
     "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
-    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_level_blocks", "vmlbm_refinements",
+    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
 ]
 
@@ -80,6 +80,7 @@ def lib():
             "vmlbm_stats": [vp, vp, vp],
             "vmlbm_profile": [vp, ctypes.c_int],
             "vmlbm_sweep_time": [vp, vp, vp],
+            "vmlbm_cell_counts": [vp, ctypes.c_int, vp, vp],
             "vmlbm_level_blocks": [vp, ctypes.c_int, vp, vp],
             "vmlbm_refinements": [vp, vp],
             "vmlbm_set_params": [vp, ctypes.c_double, ctypes.c_double],
@@ -255,6 +256,11 @@ class Sim:
         s, n = ctypes.c_double(), ctypes.c_longlong()
         self._check(self.L.vmlbm_sweep_time(self.h, ctypes.byref(s), ctypes.byref(n)), "sweep_time")
         return s.value, n.value
+
+    def cell_counts(self, level=0):
+        f, i = ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(self.L.vmlbm_cell_counts(self.h, level, ctypes.byref(f), ctypes.byref(i)), "cell_counts")
+        return f.value, i.value
 
     def level_blocks(self, level):
         cnt = ctypes.c_int()

@@ -45,9 +45,8 @@ void plan_uniform(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  c->slot_wx = (box + 62) / 64 + 1;
-  c->nwx = (g.n[0] + 63) / 64;
-  c->slot_stride = (size_t)box * box * c->slot_wx * 6;
+  // one slot of 6 doubles per wave of the boundary pass over a sphere's box
+  c->slot_stride = (((size_t)box * box * box + 255) / 256) * 4 * 6;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   c->off_status = take(kStatusWords * sizeof(int));
@@ -75,8 +74,6 @@ SweepParams sweep_params(const vmlbm_ctx* c) {
   for (int a = 0; a < 3; ++a) p.F[a] = c->F[a];
   p.N = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
   p.box = c->box;
-  p.slot_wx = c->slot_wx;
-  p.nwx = c->nwx;
   p.slot_stride = c->slot_stride;
   return p;
 }
@@ -151,18 +148,25 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
     if (c->profile) {
       HIP_TRY(c, hipEventCreate(&e0));
       HIP_TRY(c, hipEventCreate(&e1));
-      HIP_TRY(c, hipEventRecord(e0, c->stream));
+      c->sweep_events.emplace_back(e0, e1);
+    }
+    // boundary cells on the side stream, concurrently with the interior sweep
+    if (flags) {
+      HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+      HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
     }
     int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
       using S = std::remove_pointer_t<decltype(tag)>;
-      HIP_TRY(c, launch_sweep<S>(src, dst, c->flags(), c->owner(), c->parts(), c->slots(), c->status(), p,
-                                 flags, c->stream));
+      if (flags)
+        HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->slots(), c->status(), p,
+                                      c->side));
+      HIP_TRY(c, launch_interior<S>(src, dst, c->flags(), c->status(), p, flags, c->stream, e0, e1));
       return VMLBM_OK;
     });
     if (rc) return rc;
-    if (c->profile) {
-      HIP_TRY(c, hipEventRecord(e1, c->stream));
-      c->sweep_events.emplace_back(e0, e1);
+    if (flags) {
+      HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
+      HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
     }
     if (np > 0) {
       UpdateParams u{};
@@ -174,7 +178,7 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
       if (c->moving) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;
-          HIP_TRY(c, launch_refill_remap<S>(dst, c->flags(), c->owner(), c->parts(), np, p, c->stream));
+          HIP_TRY(c, launch_refill_remap<S>(dst, c->flags(), c->owner(), c->parts(), np, p, c->status(), c->stream));
           return VMLBM_OK;
         });
         if (rc) return rc;
@@ -275,6 +279,11 @@ int vmlbm_bind_workspace(vmlbm_ctx* c, void* dev_ptr, size_t bytes) {
   c->ws = (char*)dev_ptr;
   c->ws_bytes = bytes;
   c->use_flags = !c->spheres.empty() || c->wall_axis >= 0;
+  if (!c->side) {
+    HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIP_TRY(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
   return VMLBM_OK;
 }
 
@@ -312,9 +321,8 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
     }
   }
   if (np) HIP_TRY(c, hipMemcpyAsync(c->parts(), hp.data(), np * sizeof(DevParticle), hipMemcpyHostToDevice, c->stream));
-  if (np) HIP_TRY(c, hipMemsetAsync(c->slots(), 0, np * c->slot_stride * sizeof(double), c->stream));
   HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * 12 * sizeof(double), c->stream));
-  if (c->use_flags) HIP_TRY(c, launch_map_all(c->flags(), c->owner(), c->parts(), np, p0, c->stream));
+  if (c->use_flags) HIP_TRY(c, launch_map_all(c->flags(), c->owner(), c->parts(), np, p0, c->status(), c->stream));
   double* u0d = nullptr;
   if (u0) {
     u0d = (double*)(c->ws + c->off_pdf[1]);   // staging in the second population buffer
@@ -518,12 +526,38 @@ int vmlbm_sweep_time(vmlbm_ctx* c, double* seconds, long long* launches) {
   return VMLBM_OK;
 }
 
+int vmlbm_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* interior) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (c->cfg.block > 0) return refine_cell_counts(c, level, fluid, interior);
+  if (level != 0) return fail(c, VMLBM_EINVAL, "uniform grid has level 0 only");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t N = (size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
+  long long nf = (long long)N, ni = (long long)N;
+  if (c->use_flags) {
+    std::vector<uint8_t> fl(N);
+    HIP_TRY(c, hipMemcpy(fl.data(), c->flags(), N, hipMemcpyDeviceToHost));
+    nf = ni = 0;
+    for (size_t i = 0; i < N; ++i) {
+      nf += !(fl[i] & kSolid);
+      ni += fl[i] == 0;
+    }
+  }
+  if (fluid) *fluid = nf;
+  if (interior) *interior = ni;
+  return VMLBM_OK;
+}
+
 int vmlbm_destroy(vmlbm_ctx* c) {
   if (!c) return VMLBM_EINVAL;
   if (c->ws) (void)hipStreamSynchronize(c->stream);
   fold_timing(c);
   if (c->ev_start) (void)hipEventDestroy(c->ev_start);
   if (c->ev_end) (void)hipEventDestroy(c->ev_end);
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->side) (void)hipStreamDestroy(c->side);
   refine_destroy(c);
   delete c;
   return VMLBM_OK;

@@ -45,11 +45,12 @@ __device__ __host__ constexpr int pair_q(int k) {
 
 // cell flags (uint8 per cell)
 constexpr uint8_t kSolid = 0x80;   // covered by a particle (owner array holds which)
-constexpr uint8_t kNear = 0x40;    // fluid cell with at least one wall or particle link
+constexpr uint8_t kNearP = 0x40;   // fluid cell with a particle link (owner array holds which)
+constexpr uint8_t kNearW = 0x20;   // fluid cell with a wall link
 
 // status words in device memory
 constexpr int kStatusUnstable = 0;  // non-finite density / force / torque
-constexpr int kStatusRange = 1;     // particle left its box / two particles on one cell
+constexpr int kStatusRange = 1;     // particle moved too fast / links to two particles from one cell
 constexpr int kStatusWords = 16;
 
 // ---------------------------------------------------------------------------
@@ -72,6 +73,16 @@ template <> struct Store<__half> {
   static __device__ __forceinline__ __half store(float v) { return __float2half_rn(v); }
 };
 
+// streaming (nontemporal) store of one stored population
+template <typename S>
+__device__ __forceinline__ void store_nt(S* p, S v) {
+  __builtin_nontemporal_store(v, p);
+}
+template <>
+__device__ __forceinline__ void store_nt<__half>(__half* p, __half v) {
+  __builtin_nontemporal_store(__half_as_ushort(v), reinterpret_cast<unsigned short*>(p));
+}
+
 // ---------------------------------------------------------------------------
 // particle record (FP64), one per sphere, in device memory
 // ---------------------------------------------------------------------------
@@ -82,7 +93,7 @@ struct DevParticle {
   double Fprev[3], Tprev[3];   // of the step before
   double r, rho, cv, cvw;
   int fixed, have_prev;
-  int box_lo[3];               // force-slot box origin for the coming sweep
+  int box_lo[3];               // box of the coming sweep (holds every link cell)
   int remap_lo[3];             // re-mapping region origin (old and new position)
 };
 

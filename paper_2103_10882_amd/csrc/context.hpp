@@ -21,6 +21,8 @@ struct vmlbm_ctx {
   std::vector<vmlbm_sphere> spheres;
   bool moving = false;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;              // boundary kernels, forked from and joined to `stream`
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_needed = 0;
@@ -34,7 +36,7 @@ struct vmlbm_ctx {
   size_t off_status = 0, off_pdf[2] = {0, 0}, off_flags = 0, off_owner = 0, off_parts = 0, off_slots = 0,
          off_hist = 0;
   int cur = 0;
-  int box = 0, slot_wx = 0, nwx = 0;
+  int box = 0;
   size_t slot_stride = 0;
 
   // progress and timing
@@ -78,6 +80,7 @@ int refine_read_populations(vmlbm_ctx* c, int level, double* out);
 int refine_write_populations(vmlbm_ctx* c, int level, const double* in);
 int refine_read_owner(vmlbm_ctx* c, int level, int* out);
 int refine_level_cells(vmlbm_ctx* c, int level, size_t* cells);
+int refine_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* interior);
 void refine_destroy(vmlbm_ctx* c);
 // body force of a level in that level's lattice units
 void level_force(const vmlbm_ctx* c, int level, double F[3]);

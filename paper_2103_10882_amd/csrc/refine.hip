@@ -16,6 +16,7 @@ int refine_read_populations(vmlbm_ctx*, int, double*) { return VMLBM_ESTATE; }
 int refine_write_populations(vmlbm_ctx*, int, const double*) { return VMLBM_ESTATE; }
 int refine_read_owner(vmlbm_ctx*, int, int*) { return VMLBM_ESTATE; }
 int refine_level_cells(vmlbm_ctx*, int, size_t*) { return VMLBM_ESTATE; }
+int refine_cell_counts(vmlbm_ctx*, int, long long*, long long*) { return VMLBM_ESTATE; }
 void refine_destroy(vmlbm_ctx*) {}
 
 void level_force(const vmlbm_ctx* c, int level, double F[3]) {

@@ -73,36 +73,51 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
   using T = typename Store<S>::T;
   const uint32_t N = p.N;
   const int n[3] = {p.nx, p.ny, p.nz};
-  d[0] = Store<S>::load(src[c]);
+  // pass 1: pull source of every direction and its flag, loads issued together
+  uint32_t sidx[kQ];
+  int8_t wall[kQ];          // -1: inside the domain, else 2*axis + side of the wall crossed
+  uint8_t sfl[kQ];
+#pragma unroll
   for (int q = 1; q < kQ; ++q) {
+    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+    int s3[3] = {x - cq[0], y - cq[1], z - cq[2]};
+    wall[q] = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (s3[a] < 0 || s3[a] >= n[a]) {
+        if (p.per[a]) s3[a] = s3[a] < 0 ? s3[a] + n[a] : s3[a] - n[a];
+        else if (wall[q] < 0) { wall[q] = (int8_t)(2 * a + (s3[a] < 0 ? 0 : 1)); s3[a] = 0; }
+        else s3[a] = 0;
+      }
+    }
+    sidx[q] = ((uint32_t)s3[2] * n[1] + s3[1]) * n[0] + s3[0];
+  }
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;
+  // pass 2: plain streaming where the source is fluid
+  d[0] = Store<S>::load(src[c]);
+#pragma unroll
+  for (int q = 1; q < kQ; ++q)
+    if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = Store<S>::load(src[(size_t)q * N + sidx[q]]);
+  // pass 3: links
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    if (wall[q] < 0 && !(sfl[q] & kSolid)) continue;
     const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
     const int qq = opp_of(q);
     const double w = w_of(q);
-    // pull source x - c_q
-    int s[3] = {x - cq[0], y - cq[1], z - cq[2]};
-    int wall_axis = -1, wall_side = 0;
-    for (int a = 0; a < 3; ++a) {
-      if (s[a] < 0 || s[a] >= n[a]) {
-        if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-        else if (wall_axis < 0) { wall_axis = a; wall_side = s[a] < 0 ? 0 : 1; }
-      }
-    }
     const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
-    if (wall_axis >= 0) {
+    if (wall[q] >= 0) {
       // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
+      const int wa = wall[q] >> 1, ws = wall[q] & 1;
       double cv = 0.0;
-      if (wall_axis == p.wall_axis)
-        cv = -(cq[0] * p.wall_v[wall_side][0] + cq[1] * p.wall_v[wall_side][1] + cq[2] * p.wall_v[wall_side][2]);
+      if (wa == p.wall_axis)
+        cv = -(cq[0] * p.wall_v[ws][0] + cq[1] * p.wall_v[ws][1] + cq[2] * p.wall_v[ws][2]);
       d[q] = own_qq - T(6.0 * w * cv);
       continue;
     }
-    const uint32_t sidx = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
-    if (!(flags[sidx] & kSolid)) {
-      d[q] = Store<S>::load(src[(size_t)q * N + sidx]);
-      continue;
-    }
     // particle link in direction qq (c_qq = -c_q points into the solid)
-    const int pi = owner[sidx];
+    const int pi = owner[sidx[q]];
     const DevParticle& P = parts[pi];
     double off[3];
     sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
@@ -116,6 +131,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     // second node x - c_qq = x + c_q
     int t[3] = {x + cq[0], y + cq[1], z + cq[2]};
     bool second_ok = true;
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
       if (t[a] < 0 || t[a] >= n[a]) {
         if (p.per[a]) t[a] = t[a] < 0 ? t[a] + n[a] : t[a] - n[a];
@@ -140,6 +156,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     // link force: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
     const double a0 = (double)own_qq, a1 = (double)val;
     double Fq[3];
+#pragma unroll
     for (int a = 0; a < 3; ++a) Fq[a] = (-cq[a] - v[a]) * a0 + (-cq[a] + v[a]) * a1;
     if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
     pid = pi;
@@ -156,71 +173,120 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// per-wave partial sums of the link forces into the sphere's slot box
-__device__ void wave_force_partials(int pid, const double (&Fl)[3], const double (&Tl)[3],
-                                    const DevParticle* __restrict__ parts, double* __restrict__ slots,
-                                    const SweepParams& p, int x, int y, int z, int* __restrict__ status) {
-  const int lane = threadIdx.x & 63;
-  unsigned long long pending = __ballot(pid >= 0);
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const int tp = __shfl(pid, leader, 64);
-    const bool mine = pid == tp;
-    double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = wave_sum(mine ? v[k] : 0.0);
-    if (lane == leader) {
-      const DevParticle& P = parts[tp];
-      const int wx = x >> 6;
-      int ox = wx - (P.box_lo[0] >> 6);
-      if (p.per[0]) ox = (ox % p.nwx + p.nwx) % p.nwx;
-      int oy = y - P.box_lo[1];
-      if (p.per[1]) oy = (oy % p.ny + p.ny) % p.ny;
-      int oz = z - P.box_lo[2];
-      if (p.per[2]) oz = (oz % p.nz + p.nz) % p.nz;
-      if (ox < 0 || ox >= p.slot_wx || oy < 0 || oy >= p.box || oz < 0 || oz >= p.box) {
-        status[kStatusRange] = 1;
-      } else {
-        double* s = slots + (size_t)tp * p.slot_stride + (size_t)(((oz * p.box) + oy) * p.slot_wx + ox) * 6;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) s[k] += v[k];
-      }
-    }
-    pending &= ~__ballot(mine);
-  }
-}
-
+// Interior sweep: every fluid cell without a wall or particle link.  Cells
+// with a nonzero flag are left to the boundary kernels below (solid cells are
+// not computed at all), so this kernel carries only the streaming pull and
+// the collision and keeps its register footprint small.
 template <typename S, bool FLAGS>
-__global__ __launch_bounds__(256) void k_sweep(const S* __restrict__ src, S* __restrict__ dst,
-                                               const uint8_t* __restrict__ flags,
-                                               const uint16_t* __restrict__ owner,
-                                               const DevParticle* __restrict__ parts,
-                                               double* __restrict__ slots, int* __restrict__ status,
+__global__ __launch_bounds__(512) void k_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                               const uint8_t* __restrict__ flags, int* __restrict__ status,
                                                SweepParams p) {
   using T = typename Store<S>::T;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y, z = blockIdx.z;
-  const bool active = x < p.nx;
+  if (x >= p.nx) return;
   const uint32_t N = p.N;
   const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
-  uint8_t fl = 0;
-  if (FLAGS && active) fl = flags[c];
+  if (FLAGS && flags[c] != 0) return;
+  T d[kQ];
+  const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz);
+  load_all<S>(src, N, I, x, d, std::make_integer_sequence<int, kQ>{});
+  const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  if (!(drho == drho)) status[kStatusUnstable] = 1;
+  // streaming stores: the new state is not read again within this sweep
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], Store<S>::store(d[q]));
+}
+
+// cell k of a sphere's box (edge p.box) -> grid cell; false if outside the domain
+__device__ __forceinline__ bool box_cell(const int* lo, int k, int edge, const SweepParams& p,
+                                         int& x, int& y, int& z) {
+  const int i = k % edge, j = (k / edge) % edge, l = k / (edge * edge);
+  int s[3] = {lo[0] + i, lo[1] + j, lo[2] + l};
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (p.per[a]) s[a] = ((s[a] % n[a]) + n[a]) % n[a];
+    else if (s[a] < 0 || s[a] >= n[a]) return false;
+  }
+  x = s[0]; y = s[1]; z = s[2];
+  return true;
+}
+
+// Particle-link cells: one grid row per sphere over its box; a cell is
+// handled in the pass of the sphere it links to (owner array).  Every wave
+// writes its FP64 partial force/torque (zero if it holds no link) to its own
+// slot, so the per-sphere reduction reads a fixed set in a fixed order.
+template <typename S>
+__global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict__ src, S* __restrict__ dst,
+                                                            const uint8_t* __restrict__ flags,
+                                                            const uint16_t* __restrict__ owner,
+                                                            const DevParticle* __restrict__ parts,
+                                                            double* __restrict__ slots, int* __restrict__ status,
+                                                            SweepParams p) {
+  using T = typename Store<S>::T;
+  const int pi = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int edge = p.box;
+  int x = 0, y = 0, z = 0;
+  bool active = k < edge * edge * edge && box_cell(parts[pi].box_lo, k, edge, p, x, y, z);
+  uint32_t c = 0;
+  if (active) {
+    c = ((uint32_t)z * p.ny + y) * p.nx + x;
+    const uint8_t fl = flags[c];
+    active = (fl & kNearP) && owner[c] == pi;
+  }
   int pid = -1;
   double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
-  if (active && !(fl & kSolid)) {
+  if (active) {
     T d[kQ];
-    if (!FLAGS || !(fl & kNear)) {
-      const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz);
-      load_all<S>(src, N, I, x, d, std::make_integer_sequence<int, kQ>{});
-    } else {
-      boundary_cell<S>(src, flags, owner, parts, p, x, y, z, c, d, pid, Fl, Tl, status);
-    }
+    boundary_cell<S>(src, flags, owner, parts, p, x, y, z, c, d, pid, Fl, Tl, status);
+    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
     const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store(d[q]);
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
   }
-  if (FLAGS) wave_force_partials(pid, Fl, Tl, parts, slots, p, x, y, z, status);
+  double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
+  if ((threadIdx.x & 63) == 0) {
+    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(k >> 6) * 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) o[j] = v[j];
+  }
+}
+
+// Wall-link cells without particle links: the two boundary planes of each
+// non-periodic axis (a cell on planes of two axes is taken by the lower axis).
+template <typename S>
+__global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ src, S* __restrict__ dst,
+                                                        const uint8_t* __restrict__ flags,
+                                                        const uint16_t* __restrict__ owner,
+                                                        const DevParticle* __restrict__ parts,
+                                                        int* __restrict__ status, SweepParams p, int axis,
+                                                        int side) {
+  using T = typename Store<S>::T;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const int a1 = axis == 0 ? 1 : 0, a2 = axis == 2 ? 1 : 2;
+  const int u = blockIdx.x * blockDim.x + threadIdx.x, v = blockIdx.y;
+  if (u >= n[a1]) return;
+  int r[3];
+  r[axis] = side ? n[axis] - 1 : 0;
+  r[a1] = u;
+  r[a2] = v;
+  for (int b = 0; b < axis; ++b)
+    if (!p.per[b] && (r[b] == 0 || r[b] == n[b] - 1)) return;
+  const uint32_t c = ((uint32_t)r[2] * p.ny + r[1]) * p.nx + r[0];
+  const uint8_t fl = flags[c];
+  if ((fl & kSolid) || (fl & kNearP) || !(fl & kNearW)) return;
+  int pid = -1;
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  T d[kQ];
+  boundary_cell<S>(src, flags, owner, parts, p, r[0], r[1], r[2], c, d, pid, Fl, Tl, status);
+  const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  if (!(drho == drho)) status[kStatusUnstable] = 1;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,16 +328,18 @@ __device__ int cell_owner(int x, int y, int z, const DevParticle* __restrict__ p
 }
 
 __device__ void map_cell(int x, int y, int z, uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
-                         const DevParticle* __restrict__ parts, int np, const SweepParams& p) {
+                         const DevParticle* __restrict__ parts, int np, const SweepParams& p,
+                         int* __restrict__ status) {
   const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
   const int o = cell_owner(x, y, z, parts, np, p);
   uint8_t f = 0;
+  int link = -1;
   if (o >= 0) {
     f = kSolid;
-    owner[c] = (uint16_t)o;
+    link = o;
   } else {
     const int n[3] = {p.nx, p.ny, p.nz};
-    for (int q = 1; q < kQ && !f; ++q) {
+    for (int q = 1; q < kQ; ++q) {
       int s[3] = {x + cx_of(q), y + cy_of(q), z + cz_of(q)};
       bool wall = false;
       for (int a = 0; a < 3; ++a)
@@ -279,36 +347,31 @@ __device__ void map_cell(int x, int y, int z, uint8_t* __restrict__ flags, uint1
           if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
           else wall = true;
         }
-      if (wall || cell_owner(s[0], s[1], s[2], parts, np, p) >= 0) f = kNear;
+      if (wall) { f |= kNearW; continue; }
+      const int so = cell_owner(s[0], s[1], s[2], parts, np, p);
+      if (so >= 0) {
+        if (link >= 0 && link != so) status[kStatusRange] = 4;
+        if (link < 0) link = so;
+        f |= kNearP;
+      }
     }
   }
   flags[c] = f;
+  owner[c] = link < 0 ? 0 : (uint16_t)link;
 }
 
 __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
-                                                 const DevParticle* __restrict__ parts, int np, SweepParams p) {
+                                                 const DevParticle* __restrict__ parts, int np, SweepParams p,
+                                                 int* __restrict__ status) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= p.N) return;
   const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / ((uint32_t)p.nx * p.ny);
-  map_cell(x, y, z, flags, owner, parts, np, p);
-}
-
-// region cell k of the re-mapping box of particle pi -> grid cell, or false
-__device__ __forceinline__ bool region_cell(const DevParticle& P, int k, int rb, const SweepParams& p,
-                                            int& x, int& y, int& z) {
-  const int i = k % rb, j = (k / rb) % rb, l = k / (rb * rb);
-  int s[3] = {P.remap_lo[0] + i, P.remap_lo[1] + j, P.remap_lo[2] + l};
-  const int n[3] = {p.nx, p.ny, p.nz};
-  for (int a = 0; a < 3; ++a) {
-    if (p.per[a]) s[a] = ((s[a] % n[a]) + n[a]) % n[a];
-    else if (s[a] < 0 || s[a] >= n[a]) return false;
-  }
-  x = s[0]; y = s[1]; z = s[2];
-  return true;
+  map_cell(x, y, z, flags, owner, parts, np, p, status);
 }
 
 __global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
-                                               const DevParticle* __restrict__ parts, int np, SweepParams p) {
+                                               const DevParticle* __restrict__ parts, int np, SweepParams p,
+                                               int* __restrict__ status) {
   const int pi = blockIdx.y;
   const DevParticle& P = parts[pi];
   if (P.fixed) return;
@@ -316,8 +379,8 @@ __global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= rb * rb * rb) return;
   int x, y, z;
-  if (!region_cell(P, k, rb, p, x, y, z)) return;
-  map_cell(x, y, z, flags, owner, parts, np, p);
+  if (!box_cell(P.remap_lo, k, rb, p, x, y, z)) return;
+  map_cell(x, y, z, flags, owner, parts, np, p, status);
 }
 
 // ---------------------------------------------------------------------------
@@ -341,7 +404,7 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= rb * rb * rb) return;
   int x, y, z;
-  if (!region_cell(P, k, rb, p, x, y, z)) return;
+  if (!box_cell(P.remap_lo, k, rb, p, x, y, z)) return;
   const uint32_t N = p.N;
   const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
   if (!(flags[c] & kSolid) || owner[c] != pi) return;
@@ -490,10 +553,10 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
   __shared__ double red[6][256];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   double* s = slots + (size_t)pi * p.slot_stride;
-  const int nslots = p.box * p.box * p.slot_wx;
+  const int nslots = (int)(p.slot_stride / 6);
   for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) { acc[j] += s[(size_t)k * 6 + j]; s[(size_t)k * 6 + j] = 0.0; }
+    for (int j = 0; j < 6; ++j) acc[j] += s[(size_t)k * 6 + j];
   }
 #pragma unroll
   for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
@@ -520,16 +583,50 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
 // launchers
 // ---------------------------------------------------------------------------
 template <typename S>
-hipError_t launch_sweep(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
-                        const DevParticle* parts, double* slots, int* status, const SweepParams& p,
-                        bool with_flags, hipStream_t st) {
-  const int bx = p.nx >= 256 ? 256 : 64;
+hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int* status, const SweepParams& p,
+                           bool with_flags, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  // one workgroup per grid row (up to 512 cells): the x-shifted loads of a
+  // row stay within one workgroup's cache lines
+  const int bx = p.nx >= 512 ? 512 : ((p.nx + 63) / 64) * 64;
   dim3 grid((p.nx + bx - 1) / bx, p.ny, p.nz), block(bx);
+  if (e0) {
+    hipError_t er = hipEventRecord(e0, st);
+    if (er != hipSuccess) return er;
+  }
   if (with_flags)
-    k_sweep<S, true><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, owner, parts, slots, status, p);
+    k_sweep<S, true><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
   else
-    k_sweep<S, false><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, owner, parts, slots, status, p);
-  return hipGetLastError();
+    k_sweep<S, false><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && e1) e = hipEventRecord(e1, st);
+  return e;
+}
+
+template <typename S>
+hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
+                           const DevParticle* parts, int np, double* slots, int* status, const SweepParams& p,
+                           hipStream_t st) {
+  hipError_t e = hipSuccess;
+  if (np > 0) {
+    const int cells = p.box * p.box * p.box;
+    k_boundary_particles<S><<<dim3((cells + 255) / 256, np), dim3(256), 0, st>>>(
+        (const S*)src, (S*)dst, flags, owner, parts, slots, status, p);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int n[3] = {p.nx, p.ny, p.nz};
+  for (int a = 0; a < 3; ++a) {
+    if (p.per[a]) continue;
+    const int a1 = a == 0 ? 1 : 0, a2 = a == 2 ? 1 : 2;
+    for (int side = 0; side < 2; ++side) {
+      if (side == 1 && n[a] == 1) break;
+      k_boundary_walls<S><<<dim3((n[a1] + 63) / 64, n[a2]), dim3(64), 0, st>>>(
+          (const S*)src, (S*)dst, flags, owner, parts, status, p, a, side);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
 }
 
 template <typename S>
@@ -541,21 +638,21 @@ hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double
 }
 
 hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np, const SweepParams& p,
-                          hipStream_t st) {
+                          int* status, hipStream_t st) {
   dim3 grid((p.N + 255) / 256), block(256);
-  k_map_all<<<grid, block, 0, st>>>(flags, owner, parts, np, p);
+  k_map_all<<<grid, block, 0, st>>>(flags, owner, parts, np, p, status);
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                               const SweepParams& p, hipStream_t st) {
+                               const SweepParams& p, int* status, hipStream_t st) {
   const int rb = p.box + 1;
   dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
   k_refill<S><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_remap<<<grid, block, 0, st>>>(flags, owner, parts, np, p);
+  k_remap<<<grid, block, 0, st>>>(flags, owner, parts, np, p, status);
   return hipGetLastError();
 }
 
@@ -565,20 +662,26 @@ hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, doubl
   return hipGetLastError();
 }
 
-template hipError_t launch_sweep<double>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                         double*, int*, const SweepParams&, bool, hipStream_t);
-template hipError_t launch_sweep<float>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                        double*, int*, const SweepParams&, bool, hipStream_t);
-template hipError_t launch_sweep<__half>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                         double*, int*, const SweepParams&, bool, hipStream_t);
+template hipError_t launch_interior<double>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
+                                            hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_boundary<double>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
+                                            int, double*, int*, const SweepParams&, hipStream_t);
+template hipError_t launch_interior<float>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
+                                            hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_boundary<float>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
+                                            int, double*, int*, const SweepParams&, hipStream_t);
+template hipError_t launch_interior<__half>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
+                                            hipStream_t, hipEvent_t, hipEvent_t);
+template hipError_t launch_boundary<__half>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
+                                            int, double*, int*, const SweepParams&, hipStream_t);
 template hipError_t launch_init<double>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_init<float>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_init<__half>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_refill_remap<double>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                                const SweepParams&, hipStream_t);
+                                                const SweepParams&, int*, hipStream_t);
 template hipError_t launch_refill_remap<float>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                               const SweepParams&, hipStream_t);
+                                               const SweepParams&, int*, hipStream_t);
 template hipError_t launch_refill_remap<__half>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                                const SweepParams&, hipStream_t);
+                                                const SweepParams&, int*, hipStream_t);
 
 }  // namespace vm

@@ -16,10 +16,8 @@ struct SweepParams {
   double sp, sm;          // s+ = omega, s- from the magic parameter
   double F[3];            // fluid body force
   uint32_t N;             // cells
-  int box;                // force-slot box edge (cells)
-  int slot_wx;            // x-waves per box row
-  int nwx;                // x-waves per grid row
-  size_t slot_stride;     // doubles per particle in the slot array
+  int box;                // edge of a sphere's box (cells); holds all its link cells
+  size_t slot_stride;     // doubles per sphere in the force-slot array (6 per wave)
 };
 
 struct UpdateParams {
@@ -29,18 +27,25 @@ struct UpdateParams {
   int np;
 };
 
+// interior sweep (cells without links); e0/e1, if given, are recorded
+// around it
 template <typename S>
-hipError_t launch_sweep(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
-                        const DevParticle* parts, double* slots, int* status, const SweepParams& p,
-                        bool with_flags, hipStream_t st);
+hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int* status, const SweepParams& p,
+                           bool with_flags, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// particle-link and wall-link cells; writes cells disjoint from the
+// interior sweep, so both may run concurrently
+template <typename S>
+hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
+                           const DevParticle* parts, int np, double* slots, int* status, const SweepParams& p,
+                           hipStream_t st);
 template <typename S>
 hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double drho, const SweepParams& p,
                        hipStream_t st);
 hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                          const SweepParams& p, hipStream_t st);
+                          const SweepParams& p, int* status, hipStream_t st);
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                               const SweepParams& p, hipStream_t st);
+                               const SweepParams& p, int* status, hipStream_t st);
 hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
                                 const SweepParams& p, const UpdateParams& u, hipStream_t st);
 
