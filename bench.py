@@ -112,6 +112,28 @@ def run_rising(pkg, steps):
     return out
 
 
+def run_adjoint(pkg, storage="f32"):
+    """Drag gradient on a fixed sphere (128^3, r=10, 2000 steps, window
+    1500..1999, checkpoints every 50): forward-with-checkpoints time vs
+    reverse time (segment recomputation + adjoint sweeps)."""
+    import torch
+    import synth
+    w = synth.adjoint()
+    N, A, K = w["steps"], w["avg_from"], w["ckpt_every"]
+    sim = pkg.Sim(w["config"], w["spheres"], storage=storage, history=N - A, adjoint_steps=N, ckpt_every=K)
+    sim.forward_ckpt(0, N, A, K)          # warm-up
+    sim.adjoint(1.0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = sim.forward_ckpt(0, N, A, K)
+    t1 = time.perf_counter()
+    g = sim.adjoint(1.0)
+    t2 = time.perf_counter()
+    sim.close()
+    return {"storage": storage, "steps": N, "J": J, "dJ_dF": float(g[0]), "dJ_domega": float(g[1]),
+            "forward_s": t1 - t0, "reverse_s": t2 - t1, "cost_ratio": (t2 - t1) / (t1 - t0)}
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle on a bounded sample of the headline workload: a 128^3
     periodic box holding one of its fixed r=20 spheres, same omega and body
@@ -216,6 +238,9 @@ def main():
     if not args.no_extra:
         log("rising sphere 256^3")
         line["rising"] = run_rising(pkg, 2000)
+        log("adjoint 128^3")
+        line["adjoint"] = run_adjoint(pkg)
+        line["adjoint_cost"] = round(line["adjoint"]["cost_ratio"], 3)
     if not args.no_cpu:
         log("cpu baseline")
         line["cpu_baseline"] = cpu_baseline()

@@ -288,3 +288,32 @@ class Sim:
         g = np.zeros(2)
         self._check(self.L.vmlbm_adjoint(self.h, float(dJ), _ptr(g)), "adjoint")
         return g
+
+
+def _drag_grad_function():
+    import torch
+
+    class DragGrad(torch.autograd.Function):
+        """J(F_z, omega): time-averaged z-drag of a fixed sphere after a
+        forward run from rest; backward runs the library's discrete adjoint
+        with checkpoint recomputation."""
+
+        @staticmethod
+        def forward(ctx, force_z, omega, sim, sphere, n_steps, avg_from, ckpt_every):
+            sim.set_params(float(force_z), float(omega))
+            J = sim.forward_ckpt(sphere, n_steps, avg_from, ckpt_every)
+            ctx.sim = sim
+            return torch.tensor(J, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gJ):
+            g = ctx.sim.adjoint(float(gJ))
+            return (torch.tensor(g[0], dtype=torch.float64), torch.tensor(g[1], dtype=torch.float64),
+                    None, None, None, None, None)
+
+    return DragGrad
+
+
+def drag(force_z, omega, sim, sphere=0, n_steps=2000, avg_from=1500, ckpt_every=50):
+    """Differentiable time-averaged drag (torch scalars in, torch scalar out)."""
+    return _drag_grad_function().apply(force_z, omega, sim, sphere, n_steps, avg_from, ckpt_every)

@@ -14,7 +14,7 @@
 
 using namespace vm;
 
-namespace {
+namespace vm {
 
 int fail(vmlbm_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -26,15 +26,13 @@ int fail(vmlbm_ctx* c, int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(ctx, expr)                                                                  \
-  do {                                                                                      \
-    hipError_t e_ = (expr);                                                                 \
-    if (e_ != hipSuccess) return fail(ctx, VMLBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
-  } while (0)
+size_t storage_bytes(int storage) { return storage == VMLBM_F64 ? 8 : storage == VMLBM_F32 ? 4 : 2; }
+
+}  // namespace vm
+
+namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-size_t storage_bytes(int storage) { return storage == VMLBM_F64 ? 8 : storage == VMLBM_F32 ? 4 : 2; }
 
 // uniform-grid workspace layout
 void plan_uniform(vmlbm_ctx* c) {
@@ -59,30 +57,6 @@ void plan_uniform(vmlbm_ctx* c) {
   c->off_hist = take((size_t)std::max(g.history, 1) * std::max(np, 1) * 12 * sizeof(double));
   adjoint_plan(c, take);
   c->ws_needed = off;
-}
-
-SweepParams sweep_params(const vmlbm_ctx* c) {
-  const vmlbm_config& g = c->cfg;
-  SweepParams p{};
-  p.nx = g.n[0]; p.ny = g.n[1]; p.nz = g.n[2];
-  for (int a = 0; a < 3; ++a) p.per[a] = g.periodic[a];
-  p.wall_axis = c->wall_axis;
-  for (int s = 0; s < 2; ++s)
-    for (int a = 0; a < 3; ++a) p.wall_v[s][a] = g.wall_velocity[s][a];
-  p.sp = c->sp;
-  p.sm = c->sm;
-  for (int a = 0; a < 3; ++a) p.F[a] = c->F[a];
-  p.N = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
-  p.box = c->box;
-  p.slot_stride = c->slot_stride;
-  return p;
-}
-
-template <typename F>
-int dispatch(int storage, F&& f) {
-  if (storage == VMLBM_F64) return f((double*)nullptr);
-  if (storage == VMLBM_F32) return f((float*)nullptr);
-  return f((__half*)nullptr);
 }
 
 double dev_to_double(const void* buf, int storage, size_t i) {
@@ -137,10 +111,51 @@ void fold_timing(vmlbm_ctx* c) {
 // ---------------------------------------------------------------------------
 namespace vm {
 
+SweepParams sweep_params(const vmlbm_ctx* c) {
+  const vmlbm_config& g = c->cfg;
+  SweepParams p{};
+  p.nx = g.n[0]; p.ny = g.n[1]; p.nz = g.n[2];
+  for (int a = 0; a < 3; ++a) p.per[a] = g.periodic[a];
+  p.wall_axis = c->wall_axis;
+  for (int s = 0; s < 2; ++s)
+    for (int a = 0; a < 3; ++a) p.wall_v[s][a] = g.wall_velocity[s][a];
+  p.sp = c->sp;
+  p.sm = c->sm;
+  for (int a = 0; a < 3; ++a) p.F[a] = c->F[a];
+  p.N = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
+  p.box = c->box;
+  p.slot_stride = c->slot_stride;
+  return p;
+}
+
+// one sweep src -> dst: boundary cells on the side stream, concurrently with
+// the interior sweep; joined back into the main stream
+int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1) {
+  const int np = (int)c->spheres.size();
+  const bool flags = c->use_flags;
+  if (flags) {
+    HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+  }
+  int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    if (flags)
+      HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->slots(), c->status(), p,
+                                    c->side));
+    HIP_TRY(c, launch_interior<S>(src, dst, c->flags(), c->status(), p, flags, c->stream, e0, e1));
+    return VMLBM_OK;
+  });
+  if (rc) return rc;
+  if (flags) {
+    HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
+    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  }
+  return VMLBM_OK;
+}
+
 int uniform_step(vmlbm_ctx* c, int nsteps) {
   const SweepParams p = sweep_params(c);
   const int np = (int)c->spheres.size();
-  const bool flags = c->use_flags;
   for (int s = 0; s < nsteps; ++s) {
     void* src = c->ws + c->off_pdf[c->cur];
     void* dst = c->ws + c->off_pdf[1 - c->cur];
@@ -150,24 +165,8 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
       HIP_TRY(c, hipEventCreate(&e1));
       c->sweep_events.emplace_back(e0, e1);
     }
-    // boundary cells on the side stream, concurrently with the interior sweep
-    if (flags) {
-      HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
-      HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-    }
-    int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
-      using S = std::remove_pointer_t<decltype(tag)>;
-      if (flags)
-        HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->slots(), c->status(), p,
-                                      c->side));
-      HIP_TRY(c, launch_interior<S>(src, dst, c->flags(), c->status(), p, flags, c->stream, e0, e1));
-      return VMLBM_OK;
-    });
+    int rc = sweep_once(c, p, src, dst, e0, e1);
     if (rc) return rc;
-    if (flags) {
-      HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
-      HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-    }
     if (np > 0) {
       UpdateParams u{};
       for (int a = 0; a < 3; ++a) u.g[a] = c->cfg.gravity[a];

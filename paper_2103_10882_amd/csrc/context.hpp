@@ -66,6 +66,26 @@ struct vmlbm_ctx {
 namespace vm {
 using Take = std::function<size_t(size_t)>;
 
+int fail(vmlbm_ctx* c, int code, const char* fmt, ...);
+#define HIP_TRY(ctx, expr)                                                                           \
+  do {                                                                                               \
+    hipError_t e_ = (expr);                                                                          \
+    if (e_ != hipSuccess) return vm::fail(ctx, VMLBM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// run f with a null pointer of the storage type
+template <typename F>
+int dispatch(int storage, F&& f) {
+  if (storage == VMLBM_F64) return f((double*)nullptr);
+  if (storage == VMLBM_F32) return f((float*)nullptr);
+  return f((__half*)nullptr);
+}
+
+struct SweepParams;
+SweepParams sweep_params(const vmlbm_ctx* c);
+int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1);
+size_t storage_bytes(int storage);
+
 int uniform_step(vmlbm_ctx* c, int nsteps);
 
 // adjoint (adjoint.hip)
