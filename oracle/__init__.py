@@ -269,5 +269,136 @@ def num_threads():
     return lib().ora_num_threads()
 
 
+class RConfig(ctypes.Structure):
+    _fields_ = [("n0", ctypes.c_int * 3), ("block", ctypes.c_int), ("levels", ctypes.c_int),
+                ("omega", ctypes.c_double), ("magic", ctypes.c_double), ("body_force", ctypes.c_double * 3),
+                ("gravity", ctypes.c_double * 3), ("check_every", ctypes.c_int)]
+
+
 def _bind_refine(L):
-    pass
+    vp = ctypes.c_void_p
+    L.orf_create.restype = vp
+    L.orf_create.argtypes = [ctypes.POINTER(RConfig)]
+    L.orf_destroy.restype = None
+    L.orf_destroy.argtypes = [vp]
+    for name, args in [
+        ("orf_add_region", [vp, vp, vp, ctypes.c_int]),
+        ("orf_add_sphere", [vp, ctypes.POINTER(Sphere)]),
+        ("orf_init", [vp, ctypes.c_double, vp]),
+        ("orf_set_level_velocity", [vp, ctypes.c_int, ctypes.c_double, vp]),
+        ("orf_step", [vp, ctypes.c_int]),
+        ("orf_level_dims", [vp, ctypes.c_int, vp]),
+        ("orf_block_grid", [vp, vp]),
+        ("orf_leaf", [vp, vp]),
+        ("orf_read_level", [vp, ctypes.c_int, vp, vp]),
+        ("orf_mass", [vp, vp]),
+        ("orf_force_torque", [vp, ctypes.c_int, vp, vp]),
+        ("orf_particle", [vp, ctypes.c_int, vp, vp, vp]),
+        ("orf_owner", [vp, vp]),
+        ("orf_counters", [vp, vp, vp, vp]),
+    ]:
+        fn = getattr(L, name)
+        fn.restype = ctypes.c_int
+        fn.argtypes = args
+
+
+class Refined:
+    """Refined-grid oracle: periodic block-structured 2:1 grid.
+
+    cfg: synth config with "levels" and "block"; n is the coarsest grid.
+    regions: list of (lo, hi, level) coarse-cell boxes to hold at >= level.
+    """
+
+    def __init__(self, cfg, spheres=(), regions=(), check_every=0):
+        c = RConfig()
+        for a in range(3):
+            c.n0[a] = int(cfg["n"][a])
+            c.body_force[a] = float(cfg["body_force"][a])
+            c.gravity[a] = float(cfg["gravity"][a])
+        c.block = int(cfg["block"])
+        c.levels = int(cfg["levels"])
+        c.omega = float(cfg["omega"])
+        c.magic = float(cfg["magic"])
+        c.check_every = int(check_every)
+        self._c = c
+        self.h = lib().orf_create(ctypes.byref(c))
+        if not self.h:
+            raise RuntimeError("orf_create failed")
+        self.levels = c.levels
+        for lo, hi, lev in regions:
+            lo = np.ascontiguousarray(lo, dtype=np.int32)
+            hi = np.ascontiguousarray(hi, dtype=np.int32)
+            _check(lib().orf_add_region(self.h, lo.ctypes.data, hi.ctypes.data, int(lev)), "add_region")
+        for s in spheres:
+            o = make_sphere(s)
+            if lib().orf_add_sphere(self.h, ctypes.byref(o)) < 0:
+                raise RuntimeError("orf_add_sphere failed")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orf_destroy(self.h)
+            self.h = None
+
+    def init(self, rho=1.0, u0=None):
+        if u0 is not None:
+            u0 = np.ascontiguousarray(u0, dtype=np.float64)
+            _check(lib().orf_init(self.h, float(rho), u0.ctypes.data), "init")
+        else:
+            _check(lib().orf_init(self.h, float(rho), None), "init")
+
+    def set_level_velocity(self, level, rho, u):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        _check(lib().orf_set_level_velocity(self.h, level, float(rho), u.ctypes.data), "set_level_velocity")
+
+    def step(self, n=1):
+        _check(lib().orf_step(self.h, int(n)), "step")
+
+    def dims(self, level):
+        n = np.zeros(3, dtype=np.int32)
+        _check(lib().orf_level_dims(self.h, level, n.ctypes.data), "level_dims")
+        return tuple(int(v) for v in n)
+
+    def block_grid(self):
+        n = np.zeros(3, dtype=np.int32)
+        _check(lib().orf_block_grid(self.h, n.ctypes.data), "block_grid")
+        return tuple(int(v) for v in n)
+
+    def leaf(self):
+        nx, ny, nz = self.block_grid()
+        out = np.zeros((nz, ny, nx), dtype=np.int32)
+        _check(lib().orf_leaf(self.h, out.ctypes.data), "leaf")
+        return out
+
+    def level(self, level):
+        nx, ny, nz = self.dims(level)
+        f = np.zeros((19, nz, ny, nx))
+        k = np.zeros((nz, ny, nx), dtype=np.uint8)
+        _check(lib().orf_read_level(self.h, level, f.ctypes.data, k.ctypes.data), "read_level")
+        return f, k
+
+    def mass(self):
+        m = np.zeros(1)
+        _check(lib().orf_mass(self.h, m.ctypes.data), "mass")
+        return float(m[0])
+
+    def force_torque(self, i=0):
+        F, T = np.zeros(3), np.zeros(3)
+        _check(lib().orf_force_torque(self.h, i, F.ctypes.data, T.ctypes.data), "force_torque")
+        return F, T
+
+    def particle(self, i=0):
+        x, u, w = np.zeros(3), np.zeros(3), np.zeros(3)
+        _check(lib().orf_particle(self.h, i, x.ctypes.data, u.ctypes.data, w.ctypes.data), "particle")
+        return x, u, w
+
+    def owner(self):
+        nx, ny, nz = self.dims(self.levels - 1)
+        out = np.zeros((nz, ny, nx), dtype=np.int32)
+        _check(lib().orf_owner(self.h, out.ctypes.data), "owner")
+        return out
+
+    def counters(self):
+        a, b = ctypes.c_longlong(), ctypes.c_longlong()
+        r = ctypes.c_int()
+        _check(lib().orf_counters(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(r)), "counters")
+        return a.value, b.value, r.value

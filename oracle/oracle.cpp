@@ -19,153 +19,10 @@
 #include <vector>
 #include <omp.h>
 
+#include "core.hpp"
+
 namespace {
-
-// ---------------------------------------------------------------------------
-// D3Q19 lattice (Sec. 2.1).  The paper does not print the set; this is the
-// textbook D3Q19 in the order: rest, 6 axis, then the xy, xz, yz diagonals.
-// ---------------------------------------------------------------------------
-const int CX[19] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
-const int CY[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
-const int CZ[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
-
-double weight(int q) {
-  int c2 = CX[q] * CX[q] + CY[q] * CY[q] + CZ[q] * CZ[q];
-  if (c2 == 0) return 1.0 / 3.0;
-  if (c2 == 1) return 1.0 / 18.0;
-  return 1.0 / 36.0;
-}
-
-int opposite(int q) {
-  for (int r = 0; r < 19; ++r)
-    if (CX[r] == -CX[q] && CY[r] == -CY[q] && CZ[r] == -CZ[q]) return r;
-  return -1;
-}
-
-// ---------------------------------------------------------------------------
-// dual numbers: value plus N tangents, for the exact forward derivative
-// ---------------------------------------------------------------------------
-template <int N>
-struct Dual {
-  double v;
-  double d[N];
-  Dual() : v(0.0) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
-  Dual(double x) : v(x) { for (int i = 0; i < N; ++i) d[i] = 0.0; }
-};
-template <int N> Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r; r.v = a.v + b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
-template <int N> Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r; r.v = a.v - b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
-template <int N> Dual<N> operator-(const Dual<N>& a) {
-  Dual<N> r; r.v = -a.v; for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
-template <int N> Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r; r.v = a.v * b.v; for (int i = 0; i < N; ++i) r.d[i] = a.d[i] * b.v + a.v * b.d[i]; return r; }
-template <int N> Dual<N> operator/(const Dual<N>& a, const Dual<N>& b) {
-  Dual<N> r; r.v = a.v / b.v;
-  for (int i = 0; i < N; ++i) r.d[i] = (a.d[i] * b.v - a.v * b.d[i]) / (b.v * b.v);
-  return r; }
-template <int N> Dual<N> operator+(const Dual<N>& a, double b) { return a + Dual<N>(b); }
-template <int N> Dual<N> operator+(double a, const Dual<N>& b) { return Dual<N>(a) + b; }
-template <int N> Dual<N> operator-(const Dual<N>& a, double b) { return a - Dual<N>(b); }
-template <int N> Dual<N> operator-(double a, const Dual<N>& b) { return Dual<N>(a) - b; }
-template <int N> Dual<N> operator*(const Dual<N>& a, double b) { return a * Dual<N>(b); }
-template <int N> Dual<N> operator*(double a, const Dual<N>& b) { return Dual<N>(a) * b; }
-template <int N> Dual<N> operator/(const Dual<N>& a, double b) { return a / Dual<N>(b); }
-template <int N> Dual<N> operator/(double a, const Dual<N>& b) { return Dual<N>(a) / b; }
-template <int N> Dual<N>& operator+=(Dual<N>& a, const Dual<N>& b) { a = a + b; return a; }
-
-using D2 = Dual<2>;
-
-inline double value(double x) { return x; }
-template <int N> inline double value(const Dual<N>& x) { return x.v; }
-
-// accumulator for the force sums: extended precision for plain FP64
-template <class T> struct Acc { using type = T; };
-template <> struct Acc<double> { using type = long double; };
-inline double to_double(long double x) { return (double)x; }
-template <int N> inline Dual<N> to_double(const Dual<N>& x) { return x; }
-
-// ---------------------------------------------------------------------------
-// collision: TRT (MRT of Sec. 2.1 with Lambda_b = 1), incompressible
-// equilibrium with rho0 = 1 (moments of Sec. 2.1), Guo forcing.
-// reading: the paper gives no fluid body force; forcing follows Guo et al.
-// with the velocity shifted by F/2, split into its even and odd parts.
-// ---------------------------------------------------------------------------
-template <class T>
-void equilibrium(const T& rho, const T u[3], T feq[19]) {
-  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  for (int q = 0; q < 19; ++q) {
-    T cu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
-    feq[q] = weight(q) * (rho + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-  }
-}
-
-template <class T>
-T s_minus(const T& s_plus, double magic) {
-  // Lambda = (1/s+ - 1/2)(1/s- - 1/2)  ->  1/s- = 1/2 + Lambda / (1/s+ - 1/2)
-  return 1.0 / (0.5 + magic / (1.0 / s_plus - 0.5));
-}
-
-template <class T>
-void collide(const T f[19], const T& sp, const T& sm, const T F[3], T out[19]) {
-  T rho = 0.0, j[3] = {0.0, 0.0, 0.0};
-  for (int q = 0; q < 19; ++q) {
-    rho = rho + f[q];
-    j[0] = j[0] + CX[q] * f[q];
-    j[1] = j[1] + CY[q] * f[q];
-    j[2] = j[2] + CZ[q] * f[q];
-  }
-  T u[3];
-  for (int a = 0; a < 3; ++a) u[a] = j[a] + 0.5 * F[a];
-  T feq[19];
-  equilibrium(rho, u, feq);
-  T S[19];
-  for (int q = 0; q < 19; ++q) {
-    T cmu[3] = {CX[q] - u[0], CY[q] - u[1], CZ[q] - u[2]};
-    T cu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
-    T cF = CX[q] * F[0] + CY[q] * F[1] + CZ[q] * F[2];
-    S[q] = weight(q) * (3.0 * (cmu[0] * F[0] + cmu[1] * F[1] + cmu[2] * F[2]) + 9.0 * cu * cF);
-  }
-  for (int q = 0; q < 19; ++q) {
-    int qb = opposite(q);
-    T fp = 0.5 * (f[q] + f[qb]), fm = 0.5 * (f[q] - f[qb]);
-    T ep = 0.5 * (feq[q] + feq[qb]), em = 0.5 * (feq[q] - feq[qb]);
-    T Sp = 0.5 * (S[q] + S[qb]), Sm = 0.5 * (S[q] - S[qb]);
-    out[q] = f[q] - sp * (fp - ep) - sm * (fm - em) + (1.0 - 0.5 * sp) * Sp + (1.0 - 0.5 * sm) * Sm;
-  }
-}
-
-// ---------------------------------------------------------------------------
-// sphere geometry (Sec. 2.3): a cell is solid iff its centre lies in the
-// sphere (reading: |x_c - x_p|^2 <= r^2, minimum image on periodic axes);
-// the boundary distance ratio delta_q is the exact ray-sphere root.
-// ---------------------------------------------------------------------------
-struct Sph {
-  double x[3], u[3], w[3];
-  double r, rho, cv, cvw;
-  int fixed;
-  double a[3], b[3];            // accelerations of the previous step
-  double Fprev[3], Tprev[3];    // raw hydrodynamic F/T of the previous step
-  int have_prev;
-  double F[3], T[3];            // raw F^n, T^n of the last step
-};
-
-double min_image(double d, int n, int periodic) {
-  if (!periodic) return d;
-  if (d > 0.5 * n) d -= n;
-  else if (d < -0.5 * n) d += n;
-  return d;
-}
-
-double link_delta(const double d[3], const int c[3], double r) {
-  // |d + delta c|^2 = r^2, smallest root in (0, 1]
-  double cc = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-  double dc = d[0] * c[0] + d[1] * c[1] + d[2] * c[2];
-  double dd = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  double disc = dc * dc - cc * (dd - r * r);
-  if (disc < 0.0) return -1.0;
-  return (-dc - std::sqrt(disc)) / cc;
-}
+using namespace ora;
 
 // ---------------------------------------------------------------------------
 // uniform grid
@@ -378,44 +235,6 @@ struct Grid {
 };
 
 // ---------------------------------------------------------------------------
-// particle update (FP64): Sec. 2.2 velocity Verlet, Algorithm 1 with the
-// virtual force/torque of Sec. 3.3.
-// reading: hydrodynamic F/T "averaged over two time steps" is the mean of the
-// raw sums of this and the previous step (the first step uses its own);
-// a_{t-1} and beta_{t-1} start at zero; rho_f = 1; V_p = 4/3 pi r^3.
-// ---------------------------------------------------------------------------
-void update_particle(Sph& s, const double g[3], const int n[3], const int periodic[3]) {
-  double Fav[3], Tav[3];
-  for (int a = 0; a < 3; ++a) {
-    Fav[a] = s.have_prev ? 0.5 * (s.F[a] + s.Fprev[a]) : s.F[a];
-    Tav[a] = s.have_prev ? 0.5 * (s.T[a] + s.Tprev[a]) : s.T[a];
-  }
-  const double PI = 3.14159265358979323846;
-  double V = 4.0 / 3.0 * PI * s.r * s.r * s.r;
-  double m = (s.rho + s.cv) * V;                           // virtually increased mass
-  double I = 0.4 * (s.rho + s.cvw) * V * s.r * s.r;        // and moment of inertia
-  double an[3], bn[3];
-  for (int a = 0; a < 3; ++a) {
-    double Fg = (s.rho - 1.0) * g[a] * V;                  // gravity + buoyancy
-    double Fv = s.cv * V * s.a[a];                         // virtual force, m_v a_{t-1}
-    double Tv = 0.4 * s.cvw * V * s.r * s.r * s.b[a];      // virtual torque
-    an[a] = (Fav[a] + Fg + Fv) / m;
-    bn[a] = (Tav[a] + Tv) / I;
-  }
-  for (int a = 0; a < 3; ++a) {
-    s.u[a] = s.u[a] + 0.5 * (s.a[a] + an[a]);
-    s.w[a] = s.w[a] + 0.5 * (s.b[a] + bn[a]);
-    s.x[a] = s.x[a] + s.u[a] + 0.5 * an[a];
-    if (periodic[a]) {
-      if (s.x[a] < 0.0) s.x[a] += n[a];
-      else if (s.x[a] >= n[a]) s.x[a] -= n[a];
-    }
-    s.a[a] = an[a];
-    s.b[a] = bn[a];
-  }
-}
-
-// ---------------------------------------------------------------------------
 // refill of a newly uncovered cell (Sec. 2.3, after Dorschner et al.):
 // reading: rho is the mean density of the D3Q19 neighbours that held fluid
 // before the re-mapping; the velocity is the rigid-body velocity of the
@@ -473,17 +292,9 @@ void refill_cell(Grid<double>& G, const std::vector<int>& old_own, int x, int y,
   double S[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b) S[a][b] = 0.5 * (grad[a][b] + grad[b][a]);
-  double feq[19];
-  equilibrium(rho, v, feq);
-  double trS = S[0][0] + S[1][1] + S[2][2];
-  for (int q = 0; q < 19; ++q) {
-    const int cq[3] = {CX[q], CY[q], CZ[q]};
-    double QS = 0.0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) QS += cq[a] * cq[b] * S[a][b];
-    QS -= trS / 3.0;
-    G.fn[q * N + c] = feq[q] - 3.0 * weight(q) / G.cfg.omega * QS;
-  }
+  double out[19];
+  refill_populations(rho, v, S, G.cfg.omega, out);
+  for (int q = 0; q < 19; ++q) G.fn[q * N + c] = out[q];
 }
 
 // one full step of Algorithm 1 on the plain-FP64 grid

@@ -1,0 +1,187 @@
+"""Pins of the refined-grid oracle (block-structured 2:1 grid, Sec. 4.1-4.2).
+
+What pins it: the single-level layout reproduces the uniform grid bit for
+bit; on multi-level layouts with faces, edges and corners between levels a
+uniform equilibrium is invariant, total mass (volume-weighted) is conserved
+to round-off and total momentum grows by exactly V 2^L F per coarse step; a
+shear wave decays at the analytic rate with the per-level viscosity of
+acoustic scaling; the balanced layouts satisfy 2:1 by brute force; a sphere
+moving with a uniform flow across re-refinements leaves f = f^eq(1, U).
+"""
+import numpy as np
+import pytest
+
+import synth
+
+
+def cfg_of(n0, levels, block, omega=1.6, F=(0.0, 0.0, 0.0)):
+    c = synth.base_config(n0, omega=omega, body_force=F)
+    c["levels"] = levels
+    c["block"] = block
+    return c
+
+
+REGIONS3 = [((4, 4, 4), (9, 8, 12), 2), ((10, 2, 1), (14, 6, 5), 1)]
+REGIONS2 = [((3, 5, 2), (11, 9, 9), 1), ((12, 12, 12), (15, 16, 14), 1)]
+
+
+def volume_totals(ora, R, levels):
+    c, _, _ = ora.lattice()
+    m, J = 0.0, np.zeros(3)
+    for l in range(levels):
+        f, k = R.level(l)
+        sel = k == 1
+        m += f[:, sel].sum() / 8 ** l
+        J += np.einsum("qa,qc->a", c, f[:, sel]) / 8 ** l
+    return m, J
+
+
+def test_single_level_equals_uniform(ora):
+    c = cfg_of((12, 8, 10), 1, 2, omega=1.3, F=(1e-5, 0.0, 2e-5))
+    u0 = synth.velocity_perturbation((12, 8, 10), seed=2)
+    R = ora.Refined(c)
+    R.init(1.0, u0)
+    R.step(7)
+    U = ora.Uniform(c)
+    U.init(1.0, u0)
+    U.step(7)
+    f, _ = R.level(0)
+    assert np.array_equal(f, U.post_collision())
+
+
+@pytest.mark.parametrize("levels,regions", [(2, REGIONS2), (3, REGIONS3)])
+def test_mass_and_momentum_exact(ora, levels, regions):
+    F = np.array([1e-5, -2e-5, 3e-5])
+    c = cfg_of((16, 16, 16), levels, 4, omega=1.7, F=tuple(F))
+    R = ora.Refined(c, regions=regions)
+    R.init(1.0, synth.velocity_perturbation((16, 16, 16), seed=5))
+    leaf = R.leaf()
+    assert leaf.max() == levels - 1 and leaf.min() == 0
+    m0, J0 = volume_totals(ora, R, levels)
+    assert abs(R.mass() - m0) < 1e-11
+    V = 16 ** 3
+    for s in range(1, 5):
+        R.step(1)
+        m, J = volume_totals(ora, R, levels)
+        assert abs(m - m0) < s * V * 1e-15, (s, m - m0)
+        assert np.abs(J - J0 - s * V * 2 ** (levels - 1) * F).max() < s * V * 1e-15
+
+
+def test_equilibrium_invariant(ora):
+    c = cfg_of((16, 16, 16), 3, 4, omega=1.7)
+    R = ora.Refined(c, regions=REGIONS3)
+    U = np.array([0.01, -0.02, 0.005])
+    u = np.broadcast_to(U[:, None, None, None], (3, 16, 16, 16)).copy()
+    R.init(1.02, u)
+    R.step(3)
+    feq = ora.equilibrium(1.02, U)
+    for l in range(3):
+        f, k = R.level(l)
+        sel = k == 1
+        assert sel.sum() > 0
+        assert np.abs(f[:, sel] - feq[:, None]).max() < 1e-15
+
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_shear_wave_decay(ora, levels):
+    """u_x = U sin(2 pi z / Lz) with a refined slab across the wave: the mode
+    amplitude after T coarse steps follows exp(-nu k^2 T), nu of the coarse
+    level from acoustic scaling of the finest omega."""
+    n0, Lz, T, Uamp = (8, 8, 32), 32, 200, 1e-3
+    c = cfg_of(n0, levels, 4, omega=1.2)
+    regs = [((0, 0, 8), (8, 8, 24), levels - 1)] if levels > 1 else []
+    if levels == 3:
+        regs.append(((0, 0, 12), (8, 8, 20), 2))
+    R = ora.Refined(c, regions=regs)
+    R.init(1.0)
+    cv, _, _ = ora.lattice()
+    for l in range(levels):
+        nx, ny, nz = R.dims(l)
+        z = (np.arange(nz) + 0.5) / 2 ** l
+        u = np.zeros((3, nz, ny, nx))
+        u[0] = Uamp * np.sin(2 * np.pi * z / Lz)[:, None, None]
+        R.set_level_velocity(l, 1.0, u)
+    R.step(T)
+    amp = 0.0
+    for l in range(levels):
+        f, k = R.level(l)
+        nx, ny, nz = R.dims(l)
+        z = (np.arange(nz) + 0.5) / 2 ** l
+        jx = np.einsum("q,qzyx->zyx", cv[:, 0].astype(float), f)
+        amp += (jx * np.sin(2 * np.pi * z / Lz)[:, None, None] * (k == 1)).sum() / 8 ** l
+    amp /= n0[0] * n0[1] * n0[2] / 2 * Uamp
+    tau_c = (1 / 1.2 - 0.5) / 2 ** (levels - 1) + 0.5
+    nu = (tau_c - 0.5) / 3
+    exact = np.exp(-nu * (2 * np.pi / Lz) ** 2 * T)
+    assert abs(amp / exact - 1) < 3e-3, (amp, exact)
+
+
+def two_to_one_ok(leaf):
+    nz, ny, nx = leaf.shape
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                l = leaf[k, j, i]
+                for dz in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            if abs(leaf[(k + dz) % nz, (j + dy) % ny, (i + dx) % nx] - l) > 1:
+                                return False
+    return True
+
+
+def octree_ok(leaf, L):
+    """Every leaf of level l covers an aligned cube of 2^(L-l) positions."""
+    nz, ny, nx = leaf.shape
+    for k in range(nz):
+        for j in range(ny):
+            for i in range(nx):
+                s = 2 ** (L - leaf[k, j, i])
+                k0, j0, i0 = (k // s) * s, (j // s) * s, (i // s) * s
+                if not (leaf[k0:k0 + s, j0:j0 + s, i0:i0 + s] == leaf[k, j, i]).all():
+                    return False
+    return True
+
+
+def test_balance_random_targets(ora):
+    rng = np.random.default_rng(3)
+    for trial in range(4):
+        c = cfg_of((16, 16, 16), 4, 8)
+        regs = []
+        for _ in range(3):
+            lo = rng.integers(0, 14, 3)
+            hi = lo + rng.integers(1, 3, 3)
+            regs.append((tuple(lo), tuple(hi), int(rng.integers(1, 4))))
+        R = ora.Refined(c, regions=regs)
+        R.init()
+        leaf = R.leaf()
+        assert leaf.max() == max(r[2] for r in regs)
+        assert two_to_one_ok(leaf)
+        assert octree_ok(leaf, 3)
+
+
+def test_comoving_sphere_across_rerefinement(ora):
+    """A heavy sphere translating with a uniform flow moves across block
+    boundaries; the layout follows it (blocks near the sphere on the finest
+    level), data is moved between levels, cells are re-mapped and refilled:
+    every level must stay at f^eq(1, U) and the sphere must not accelerate."""
+    U = np.array([0.0, 0.0, 0.06])
+    c = cfg_of((8, 8, 48), 3, 4, omega=1.5)
+    s = synth.sphere((16.3, 15.7, 40.0), 3.5, density_ratio=1e9, fixed=False, u=tuple(U))
+    R = ora.Refined(c, spheres=[s], check_every=1)
+    u = np.broadcast_to(U[:, None, None, None], (3, 48, 8, 8)).copy()
+    R.init(1.0, u)
+    leaf0 = R.leaf()
+    R.step(40)
+    _, _, nref = R.counters()
+    assert nref >= 1
+    assert not np.array_equal(R.leaf(), leaf0)
+    feq = ora.equilibrium(1.0, U)
+    for l in range(3):
+        f, k = R.level(l)
+        sel = (k == 1) & (np.abs(f).sum(axis=0) > 0)
+        assert sel.sum() > 0
+        assert np.abs(f[:, sel] - feq[:, None]).max() < 2e-14
+    x, uu, _ = R.particle(0)
+    assert np.abs(uu - U).max() < 1e-13
+    assert abs(x[2] - (40.0 + 40 * 4 * 0.06)) < 1e-9
