@@ -86,6 +86,10 @@ int vmlbm_create(const vmlbm_config* cfg, vmlbm_ctx** out);
  * its index.  Spheres must lie at least 3 cells apart. */
 int vmlbm_add_sphere(vmlbm_ctx* ctx, const vmlbm_sphere* s, int* id);
 
+/* Block-structured grid: hold the blocks intersecting the coarse-cell box
+ * [lo, hi) at level >= `level` (Sec. 4.2), before the workspace is bound. */
+int vmlbm_add_refine_region(vmlbm_ctx* ctx, const int lo[3], const int hi[3], int level);
+
 /* Device workspace size in bytes for the current configuration and spheres. */
 int vmlbm_required_bytes(const vmlbm_ctx* ctx, size_t* bytes);
 

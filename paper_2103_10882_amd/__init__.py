@@ -20,7 +20,7 @@ BYTES = {F64: 8, F32: 4, F16: 2}
 ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EUNSTABLE", -6: "ERANGE"}
 
 EXPORTS = [
-    "vmlbm_create", "vmlbm_add_sphere", "vmlbm_required_bytes", "vmlbm_bind_workspace",
+    "vmlbm_create", "vmlbm_add_sphere", "vmlbm_add_refine_region", "vmlbm_required_bytes", "vmlbm_bind_workspace",
     "vmlbm_set_stream", "vmlbm_init_equilibrium", "vmlbm_step", "vmlbm_sync", "vmlbm_get_particle",
     "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
@@ -64,6 +64,7 @@ def lib():
         sig = {
             "vmlbm_create": [ctypes.POINTER(Config), ctypes.POINTER(vp)],
             "vmlbm_add_sphere": [vp, ctypes.POINTER(Sphere), ctypes.POINTER(ctypes.c_int)],
+            "vmlbm_add_refine_region": [vp, vp, vp, ctypes.c_int],
             "vmlbm_required_bytes": [vp, ctypes.POINTER(ctypes.c_size_t)],
             "vmlbm_bind_workspace": [vp, vp, ctypes.c_size_t],
             "vmlbm_set_stream": [vp, vp],
@@ -141,11 +142,13 @@ class Sim:
     """One simulation context on the current CUDA (HIP) device."""
 
     def __init__(self, cfg, spheres=(), storage="f64", history=4, adjoint_steps=0, ckpt_every=0,
-                 device="cuda"):
+                 device="cuda", regions=(), check_every=None):
         import torch
         self.L = lib()
         self.cfg = cfg
         self._c = make_config(cfg, storage, history, adjoint_steps, ckpt_every)
+        if check_every is not None:
+            self._c.check_every = int(check_every)
         self.h = ctypes.c_void_p()
         self._check(self.L.vmlbm_create(ctypes.byref(self._c), ctypes.byref(self.h)), "create")
         for s in spheres:
@@ -153,6 +156,10 @@ class Sim:
             i = ctypes.c_int()
             self._check(self.L.vmlbm_add_sphere(self.h, ctypes.byref(o), ctypes.byref(i)), "add_sphere")
         self.nsph = len(spheres)
+        for lo, hi, lev in regions:
+            lo = np.ascontiguousarray(lo, dtype=np.int32)
+            hi = np.ascontiguousarray(hi, dtype=np.int32)
+            self._check(self.L.vmlbm_add_refine_region(self.h, _ptr(lo), _ptr(hi), int(lev)), "add_refine_region")
         nb = ctypes.c_size_t()
         self._check(self.L.vmlbm_required_bytes(self.h, ctypes.byref(nb)), "required_bytes")
         self.ws_bytes = nb.value

@@ -102,6 +102,7 @@ int refine_read_owner(vmlbm_ctx* c, int level, int* out);
 int refine_level_cells(vmlbm_ctx* c, int level, size_t* cells);
 int refine_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* interior);
 void refine_destroy(vmlbm_ctx* c);
+int refine_add_region(vmlbm_ctx* c, const int lo[3], const int hi[3], int level);
 // body force of a level in that level's lattice units
 void level_force(const vmlbm_ctx* c, int level, double F[3]);
 }  // namespace vm

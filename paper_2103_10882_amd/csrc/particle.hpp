@@ -1,0 +1,331 @@
+// Particle coupling kernels shared by the uniform grid and the finest level
+// of the block-structured grid, written against an addressing policy
+// (UAddr / BAddr): the pull of a cell with its wall and particle links, the
+// per-sphere box pass, mapping, re-mapping and refill.
+#pragma once
+
+#include "common.hpp"
+#include "uniform.hpp"
+#include "stencil.hpp"
+
+namespace vm {
+
+// Slow path for a fluid cell with wall or particle links: builds the 19
+// incoming populations with Eq. 10 (CLI) on particle links and halfway
+// bounce-back on walls, and accumulates the link forces of Eq. 11 and their
+// torques (Eq. 12) in FP64.  The constant part 2 w_q c_q of each link force
+// is left out: summed over the closed surface of a body it vanishes exactly
+// (every lattice line enters and leaves the body equally often), and so does
+// its torque (entry and exit points of a line differ by a multiple of c_q).
+template <typename S, typename A>
+__device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restrict__ flags,
+                              const uint16_t* __restrict__ owner, const DevParticle* __restrict__ parts,
+                              const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
+                              typename Store<S>::T (&d)[kQ], int& pid, double (&Fl)[3], double (&Tl)[3],
+                              int* __restrict__ status, uint32_t* link_mask = nullptr,
+                              typename Store<S>::T* kappa_out = nullptr) {
+  using T = typename Store<S>::T;
+  const uint32_t N = ad.N;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  // pass 1: pull source of every direction and its flag, loads issued together
+  uint32_t sidx[kQ];
+  int8_t wall[kQ];          // -1: inside the domain, else 2*axis + side of the wall crossed
+  uint8_t sfl[kQ];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    int wa = 0, ws = 0;
+    sidx[q] = c;
+    const int st = ad.locate(x - cx_of(q), y - cy_of(q), z - cz_of(q), sidx[q], wa, ws);
+    wall[q] = st == 0 ? (int8_t)(2 * wa + ws) : (int8_t)-1;
+    if (st < 0) { status[kStatusRange] = 5; sidx[q] = c; }
+  }
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;
+  // pass 2: plain streaming where the source is fluid
+  d[0] = Store<S>::load(src[c]);
+#pragma unroll
+  for (int q = 1; q < kQ; ++q)
+    if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = Store<S>::load(src[(size_t)q * N + sidx[q]]);
+  // pass 3: links
+  if (link_mask) *link_mask = 0;
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    if (kappa_out) kappa_out[q] = T(0);
+    if (wall[q] < 0 && !(sfl[q] & kSolid)) continue;
+    if (link_mask) *link_mask |= 1u << q;
+    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+    const int qq = opp_of(q);
+    const double w = w_of(q);
+    const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
+    if (wall[q] >= 0) {
+      // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
+      const int wa = wall[q] >> 1, ws = wall[q] & 1;
+      double cv = 0.0;
+      if (wa == p.wall_axis)
+        cv = -(cq[0] * p.wall_v[ws][0] + cq[1] * p.wall_v[ws][1] + cq[2] * p.wall_v[ws][2]);
+      d[q] = own_qq - T(6.0 * w * cv);
+      continue;
+    }
+    // particle link in direction qq (c_qq = -c_q points into the solid)
+    const int pi = owner[sidx[q]];
+    const DevParticle& P = parts[pi];
+    double off[3];
+    sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
+    const double delta = ray_delta(off, -cq[0], -cq[1], -cq[2], P.r);
+    double rb[3] = {off[0] - delta * cq[0], off[1] - delta * cq[1], off[2] - delta * cq[2]};
+    double v[3] = {P.u[0] + (P.w[1] * rb[2] - P.w[2] * rb[1]),
+                   P.u[1] + (P.w[2] * rb[0] - P.w[0] * rb[2]),
+                   P.u[2] + (P.w[0] * rb[1] - P.w[1] * rb[0])};
+    double kappa = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
+    double alpha = 4.0 / (1.0 + 2.0 * delta);
+    // second node x - c_qq = x + c_q
+    uint32_t tidx = 0;
+    int wa2 = 0, ws2 = 0;
+    bool second_ok = ad.locate(x + cq[0], y + cq[1], z + cq[2], tidx, wa2, ws2) == 1;
+    if (second_ok && (flags[tidx] & kSolid)) second_ok = false;
+    if (!second_ok) { kappa = 0.0; alpha = 2.0; }
+    if (kappa_out) kappa_out[q] = T(kappa);
+    // c_qq . v with c_qq = -c_q
+    const double cqv = -(cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2]);
+    T val = own_qq - T(3.0 * alpha * w * cqv);
+    if (second_ok) {
+      const T sec = Store<S>::load(src[(size_t)qq * N + tidx]);
+      const T own_q = Store<S>::load(src[(size_t)q * N + c]);
+      val = val + T(kappa) * (sec - own_q);
+    }
+    d[q] = val;
+    // link force: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
+    const double a0 = (double)own_qq, a1 = (double)val;
+    double Fq[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Fq[a] = (-cq[a] - v[a]) * a0 + (-cq[a] + v[a]) * a1;
+    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
+    pid = pi;
+    Fl[0] += Fq[0]; Fl[1] += Fq[1]; Fl[2] += Fq[2];
+    Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
+    Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
+    Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
+  }
+}
+
+
+// cell k of a box of edge `edge` at origin lo -> lattice coordinates (periodic
+// axes wrapped); false if it lies outside the domain
+__device__ __forceinline__ bool box_cell(const int* lo, int k, int edge, const SweepParams& p, int& x, int& y,
+                                         int& z) {
+  const int i = k % edge, j = (k / edge) % edge, l = k / (edge * edge);
+  int s[3] = {lo[0] + i, lo[1] + j, lo[2] + l};
+  const int n[3] = {p.nx, p.ny, p.nz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (p.per[a]) s[a] = ((s[a] % n[a]) + n[a]) % n[a];
+    else if (s[a] < 0 || s[a] >= n[a]) return false;
+  }
+  x = s[0]; y = s[1]; z = s[2];
+  return true;
+}
+
+// Particle-link cells: one grid row per sphere over its box; a cell is
+// handled in the pass of the sphere it links to (owner array).  Every wave
+// writes its FP64 partial force/torque (zero if it holds no link) to its own
+// slot, so the per-sphere reduction reads a fixed set in a fixed order.
+template <typename S, typename A>
+__global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict__ src, S* __restrict__ dst,
+                                                            const uint8_t* __restrict__ flags,
+                                                            const uint16_t* __restrict__ owner,
+                                                            const DevParticle* __restrict__ parts,
+                                                            double* __restrict__ slots, int* __restrict__ status,
+                                                            SweepParams p, A ad) {
+  using T = typename Store<S>::T;
+  const int pi = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int edge = p.box;
+  int x = 0, y = 0, z = 0, wa = 0, ws = 0;
+  uint32_t c = 0;
+  bool active = k < edge * edge * edge && box_cell(parts[pi].box_lo, k, edge, p, x, y, z) &&
+                ad.locate(x, y, z, c, wa, ws) == 1;
+  if (active) active = (flags[c] & kNearP) && owner[c] == pi;
+  int pid = -1;
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  if (active) {
+    T d[kQ];
+    boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status);
+    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
+    const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+    if (!(drho == drho)) status[kStatusUnstable] = 1;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * ad.N + c] = Store<S>::store(d[q]);
+  }
+  double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
+  if ((threadIdx.x & 63) == 0) {
+    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(k >> 6) * 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) o[j] = v[j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// mapping (Sec. 2.3): a cell is solid for the first sphere whose centre lies
+// within r of its centre; a fluid cell next to a solid one carries the
+// particle-link flag and the id of that sphere, one next to a wall the
+// wall-link flag
+// ---------------------------------------------------------------------------
+__device__ inline int cell_owner(int x, int y, int z, const DevParticle* __restrict__ parts, int np,
+                                 const SweepParams& p) {
+  for (int i = 0; i < np; ++i) {
+    double off[3];
+    sphere_offset(parts[i].x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
+    if (inside_sphere(off, parts[i].r)) return i;
+  }
+  return -1;
+}
+
+template <typename A>
+__device__ void map_cell(int x, int y, int z, uint32_t c, uint8_t* __restrict__ flags,
+                         uint16_t* __restrict__ owner, const DevParticle* __restrict__ parts, int np,
+                         const SweepParams& p, const A& ad, int* __restrict__ status) {
+  const int o = cell_owner(x, y, z, parts, np, p);
+  uint8_t f = 0;
+  int link = -1;
+  if (o >= 0) {
+    f = kSolid;
+    link = o;
+  } else {
+    for (int q = 1; q < kQ; ++q) {
+      uint32_t sc = 0;
+      int wa = 0, ws = 0;
+      const int st = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws);
+      if (st == 0) { f |= kNearW; continue; }
+      if (st < 0) continue;
+      const int so = cell_owner(x + cx_of(q), y + cy_of(q), z + cz_of(q), parts, np, p);
+      if (so >= 0) {
+        if (link >= 0 && link != so) status[kStatusRange] = 4;
+        if (link < 0) link = so;
+        f |= kNearP;
+      }
+    }
+  }
+  flags[c] = f;
+  owner[c] = link < 0 ? 0 : (uint16_t)link;
+}
+
+template <typename A>
+__global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
+                                               const DevParticle* __restrict__ parts, int np, SweepParams p,
+                                               A ad, int* __restrict__ status) {
+  const int pi = blockIdx.y;
+  const DevParticle& P = parts[pi];
+  if (P.fixed) return;
+  const int rb = p.box + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= rb * rb * rb) return;
+  int x, y, z, wa = 0, ws = 0;
+  uint32_t c = 0;
+  if (!box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1) return;
+  map_cell<A>(x, y, z, c, flags, owner, parts, np, p, ad, status);
+}
+
+// ---------------------------------------------------------------------------
+// refill of cells uncovered by a moving sphere (Sec. 2.3, after Dorschner):
+// rho = mean density of the D3Q19 neighbours that held fluid before the
+// re-mapping; v = rigid-body velocity; strain rate S from central differences
+// over the axis neighbours (fluid velocity where the neighbour held fluid,
+// rigid-body velocity of its sphere or the wall velocity otherwise);
+// f = f^eq(rho, v) - 3 w_q / s+ (c c - I/3) : S, then collided.  Runs before
+// the flags are updated, so flags/owner still describe the old mapping.
+// ---------------------------------------------------------------------------
+template <typename S, typename A>
+__global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uint8_t* __restrict__ flags,
+                                                const uint16_t* __restrict__ owner,
+                                                const DevParticle* __restrict__ parts, int np, SweepParams p,
+                                                A ad, int* __restrict__ status) {
+  using T = typename Store<S>::T;
+  const int pi = blockIdx.y;
+  const DevParticle& P = parts[pi];
+  if (P.fixed) return;
+  const int rb = p.box + 1;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= rb * rb * rb) return;
+  int x, y, z, wa = 0, ws = 0;
+  uint32_t c = 0;
+  if (!box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1) return;
+  const uint32_t N = ad.N;
+  if (!(flags[c] & kSolid) || owner[c] != pi) return;
+  if (cell_owner(x, y, z, parts, np, p) >= 0) return;   // still covered
+  // density from old-fluid neighbours
+  double rsum = 0.0;
+  int cnt = 0;
+  for (int q = 1; q < kQ; ++q) {
+    uint32_t sc = 0;
+    if (ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws) != 1) continue;
+    if (flags[sc] & kSolid) continue;
+    double r = 0.0;
+    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + sc]);
+    rsum += 1.0 + r;
+    ++cnt;
+  }
+  const double rho = cnt ? rsum / cnt : 1.0;
+  double off[3];
+  sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
+  const double v[3] = {P.u[0] + (P.w[1] * off[2] - P.w[2] * off[1]),
+                       P.u[1] + (P.w[2] * off[0] - P.w[0] * off[2]),
+                       P.u[2] + (P.w[0] * off[1] - P.w[1] * off[0])};
+  // velocity at the six axis neighbours
+  double Vn[3][2][3];
+  for (int a = 0; a < 3; ++a)
+    for (int side = 0; side < 2; ++side) {
+      int s[3] = {x, y, z};
+      s[a] += side ? 1 : -1;
+      double* V = Vn[a][side];
+      uint32_t sc = 0;
+      int wa2 = 0, ws2 = 0;
+      const int st = ad.locate(s[0], s[1], s[2], sc, wa2, ws2);
+      if (st == 0) {
+        for (int b = 0; b < 3; ++b) V[b] = (wa2 == p.wall_axis) ? p.wall_v[ws2][b] : 0.0;
+        continue;
+      }
+      if (st < 0) {
+        status[kStatusRange] = 5;
+        for (int b = 0; b < 3; ++b) V[b] = v[b];
+        continue;
+      }
+      if (!(flags[sc] & kSolid)) {
+        double j[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < kQ; ++q) {
+          const double dq = (double)Store<S>::load(state[(size_t)q * N + sc]);
+          j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
+        }
+        // post-collision momentum minus F/2 is the macroscopic velocity
+        for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
+      } else {
+        const DevParticle& Q = parts[owner[sc]];
+        double o2[3];
+        sphere_offset(Q.x, s[0] + 0.5, s[1] + 0.5, s[2] + 0.5, p.nx, p.ny, p.nz, p.per, o2);
+        V[0] = Q.u[0] + (Q.w[1] * o2[2] - Q.w[2] * o2[1]);
+        V[1] = Q.u[1] + (Q.w[2] * o2[0] - Q.w[0] * o2[2]);
+        V[2] = Q.u[2] + (Q.w[0] * o2[1] - Q.w[1] * o2[0]);
+      }
+    }
+  double Sab[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      Sab[a][b] = 0.25 * ((Vn[a][1][b] - Vn[a][0][b]) + (Vn[b][1][a] - Vn[b][0][a]));
+  const double trS = Sab[0][0] + Sab[1][1] + Sab[2][2];
+  const double usq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  T d[kQ];
+  for (int q = 0; q < kQ; ++q) {
+    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+    const double cu = cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2];
+    double QS = -trS / 3.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) QS += cq[a] * cq[b] * Sab[a][b];
+    const double w = w_of(q);
+    d[q] = T(w * (rho - 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) - 3.0 * w / p.sp * QS);
+  }
+  trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store(d[q]);
+}
+
+}  // namespace vm

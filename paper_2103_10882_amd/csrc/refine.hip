@@ -1,22 +1,1132 @@
-// Block-structured 2:1 refined grid (Sec. 4.1-4.2): not built yet.
+// Block-structured 2:1 refined grid (Sec. 4.1-4.2) with sub-cycled levels.
+//
+// Every level stores 16^3-cell blocks in slots, populations SoA
+// [q][slot][16][16][16] (post-collision deviations, storage type S), two
+// buffers per level.  Level l holds its leaf blocks ("interior") and ghost
+// blocks: block positions of level l inside level-(l-1) leaves next to a
+// level-l leaf; their cells within two level-l cells of the level-l region
+// form the ghost band.  Per coarse step, Step(l):
+//   explode level l into the ghost blocks of l+1 (each fine cell copies its
+//   parent's 19 populations); Step(l+1) twice; then the level-l sweep:
+//   interior cells pull and collide (omega_l from acoustic scaling), ghost
+//   cells stream only; cells next to the finer region take the coalescence
+//   pull from a precomputed table: the coarse source keeps the fraction
+//   (1 - n_in/8) that did not cut into the finer region, and the fine
+//   populations that left the finer region into the ghost cells of the cell
+//   are added with weight 1/8.
+// The particle lives on the finest level; its coupling runs the same kernels
+// as on the uniform grid through block addressing (BAddr).  Blocks near the
+// particle are held on the finest level; the layout is re-checked every
+// check_every coarse steps and data moves between levels by copying a cell to
+// its children or averaging them.  Domains are periodic.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.hpp"
+#include "uniform.hpp"
+#include "stencil.hpp"
+#include "particle.hpp"
 #include "context.hpp"
 
 namespace vm {
 
-struct Forest {};
+namespace {
+
+constexpr uint8_t kIface = 0x10;   // interior cell with a coalescence pull
+
+struct IfaceEntry {
+  int slot, local;      // the coarse cell
+  int fine_slot;        // level-(l+1) slot holding its 8 children (-1 if unused)
+  int fine_local;       // local index of child (0,0,0)
+  float weight[kQ];     // weight of the plain pull from the coarse source
+  uint8_t mask[kQ];     // children whose value is added with weight 1/8
+  uint8_t pad[1];
+};
+
+struct LevelParams {
+  double sp, sm, F[3];
+};
+
+}  // namespace
+
+struct Forest {
+  int L = 0;
+  int nb0[3] = {0, 0, 0};     // coarse block positions
+  int nbL[3] = {0, 0, 0};     // finest block positions
+  std::vector<int8_t> leaf, base;
+  int refinements = 0;
+  long long coarse_steps = 0;
+  struct Lev {
+    int n[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
+    long npos = 0;
+    int cap = 0, iface_cap = 0;
+    std::vector<int> slot_of;         // per block position: slot, -1 coarser, -2 finer
+    std::vector<int> interior, ghost; // slot lists
+    std::vector<int> pos;             // per slot: x, y, z block position
+    std::vector<int> explode;         // per ghost slot: ghost slot, parent slot, ox, oy, oz
+    std::vector<IfaceEntry> iface;
+    LevelParams lp{};
+    // device
+    size_t off_pdf[2] = {0, 0}, off_flags = 0, off_slot_of[2] = {0, 0}, off_pos = 0, off_int = 0, off_ghost = 0,
+           off_explode = 0, off_iface = 0;
+    int cur = 0, tab = 0;
+    int n_int = 0, n_ghost = 0, n_iface = 0;
+  };
+  std::vector<Lev> lv;
+  size_t off_owner = 0, off_leaf[2] = {0, 0};
+  int leaf_tab = 0;
+  int wrap(int v, int n) const { return ((v % n) + n) % n; }
+  long lpos(int i, int j, int k) const { return ((long)k * nbL[1] + j) * nbL[0] + i; }
+  // leaf level of the region holding level-l block position (bi, bj, bk)
+  int leaf_block(const std::vector<int8_t>& lf, int l, int bi, int bj, int bk) const {
+    const Lev& V = lv[l];
+    bi = wrap(bi, V.nb[0]); bj = wrap(bj, V.nb[1]); bk = wrap(bk, V.nb[2]);
+    const int s = L - l;
+    return lf[lpos(bi << s, bj << s, bk << s)];
+  }
+  // leaf level of the region holding level-l cell (i, j, k)
+  int leaf_cell(const std::vector<int8_t>& lf, int l, int i, int j, int k) const {
+    return leaf_block(lf, l, wrap(i, lv[l].n[0]) >> 4, wrap(j, lv[l].n[1]) >> 4, wrap(k, lv[l].n[2]) >> 4);
+  }
+};
+
+namespace {
+
+enum CellKind { K_INTERIOR, K_GHOST, K_COARSER, K_FINER };
+
+int cell_kind(const Forest& f, int l, int i, int j, int k) {
+  const int lf = f.leaf_cell(f.leaf, l, i, j, k);
+  if (lf == l) return K_INTERIOR;
+  if (lf > l) return K_FINER;
+  if (l >= 1 && lf == l - 1) {
+    const int pi = f.wrap(i, f.lv[l].n[0]) >> 1, pj = f.wrap(j, f.lv[l].n[1]) >> 1,
+              pk = f.wrap(k, f.lv[l].n[2]) >> 1;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx)
+          if (f.leaf_cell(f.leaf, l - 1, pi + dx, pj + dy, pk + dz) == l) return K_GHOST;
+  }
+  return K_COARSER;
+}
+
+// Leaf level per finest block position from targets: a node of level l is
+// split when any target inside exceeds l; nodes whose 26 neighbours hold
+// leaves more than one level finer are split too, until nothing changes.
+std::vector<int8_t> balance_layout(const Forest& f, std::vector<int8_t> t) {
+  const int L = f.L;
+  const long NB = (long)f.nbL[0] * f.nbL[1] * f.nbL[2];
+  std::vector<int8_t> lf(NB, 0);
+  // pyramid of maxima: level-l node (edge 2^(L-l) positions)
+  auto node_dims = [&](int l, int d[3]) { for (int a = 0; a < 3; ++a) d[a] = f.nbL[a] >> (L - l); };
+  std::vector<std::vector<int8_t>> mx(L + 1);
+  for (int iter = 0; iter < 64; ++iter) {
+    mx[L] = t;
+    for (int l = L - 1; l >= 0; --l) {
+      int d[3], e[3];
+      node_dims(l, d);
+      node_dims(l + 1, e);
+      mx[l].assign((long)d[0] * d[1] * d[2], 0);
+      for (int k = 0; k < e[2]; ++k)
+        for (int j = 0; j < e[1]; ++j)
+          for (int i = 0; i < e[0]; ++i) {
+            int8_t& m = mx[l][((long)(k >> 1) * d[1] + (j >> 1)) * d[0] + (i >> 1)];
+            m = std::max(m, mx[l + 1][((long)k * e[1] + j) * e[0] + i]);
+          }
+    }
+    // leaf of a position: first level whose node holds no target beyond it
+    for (int k = 0; k < f.nbL[2]; ++k)
+      for (int j = 0; j < f.nbL[1]; ++j)
+        for (int i = 0; i < f.nbL[0]; ++i) {
+          int l = 0;
+          while (l < L) {
+            int d[3];
+            node_dims(l, d);
+            const int s = L - l;
+            if (mx[l][((long)(k >> s) * d[1] + (j >> s)) * d[0] + (i >> s)] <= l) break;
+            ++l;
+          }
+          lf[f.lpos(i, j, k)] = (int8_t)l;
+        }
+    // 2:1 over the 26 neighbours of every leaf node, with a pyramid of the
+    // finest leaf level inside each node
+    std::vector<std::vector<int8_t>> lm(L + 1);
+    lm[L] = lf;
+    for (int l = L - 1; l >= 0; --l) {
+      int d[3], e[3];
+      node_dims(l, d);
+      node_dims(l + 1, e);
+      lm[l].assign((long)d[0] * d[1] * d[2], 0);
+      for (int k = 0; k < e[2]; ++k)
+        for (int j = 0; j < e[1]; ++j)
+          for (int i = 0; i < e[0]; ++i) {
+            int8_t& m = lm[l][((long)(k >> 1) * d[1] + (j >> 1)) * d[0] + (i >> 1)];
+            m = std::max(m, lm[l + 1][((long)k * e[1] + j) * e[0] + i]);
+          }
+    }
+    bool changed = false;
+    for (int k = 0; k < f.nbL[2]; ++k)
+      for (int j = 0; j < f.nbL[1]; ++j)
+        for (int i = 0; i < f.nbL[0]; ++i) {
+          const int l = lf[f.lpos(i, j, k)];
+          const int s = L - l;
+          if ((i & ((1 << s) - 1)) || (j & ((1 << s) - 1)) || (k & ((1 << s) - 1))) continue;  // node origin only
+          int d[3];
+          node_dims(l, d);
+          int m = 0;
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                if (!dx && !dy && !dz) continue;
+                const int ni = f.wrap((i >> s) + dx, d[0]), nj = f.wrap((j >> s) + dy, d[1]),
+                          nk = f.wrap((k >> s) + dz, d[2]);
+                m = std::max(m, (int)lm[l][((long)nk * d[1] + nj) * d[0] + ni]);
+              }
+          if (m > l + 1) {
+            const int S = 1 << s;
+            for (int c = 0; c < S; ++c)
+              for (int bb = 0; bb < S; ++bb)
+                for (int a = 0; a < S; ++a) {
+                  int8_t& tv = t[f.lpos(i + a, j + bb, k + c)];
+                  if (tv < m - 1) { tv = (int8_t)(m - 1); changed = true; }
+                }
+          }
+        }
+    if (!changed) return lf;
+  }
+  return lf;
+}
+
+std::vector<int8_t> layout_targets(const vmlbm_ctx* c, const Forest& f, const std::vector<vmlbm_sphere>& sph) {
+  std::vector<int8_t> t = f.base;
+  const int b = kBlock;
+  for (const auto& s : sph) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = (int)std::floor((s.x[a] - s.radius - b) / b);
+      hi[a] = (int)std::floor((s.x[a] + s.radius + b) / b);
+    }
+    for (int k = lo[2]; k <= hi[2]; ++k)
+      for (int j = lo[1]; j <= hi[1]; ++j)
+        for (int i = lo[0]; i <= hi[0]; ++i)
+          t[f.lpos(f.wrap(i, f.nbL[0]), f.wrap(j, f.nbL[1]), f.wrap(k, f.nbL[2]))] = (int8_t)f.L;
+  }
+  (void)c;
+  return t;
+}
+
+// slot lists, ghost blocks, explosion map and coalescence table of every
+// level for the current leaf field
+int build_tables(vmlbm_ctx* c, Forest& f) {
+  const int L = f.L;
+  for (int l = 0; l <= L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    V.slot_of.assign(V.npos, -1);
+    V.interior.clear();
+    V.ghost.clear();
+    V.pos.clear();
+    std::vector<int> gpos;
+    for (int k = 0; k < V.nb[2]; ++k)
+      for (int j = 0; j < V.nb[1]; ++j)
+        for (int i = 0; i < V.nb[0]; ++i) {
+          const long p = ((long)k * V.nb[1] + j) * V.nb[0] + i;
+          const int lf = f.leaf_block(f.leaf, l, i, j, k);
+          if (lf == l) {
+            V.slot_of[p] = (int)V.interior.size();
+            V.interior.push_back(V.slot_of[p]);
+            V.pos.insert(V.pos.end(), {i, j, k});
+          } else if (lf > l) {
+            V.slot_of[p] = -2;
+          } else if (l >= 1 && lf == l - 1) {
+            bool g = false;
+            for (int dz = -1; dz <= 1 && !g; ++dz)
+              for (int dy = -1; dy <= 1 && !g; ++dy)
+                for (int dx = -1; dx <= 1 && !g; ++dx)
+                  if (f.leaf_block(f.leaf, l, i + dx, j + dy, k + dz) == l) g = true;
+            if (g) gpos.insert(gpos.end(), {i, j, k});
+          }
+        }
+    for (size_t g = 0; g < gpos.size(); g += 3) {
+      const int s = (int)(V.pos.size() / 3);
+      V.slot_of[((long)gpos[g + 2] * V.nb[1] + gpos[g + 1]) * V.nb[0] + gpos[g]] = s;
+      V.ghost.push_back(s);
+      V.pos.insert(V.pos.end(), {gpos[g], gpos[g + 1], gpos[g + 2]});
+    }
+    const int nslots = (int)(V.pos.size() / 3);
+    if (V.cap && nslots > V.cap)
+      return fail(c, VMLBM_ERANGE, "level %d needs %d block slots, capacity %d", l, nslots, V.cap);
+  }
+  // explosion: ghost block of level l+1 -> parent interior block of level l
+  for (int l = 1; l <= L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    const Forest::Lev& P = f.lv[l - 1];
+    V.explode.clear();
+    for (int g : V.ghost) {
+      const int bi = V.pos[3 * g], bj = V.pos[3 * g + 1], bk = V.pos[3 * g + 2];
+      const long pp = ((long)(bk >> 1) * P.nb[1] + (bj >> 1)) * P.nb[0] + (bi >> 1);
+      const int ps = P.slot_of[pp];
+      if (ps < 0 || ps >= (int)P.interior.size())
+        return fail(c, VMLBM_ERANGE, "ghost block of level %d without an interior parent", l);
+      V.explode.insert(V.explode.end(), {g, ps, (bi & 1) * 8, (bj & 1) * 8, (bk & 1) * 8});
+    }
+  }
+  // coalescence table: interior cells of level l within two cells of the
+  // level-(l+1) region whose pull differs from plain streaming
+  for (int l = 0; l < L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    const Forest::Lev& Fl = f.lv[l + 1];
+    V.iface.clear();
+    for (int s : V.interior) {
+      const int bi = V.pos[3 * s], bj = V.pos[3 * s + 1], bk = V.pos[3 * s + 2];
+      bool near = false;
+      for (int dz = -1; dz <= 1 && !near; ++dz)
+        for (int dy = -1; dy <= 1 && !near; ++dy)
+          for (int dx = -1; dx <= 1 && !near; ++dx)
+            if (f.leaf_block(f.leaf, l, bi + dx, bj + dy, bk + dz) > l) near = true;
+      if (!near) continue;
+      for (int lz = 0; lz < kBlock; ++lz)
+        for (int ly = 0; ly < kBlock; ++ly)
+          for (int lx = 0; lx < kBlock; ++lx) {
+            const int i = bi * kBlock + lx, j = bj * kBlock + ly, k = bk * kBlock + lz;
+            bool cand = false;
+            for (int dz = -2; dz <= 2 && !cand; ++dz)
+              for (int dy = -2; dy <= 2 && !cand; ++dy)
+                for (int dx = -2; dx <= 2 && !cand; ++dx)
+                  if (f.leaf_cell(f.leaf, l, i + dx, j + dy, k + dz) > l) cand = true;
+            if (!cand) continue;
+            IfaceEntry e{};
+            bool special = false;
+            for (int q = 0; q < kQ; ++q) {
+              const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+              const int si = i - cq[0], sj = j - cq[1], sk = k - cq[2];
+              const int ks = cell_kind(f, l, si, sj, sk);
+              float wgt = 1.0f;
+              if (ks == K_INTERIOR) {
+                int nin = 0;
+                for (int m = 0; m < 8; ++m) {
+                  const int gi = 2 * si + (m & 1), gj = 2 * sj + ((m >> 1) & 1), gk = 2 * sk + (m >> 2);
+                  if (cell_kind(f, l + 1, gi + cq[0], gj + cq[1], gk + cq[2]) == K_INTERIOR) ++nin;
+                }
+                wgt = 1.0f - nin / 8.0f;
+              } else if (ks == K_FINER) {
+                wgt = 0.0f;
+              } else if (ks == K_COARSER) {
+                return fail(c, VMLBM_ERANGE, "level %d cell pulls from an uncovered coarser cell", l);
+              }
+              uint8_t mask = 0;
+              for (int m = 0; m < 8; ++m) {
+                const int gi = 2 * i + (m & 1), gj = 2 * j + ((m >> 1) & 1), gk = 2 * k + (m >> 2);
+                if (cell_kind(f, l + 1, gi, gj, gk) != K_GHOST) continue;
+                const int k1 = cell_kind(f, l + 1, gi - cq[0], gj - cq[1], gk - cq[2]);
+                const int k2 = cell_kind(f, l + 1, gi - 2 * cq[0], gj - 2 * cq[1], gk - 2 * cq[2]);
+                if (k1 == K_INTERIOR || (k1 == K_GHOST && k2 == K_INTERIOR)) mask |= (uint8_t)(1u << m);
+              }
+              e.weight[q] = wgt;
+              e.mask[q] = mask;
+              if (wgt != 1.0f || mask) special = true;
+            }
+            if (!special) continue;
+            e.slot = s;
+            e.local = (lz * kBlock + ly) * kBlock + lx;
+            e.fine_slot = -1;
+            e.fine_local = 0;
+            const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
+            const long fp = ((long)(fk >> 4) * Fl.nb[1] + (fj >> 4)) * Fl.nb[0] + (fi >> 4);
+            const int fs = Fl.slot_of[fp];
+            bool anymask = false;
+            for (int q = 0; q < kQ; ++q) anymask = anymask || e.mask[q];
+            if (anymask) {
+              if (fs < (int)Fl.interior.size())
+                return fail(c, VMLBM_ERANGE, "coalescence children of level %d not in a ghost block", l);
+              e.fine_slot = fs;
+              e.fine_local = (((fk & 15) * kBlock) + (fj & 15)) * kBlock + (fi & 15);
+            }
+            V.iface.push_back(e);
+          }
+    }
+    if (V.iface_cap && (int)V.iface.size() > V.iface_cap)
+      return fail(c, VMLBM_ERANGE, "level %d coalescence table needs %zu entries, capacity %d", l, V.iface.size(),
+                  V.iface_cap);
+  }
+  return VMLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+struct LevelArgs {
+  int n[3], nb[3];
+  const int* slot_of;
+  const int* pos;      // per slot: block position x, y, z
+  uint32_t N;          // population stride (cap * 4096)
+  double sp, sm, F[3];
+};
+
+__device__ __forceinline__ int nbr_slot(const LevelArgs& a, const int* pos3, int dx, int dy, int dz) {
+  int x = pos3[0] + dx, y = pos3[1] + dy, z = pos3[2] + dz;
+  x = x < 0 ? x + a.nb[0] : (x >= a.nb[0] ? x - a.nb[0] : x);
+  y = y < 0 ? y + a.nb[1] : (y >= a.nb[1] ? y - a.nb[1] : y);
+  z = z < 0 ? z + a.nb[2] : (z >= a.nb[2] ? z - a.nb[2] : z);
+  return a.slot_of[((long)z * a.nb[1] + y) * a.nb[0] + x];
+}
+
+// population q of local cell (x,y,z) pulled from x - c_q, via the neighbour
+// slot table nb[27]; returns false if the source block is not stored
+template <typename S, int Q>
+__device__ __forceinline__ bool pull_block(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x,
+                                           int y, int z, typename Store<S>::T& out) {
+  constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
+  int xs = x - cx, ys = y - cy, zs = z - cz;
+  const int bx = xs < 0 ? -1 : (xs > 15 ? 1 : 0), by = ys < 0 ? -1 : (ys > 15 ? 1 : 0),
+            bz = zs < 0 ? -1 : (zs > 15 ? 1 : 0);
+  const int s = (bx | by | bz) ? nbs[(bz + 1) * 9 + (by + 1) * 3 + (bx + 1)] : slot;
+  if (s < 0) return false;
+  const uint32_t c = (uint32_t)s * kBlockCells + (uint32_t)(((zs & 15) * 16 + (ys & 15)) * 16 + (xs & 15));
+  out = Store<S>::load(src[(size_t)Q * N + c]);
+  return true;
+}
+
+template <typename S, int... Qs>
+__device__ __forceinline__ bool pull_cell(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x, int y,
+                                          int z, typename Store<S>::T (&d)[kQ], std::integer_sequence<int, Qs...>) {
+  return (pull_block<S, Qs>(src, N, nbs, slot, x, y, z, d[Qs]) & ...);
+}
+
+template <typename S, int... Qs>
+__device__ __forceinline__ void ghost_pull(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x,
+                                           int y, int z, typename Store<S>::T (&d)[kQ],
+                                           std::integer_sequence<int, Qs...>) {
+  ((d[Qs] = pull_block<S, Qs>(src, N, nbs, slot, x, y, z, d[Qs]) ? d[Qs] : typename Store<S>::T(0)), ...);
+}
+
+__device__ __forceinline__ void load_neighbours(const LevelArgs& a, int slot, int* nbs) {
+  if (threadIdx.x < 27) {
+    const int t = threadIdx.x;
+    nbs[t] = nbr_slot(a, a.pos + 3 * slot, t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1);
+  }
+  __syncthreads();
+}
+
+// interior blocks of a level: pull + collide, cells with flags left out
+template <typename S>
+__global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                                     const uint8_t* __restrict__ flags, const int* __restrict__ list,
+                                                     int* __restrict__ status, LevelArgs a) {
+  using T = typename Store<S>::T;
+  __shared__ int nbs[27];
+  const int slot = list[blockIdx.x];
+  load_neighbours(a, slot, nbs);
+  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  for (int z = 0; z < kBlock; ++z) {
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+    if (flags[c]) continue;
+    T d[kQ];
+    if (!pull_cell<S>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
+      status[kStatusRange] = 6;
+      continue;
+    }
+    const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+    if (!(drho == drho)) status[kStatusUnstable] = 1;
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * a.N + c], Store<S>::store(d[q]));
+  }
+}
+
+// ghost blocks: stream only (sources not stored at this level give 0)
+template <typename S>
+__global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src, S* __restrict__ dst,
+                                                      const int* __restrict__ list, LevelArgs a) {
+  using T = typename Store<S>::T;
+  __shared__ int nbs[27];
+  const int slot = list[blockIdx.x];
+  load_neighbours(a, slot, nbs);
+  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  for (int z = 0; z < kBlock; ++z) {
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+    T d[kQ];
+    ghost_pull<S>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+  }
+}
+
+// explosion: every cell of a ghost block of level l+1 takes its parent's
+// populations (level l, current state)
+template <typename S>
+__global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S* __restrict__ fine,
+                                                 const int* __restrict__ ex, uint32_t Nc, uint32_t Nf) {
+  const int* e = ex + 5 * blockIdx.x;
+  const int gs = e[0], ps = e[1], ox = e[2], oy = e[3], oz = e[4];
+  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  for (int z = 0; z < kBlock; ++z) {
+    const uint32_t cf = (uint32_t)gs * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+    const uint32_t cc = (uint32_t)ps * kBlockCells +
+                        (uint32_t)(((oz + (z >> 1)) * 16 + (oy + (y >> 1))) * 16 + (ox + (x >> 1)));
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) fine[(size_t)q * Nf + cf] = coarse[(size_t)q * Nc + cc];
+  }
+}
+
+// coalescence cells of level l
+template <typename S>
+__global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __restrict__ dst,
+                                               const S* __restrict__ fine, const IfaceEntry* __restrict__ tab,
+                                               int count, int* __restrict__ status, LevelArgs a, uint32_t Nf) {
+  using T = typename Store<S>::T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const IfaceEntry& e = tab[t];
+  const int* p3 = a.pos + 3 * e.slot;
+  const int x = e.local & 15, y = (e.local >> 4) & 15, z = e.local >> 8;
+  T d[kQ];
+  for (int q = 0; q < kQ; ++q) {
+    double v = 0.0;
+    if (e.weight[q] != 0.0f) {
+      int xs = x - cx_of(q), ys = y - cy_of(q), zs = z - cz_of(q);
+      const int bx = xs < 0 ? -1 : (xs > 15 ? 1 : 0), by = ys < 0 ? -1 : (ys > 15 ? 1 : 0),
+                bz = zs < 0 ? -1 : (zs > 15 ? 1 : 0);
+      const int s = (bx | by | bz) ? nbr_slot(a, p3, bx, by, bz) : e.slot;
+      if (s < 0) {
+        status[kStatusRange] = 7;
+      } else {
+        const uint32_t c = (uint32_t)s * kBlockCells + (uint32_t)(((zs & 15) * 16 + (ys & 15)) * 16 + (xs & 15));
+        v = (double)e.weight[q] * (double)Store<S>::load(src[(size_t)q * a.N + c]);
+      }
+    }
+    if (e.mask[q]) {
+      double acc = 0.0;
+      for (int m = 0; m < 8; ++m)
+        if (e.mask[q] & (1u << m)) {
+          const uint32_t cf = (uint32_t)e.fine_slot * kBlockCells + (uint32_t)e.fine_local +
+                              (uint32_t)(((m >> 2) * 16 + ((m >> 1) & 1)) * 16 + (m & 1));
+          acc += (double)Store<S>::load(fine[(size_t)q * Nf + cf]);
+        }
+      v += 0.125 * acc;
+    }
+    d[q] = T(v);
+  }
+  const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+  if (!(drho == drho)) status[kStatusUnstable] = 1;
+  const uint32_t c = (uint32_t)e.slot * kBlockCells + (uint32_t)e.local;
+  for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+}
+
+__global__ void k_mark_iface(uint8_t* __restrict__ flags, const IfaceEntry* __restrict__ tab, int count) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  flags[(uint32_t)tab[t].slot * kBlockCells + (uint32_t)tab[t].local] |= kIface;
+}
+
+// f~(0) = collide(f^eq(rho, u)) on every cell of every slot of a level, u of
+// the coarse cell holding it
+template <typename S>
+__global__ __launch_bounds__(256) void k_init_level(S* __restrict__ dst, const double* __restrict__ u0, int l,
+                                                    int n0x, int n0y, uint32_t N0, double drho, LevelArgs a) {
+  using T = typename Store<S>::T;
+  const int slot = blockIdx.x;
+  const int* p3 = a.pos + 3 * slot;
+  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  for (int z = 0; z < kBlock; ++z) {
+    const int i = p3[0] * 16 + x, j = p3[1] * 16 + y, k = p3[2] * 16 + z;
+    double u[3] = {0.0, 0.0, 0.0};
+    if (u0) {
+      const uint32_t c0 = ((uint32_t)(k >> l) * n0y + (j >> l)) * n0x + (i >> l);
+      u[0] = u0[c0]; u[1] = u0[N0 + c0]; u[2] = u0[2 * (size_t)N0 + c0];
+    }
+    const double usq = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    T d[kQ];
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      const double cu = cx_of(q) * u[0] + cy_of(q) * u[1] + cz_of(q) * u[2];
+      d[q] = T(w_of(q) * (drho + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
+    }
+    trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+  }
+}
+
+// mapping of the finest level's interior slots
+__global__ __launch_bounds__(256) void k_map_level(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
+                                                   const DevParticle* __restrict__ parts, int np, SweepParams p,
+                                                   BAddr ad, const int* __restrict__ pos, int* __restrict__ status) {
+  const int slot = blockIdx.x;
+  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  for (int z = 0; z < kBlock; ++z) {
+    const int i = pos[3 * slot] * 16 + x, j = pos[3 * slot + 1] * 16 + y, k = pos[3 * slot + 2] * 16 + z;
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+    map_cell<BAddr>(i, j, k, c, flags, owner, parts, np, p, ad, status);
+  }
+}
+
+// Data of one new interior slot of level l from the old layout: the old leaf
+// holding each cell gives the source level; coarser sources are copied,
+// finer ones averaged.
+struct MigrateArgs {
+  int L;
+  int nbL[3];
+  const int8_t* old_leaf;
+  const void* old_pdf[4];
+  const int* old_slot_of[4];
+  int nb[4][3];
+  uint32_t oldN[4];
+};
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_migrate(S* __restrict__ dst, const int* __restrict__ list,
+                                                 const int* __restrict__ pos, int l, uint32_t N, MigrateArgs m,
+                                                 int* __restrict__ status) {
+  const int slot = list[blockIdx.x];
+  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  for (int z = 0; z < kBlock; ++z) {
+    const int i = pos[3 * slot] * 16 + x, j = pos[3 * slot + 1] * 16 + y, k = pos[3 * slot + 2] * 16 + z;
+    const int s = m.L - l;
+    const int fi = (i << s) >> 4, fj = (j << s) >> 4, fk = (k << s) >> 4;   // finest block position
+    const int lo = m.old_leaf[((long)fk * m.nbL[1] + fj) * m.nbL[0] + fi];
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+    double v[kQ];
+    for (int q = 0; q < kQ; ++q) v[q] = 0.0;
+    bool ok = true;
+    if (lo <= l) {
+      const int sh = l - lo;
+      const int ci = i >> sh, cj = j >> sh, ck = k >> sh;
+      const int os = m.old_slot_of[lo][((long)(ck >> 4) * m.nb[lo][1] + (cj >> 4)) * m.nb[lo][0] + (ci >> 4)];
+      if (os < 0) ok = false;
+      else {
+        const uint32_t oc = (uint32_t)os * kBlockCells + (uint32_t)(((ck & 15) * 16 + (cj & 15)) * 16 + (ci & 15));
+        const S* src = (const S*)m.old_pdf[lo];
+        for (int q = 0; q < kQ; ++q) v[q] = (double)Store<S>::load(src[(size_t)q * m.oldN[lo] + oc]);
+      }
+    } else {
+      const int sh = lo - l, e = 1 << sh;
+      const S* src = (const S*)m.old_pdf[lo];
+      for (int dz = 0; dz < e && ok; ++dz)
+        for (int dy = 0; dy < e && ok; ++dy)
+          for (int dx = 0; dx < e && ok; ++dx) {
+            const int ci = (i << sh) + dx, cj = (j << sh) + dy, ck = (k << sh) + dz;
+            const int os = m.old_slot_of[lo][((long)(ck >> 4) * m.nb[lo][1] + (cj >> 4)) * m.nb[lo][0] + (ci >> 4)];
+            if (os < 0) { ok = false; break; }
+            const uint32_t oc = (uint32_t)os * kBlockCells + (uint32_t)(((ck & 15) * 16 + (cj & 15)) * 16 + (ci & 15));
+            for (int q = 0; q < kQ; ++q) v[q] += (double)Store<S>::load(src[(size_t)q * m.oldN[lo] + oc]);
+          }
+      const double inv = 1.0 / (double)(e * e * e);
+      for (int q = 0; q < kQ; ++q) v[q] *= inv;
+    }
+    if (!ok) status[kStatusRange] = 8;
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store((typename Store<S>::T)v[q]);
+  }
+}
+
+void forest_free(Forest* f) { delete f; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+namespace {
+
+LevelArgs level_args(vmlbm_ctx* c, int l, int tab) {
+  Forest& f = *c->forest;
+  Forest::Lev& V = f.lv[l];
+  LevelArgs a{};
+  for (int i = 0; i < 3; ++i) { a.n[i] = V.n[i]; a.nb[i] = V.nb[i]; }
+  a.slot_of = (const int*)(c->ws + V.off_slot_of[tab]);
+  a.pos = (const int*)(c->ws + V.off_pos);
+  a.N = (uint32_t)V.cap * kBlockCells;
+  a.sp = V.lp.sp;
+  a.sm = V.lp.sm;
+  for (int i = 0; i < 3; ++i) a.F[i] = V.lp.F[i];
+  return a;
+}
+
+BAddr finest_addr(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  Forest::Lev& V = f.lv[f.L];
+  BAddr ad{};
+  for (int i = 0; i < 3; ++i) { ad.n[i] = V.n[i]; ad.nb[i] = V.nb[i]; }
+  ad.slot_of = (const int*)(c->ws + V.off_slot_of[V.tab]);
+  ad.N = (uint32_t)V.cap * kBlockCells;
+  return ad;
+}
+
+SweepParams finest_params(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  Forest::Lev& V = f.lv[f.L];
+  SweepParams p{};
+  p.nx = V.n[0]; p.ny = V.n[1]; p.nz = V.n[2];
+  p.per[0] = p.per[1] = p.per[2] = 1;
+  p.wall_axis = -1;
+  p.sp = V.lp.sp;
+  p.sm = V.lp.sm;
+  for (int i = 0; i < 3; ++i) p.F[i] = V.lp.F[i];
+  p.N = (uint32_t)V.cap * kBlockCells;
+  p.box = c->box;
+  p.slot_stride = c->slot_stride;
+  return p;
+}
+
+// upload the tables of the current layout; slot_of goes into each level's
+// current table set (the other set may still hold the previous layout)
+int upload_tables(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  for (int l = 0; l <= f.L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    HIP_TRY(c, hipMemcpy(c->ws + V.off_slot_of[V.tab], V.slot_of.data(), V.npos * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->ws + V.off_pos, V.pos.data(), V.pos.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!V.interior.empty())
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_int, V.interior.data(), V.interior.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!V.ghost.empty())
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_ghost, V.ghost.data(), V.ghost.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!V.explode.empty())
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_explode, V.explode.data(), V.explode.size() * sizeof(int),
+                           hipMemcpyHostToDevice));
+    if (!V.iface.empty())
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_iface, V.iface.data(), V.iface.size() * sizeof(IfaceEntry),
+                           hipMemcpyHostToDevice));
+    V.n_int = (int)V.interior.size();
+    V.n_ghost = (int)V.ghost.size();
+    V.n_iface = (int)V.iface.size();
+  }
+  HIP_TRY(c, hipMemcpy(c->ws + f.off_leaf[f.leaf_tab], f.leaf.data(), f.leaf.size(), hipMemcpyHostToDevice));
+  return VMLBM_OK;
+}
+
+// flags of every level: coalescence cells; particle mapping on the finest level
+int mark_flags(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  for (int l = 0; l <= f.L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    HIP_TRY(c, hipMemsetAsync(c->ws + V.off_flags, 0, (size_t)V.cap * kBlockCells, c->stream));
+    if (V.n_iface) {
+      k_mark_iface<<<(V.n_iface + 255) / 256, 256, 0, c->stream>>>((uint8_t*)(c->ws + V.off_flags),
+                                                                   (const IfaceEntry*)(c->ws + V.off_iface), V.n_iface);
+      HIP_TRY(c, hipGetLastError());
+    }
+  }
+  const int np = (int)c->spheres.size();
+  if (np) {
+    Forest::Lev& V = f.lv[f.L];
+    k_map_level<<<V.n_int, 256, 0, c->stream>>>((uint8_t*)(c->ws + V.off_flags), (uint16_t*)(c->ws + f.off_owner),
+                                                c->parts(), np, finest_params(c), finest_addr(c),
+                                                (const int*)(c->ws + V.off_pos), c->status());
+    HIP_TRY(c, hipGetLastError());
+  }
+  return VMLBM_OK;
+}
+
+int explode(vmlbm_ctx* c, int l) {
+  Forest& f = *c->forest;
+  Forest::Lev& C = f.lv[l];
+  Forest::Lev& F = f.lv[l + 1];
+  if (!F.n_ghost) return VMLBM_OK;
+  return dispatch(c->cfg.storage, [&](auto* tag) -> int {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    k_explode<S><<<F.n_ghost, 256, 0, c->stream>>>((const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]),
+                                                   (const int*)(c->ws + F.off_explode),
+                                                   (uint32_t)C.cap * kBlockCells, (uint32_t)F.cap * kBlockCells);
+    HIP_TRY(c, hipGetLastError());
+    return VMLBM_OK;
+  });
+}
+
+int sweep_level(vmlbm_ctx* c, int l) {
+  Forest& f = *c->forest;
+  Forest::Lev& V = f.lv[l];
+  const LevelArgs a = level_args(c, l, V.tab);
+  void* src = c->ws + V.off_pdf[V.cur];
+  void* dst = c->ws + V.off_pdf[1 - V.cur];
+  const int np = (int)c->spheres.size();
+  int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    if (V.n_int) {
+      k_level_sweep<S><<<V.n_int, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
+                                                       (const int*)(c->ws + V.off_int), c->status(), a);
+      HIP_TRY(c, hipGetLastError());
+    }
+    if (V.n_iface) {
+      Forest::Lev& F = f.lv[l + 1];
+      k_iface<S><<<(V.n_iface + 255) / 256, 256, 0, c->stream>>>(
+          (const S*)src, (S*)dst, (const S*)(c->ws + F.off_pdf[F.cur]), (const IfaceEntry*)(c->ws + V.off_iface),
+          V.n_iface, c->status(), a, (uint32_t)F.cap * kBlockCells);
+      HIP_TRY(c, hipGetLastError());
+    }
+    if (V.n_ghost) {
+      k_ghost_stream<S><<<V.n_ghost, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const int*)(c->ws + V.off_ghost), a);
+      HIP_TRY(c, hipGetLastError());
+    }
+    if (l == f.L && np) {
+      const SweepParams p = finest_params(c);
+      const int cells = p.box * p.box * p.box;
+      k_boundary_particles<S, BAddr><<<dim3((cells + 255) / 256, np), dim3(256), 0, c->stream>>>(
+          (const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags), (const uint16_t*)(c->ws + f.off_owner),
+          c->parts(), c->slots(), c->status(), p, finest_addr(c));
+      HIP_TRY(c, hipGetLastError());
+    }
+    return VMLBM_OK;
+  });
+  if (rc) return rc;
+  V.cur = 1 - V.cur;
+  c->cell_updates += (double)V.n_int * kBlockCells;
+  if (l == f.L) {
+    if (np) {
+      const SweepParams p = finest_params(c);
+      UpdateParams u{};
+      for (int i = 0; i < 3; ++i) u.g[i] = c->cfg.gravity[i];
+      u.step = (int)(c->fine_steps_done % std::max(c->cfg.history, 1));
+      u.hist_len = std::max(c->cfg.history, 1);
+      u.np = np;
+      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, u, c->stream));
+      if (c->moving) {
+        rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+          using S = std::remove_pointer_t<decltype(tag)>;
+          const int rb = p.box + 1;
+          dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
+          k_refill<S, BAddr><<<grid, block, 0, c->stream>>>((S*)(c->ws + V.off_pdf[V.cur]),
+                                                             (const uint8_t*)(c->ws + V.off_flags),
+                                                             (const uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
+                                                             finest_addr(c), c->status());
+          HIP_TRY(c, hipGetLastError());
+          k_remap<BAddr><<<grid, block, 0, c->stream>>>((uint8_t*)(c->ws + V.off_flags),
+                                                        (uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
+                                                        finest_addr(c), c->status());
+          HIP_TRY(c, hipGetLastError());
+          return VMLBM_OK;
+        });
+        if (rc) return rc;
+      }
+    }
+    c->fine_steps_done += 1;
+  }
+  return VMLBM_OK;
+}
+
+int step_level(vmlbm_ctx* c, int l) {
+  Forest& f = *c->forest;
+  if (l < f.L) {
+    int rc = explode(c, l);
+    if (rc) return rc;
+    rc = step_level(c, l + 1);
+    if (rc) return rc;
+    rc = step_level(c, l + 1);
+    if (rc) return rc;
+  }
+  return sweep_level(c, l);
+}
+
+// re-check the layout around the particles; move data if it changed
+int check_layout(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  const int np = (int)c->spheres.size();
+  std::vector<vmlbm_sphere> sph = c->spheres;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (np) {
+    std::vector<DevParticle> hp(np);
+    HIP_TRY(c, hipMemcpy(hp.data(), c->parts(), np * sizeof(DevParticle), hipMemcpyDeviceToHost));
+    for (int i = 0; i < np; ++i)
+      for (int a = 0; a < 3; ++a) sph[i].x[a] = hp[i].x[a];
+  }
+  std::vector<int8_t> nl = balance_layout(f, layout_targets(c, f, sph));
+  if (nl == f.leaf) return VMLBM_OK;
+  // the old layout stays readable on the device: leaf array, slot_of tables
+  // and populations of the current buffers
+  MigrateArgs m{};
+  m.L = f.L;
+  for (int a = 0; a < 3; ++a) m.nbL[a] = f.nbL[a];
+  m.old_leaf = (const int8_t*)(c->ws + f.off_leaf[f.leaf_tab]);
+  for (int l = 0; l <= f.L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    m.old_pdf[l] = c->ws + V.off_pdf[V.cur];
+    m.old_slot_of[l] = (const int*)(c->ws + V.off_slot_of[V.tab]);
+    for (int a = 0; a < 3; ++a) m.nb[l][a] = V.nb[a];
+    m.oldN[l] = (uint32_t)V.cap * kBlockCells;
+  }
+  std::vector<int8_t> old = f.leaf;
+  f.leaf = nl;
+  int rc = build_tables(c, f);
+  if (rc) { f.leaf = old; return rc; }
+  for (int l = 0; l <= f.L; ++l) f.lv[l].tab = 1 - f.lv[l].tab;
+  f.leaf_tab = 1 - f.leaf_tab;
+  rc = upload_tables(c);
+  if (rc) return rc;
+  rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    for (int l = 0; l <= f.L; ++l) {
+      Forest::Lev& V = f.lv[l];
+      if (!V.n_int) continue;
+      k_migrate<S><<<V.n_int, 256, 0, c->stream>>>((S*)(c->ws + V.off_pdf[1 - V.cur]), (const int*)(c->ws + V.off_int),
+                                                   (const int*)(c->ws + V.off_pos), l, (uint32_t)V.cap * kBlockCells, m,
+                                                   c->status());
+      HIP_TRY(c, hipGetLastError());
+    }
+    return VMLBM_OK;
+  });
+  if (rc) return rc;
+  for (int l = 0; l <= f.L; ++l) f.lv[l].cur = 1 - f.lv[l].cur;
+  rc = mark_flags(c);
+  if (rc) return rc;
+  f.refinements += 1;
+  return VMLBM_OK;
+}
+
+}  // namespace
 
 int refine_create(vmlbm_ctx* c) {
-  c->err = "block-structured grid not available";
-  return VMLBM_EINVAL;
+  const vmlbm_config& g = c->cfg;
+  if (g.block != kBlock) return fail(c, VMLBM_EINVAL, "block edge must be %d", kBlock);
+  if (g.levels < 1 || g.levels > 4) return fail(c, VMLBM_EINVAL, "levels must lie in 1..4");
+  for (int a = 0; a < 3; ++a) {
+    if (!g.periodic[a]) return fail(c, VMLBM_EINVAL, "the refined grid is periodic");
+    if (g.n[a] % kBlock) return fail(c, VMLBM_EINVAL, "coarse cells must be a multiple of %d", kBlock);
+  }
+  auto* f = new Forest();
+  f->L = g.levels - 1;
+  for (int a = 0; a < 3; ++a) {
+    f->nb0[a] = g.n[a] / kBlock;
+    f->nbL[a] = f->nb0[a] << f->L;
+  }
+  const long NB = (long)f->nbL[0] * f->nbL[1] * f->nbL[2];
+  if (NB > (1L << 26)) { delete f; return fail(c, VMLBM_ERANGE, "too many finest block positions"); }
+  f->base.assign(NB, 0);
+  f->lv.resize(f->L + 1);
+  double tau = 1.0 / g.omega;
+  for (int l = f->L; l >= 0; --l) {
+    Forest::Lev& V = f->lv[l];
+    for (int a = 0; a < 3; ++a) {
+      V.n[a] = g.n[a] << l;
+      V.nb[a] = f->nb0[a] << l;
+    }
+    V.npos = (long)V.nb[0] * V.nb[1] * V.nb[2];
+    V.lp.sp = 1.0 / tau;
+    V.lp.sm = s_minus_of(V.lp.sp, g.magic);
+    for (int a = 0; a < 3; ++a) V.lp.F[a] = g.body_force[a] * (double)(1 << (f->L - l));
+    tau = 0.5 + 0.5 * (tau - 0.5);
+  }
+  c->forest = std::unique_ptr<Forest, void (*)(Forest*)>(f, forest_free);
+  return VMLBM_OK;
 }
-int refine_plan(vmlbm_ctx*) { return VMLBM_ESTATE; }
-int refine_init(vmlbm_ctx*, double, const double*) { return VMLBM_ESTATE; }
-int refine_step(vmlbm_ctx*, int) { return VMLBM_ESTATE; }
-int refine_read_populations(vmlbm_ctx*, int, double*) { return VMLBM_ESTATE; }
-int refine_write_populations(vmlbm_ctx*, int, const double*) { return VMLBM_ESTATE; }
-int refine_read_owner(vmlbm_ctx*, int, int*) { return VMLBM_ESTATE; }
-int refine_level_cells(vmlbm_ctx*, int, size_t*) { return VMLBM_ESTATE; }
-int refine_cell_counts(vmlbm_ctx*, int, long long*, long long*) { return VMLBM_ESTATE; }
+
+int refine_plan(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  // layout from the spheres' initial positions and the static regions
+  f.leaf = balance_layout(f, layout_targets(c, f, c->spheres));
+  for (auto& V : f.lv) { V.cap = 0; V.iface_cap = 0; }
+  int rc = build_tables(c, f);
+  if (rc) return rc;
+  const size_t S = storage_bytes(c->cfg.storage);
+  int box = 0;
+  for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
+  c->box = box;
+  c->slot_stride = (((size_t)box * box * box + 255) / 256) * 4 * 6;
+  const int np = (int)c->spheres.size();
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };
+  c->off_status = take(kStatusWords * sizeof(int));
+  c->off_parts = take(std::max(np, 1) * sizeof(DevParticle));
+  c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
+  c->off_hist = take((size_t)std::max(c->cfg.history, 1) * std::max(np, 1) * 12 * sizeof(double));
+  for (int l = 0; l <= f.L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    const int n = (int)(V.pos.size() / 3);
+    V.cap = (int)std::min<long>(V.npos, 2L * n + 64);
+    V.iface_cap = 2 * (int)V.iface.size() + 4096;
+    for (int b = 0; b < 2; ++b) V.off_pdf[b] = take((size_t)kQ * V.cap * kBlockCells * S);
+    V.off_flags = take((size_t)V.cap * kBlockCells);
+    for (int b = 0; b < 2; ++b) V.off_slot_of[b] = take(V.npos * sizeof(int));
+    V.off_pos = take((size_t)V.cap * 3 * sizeof(int));
+    V.off_int = take((size_t)V.cap * sizeof(int));
+    V.off_ghost = take((size_t)V.cap * sizeof(int));
+    V.off_explode = take((size_t)V.cap * 5 * sizeof(int));
+    V.off_iface = take((size_t)V.iface_cap * sizeof(IfaceEntry));
+  }
+  f.off_owner = take((size_t)f.lv[f.L].cap * kBlockCells * sizeof(uint16_t));
+  for (int b = 0; b < 2; ++b) f.off_leaf[b] = take(f.leaf.size());
+  c->ws_needed = off;
+  return VMLBM_OK;
+}
+
+int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
+  Forest& f = *c->forest;
+  const int np = (int)c->spheres.size();
+  f.leaf = balance_layout(f, layout_targets(c, f, c->spheres));
+  int rc = build_tables(c, f);
+  if (rc) return rc;
+  for (auto& V : f.lv) { V.tab = 0; V.cur = 0; }
+  f.leaf_tab = 0;
+  rc = upload_tables(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipMemsetAsync(c->status(), 0, kStatusWords * sizeof(int), c->stream));
+  std::vector<DevParticle> hp(np);
+  for (int i = 0; i < np; ++i) {
+    const vmlbm_sphere& s = c->spheres[i];
+    DevParticle& P = hp[i];
+    memset(&P, 0, sizeof(P));
+    for (int a = 0; a < 3; ++a) {
+      P.x[a] = s.x[a];
+      P.u[a] = s.fixed ? 0.0 : s.u[a];
+      P.w[a] = s.fixed ? 0.0 : s.w[a];
+    }
+    P.r = s.radius; P.rho = s.density_ratio; P.cv = s.cv; P.cvw = s.cv_omega;
+    P.fixed = s.fixed;
+    for (int a = 0; a < 3; ++a) {
+      const int n = f.lv[f.L].n[a];
+      int lo = (int)std::floor(s.x[a] - s.radius) - 3;
+      lo = ((lo % n) + n) % n;
+      P.box_lo[a] = lo;
+      P.remap_lo[a] = lo;
+    }
+  }
+  if (np) HIP_TRY(c, hipMemcpyAsync(c->parts(), hp.data(), np * sizeof(DevParticle), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * 12 * sizeof(double), c->stream));
+  // velocity staging in the second buffer of level 0
+  Forest::Lev& V0 = f.lv[0];
+  const uint32_t N0 = (uint32_t)((size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2]);
+  double* u0d = nullptr;
+  if (u0) {
+    const size_t need = 3 * (size_t)N0 * sizeof(double);
+    if (need > (size_t)kQ * V0.cap * kBlockCells * storage_bytes(c->cfg.storage))
+      return fail(c, VMLBM_ERANGE, "velocity staging does not fit");
+    u0d = (double*)(c->ws + V0.off_pdf[1]);
+    HIP_TRY(c, hipMemcpyAsync(u0d, u0, need, hipMemcpyHostToDevice, c->stream));
+  }
+  rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+    using S = std::remove_pointer_t<decltype(tag)>;
+    for (int l = 0; l <= f.L; ++l) {
+      Forest::Lev& V = f.lv[l];
+      const int ns = V.n_int + V.n_ghost;
+      if (!ns) continue;
+      k_init_level<S><<<ns, 256, 0, c->stream>>>((S*)(c->ws + V.off_pdf[0]), u0d, l, c->cfg.n[0], c->cfg.n[1], N0,
+                                                 rho - 1.0, level_args(c, l, 0));
+      HIP_TRY(c, hipGetLastError());
+    }
+    return VMLBM_OK;
+  });
+  if (rc) return rc;
+  rc = mark_flags(c);
+  if (rc) return rc;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->steps_done = 0;
+  c->fine_steps_done = 0;
+  f.refinements = 0;
+  f.coarse_steps = 0;
+  c->cur = 0;
+  c->initialized = true;
+  return VMLBM_OK;
+}
+
+int refine_step(vmlbm_ctx* c, int n) {
+  Forest& f = *c->forest;
+  for (int s = 0; s < n; ++s) {
+    int rc = step_level(c, 0);
+    if (rc) return rc;
+    c->steps_done += 1;
+    f.coarse_steps += 1;
+    if (c->cfg.check_every > 0 && f.coarse_steps % c->cfg.check_every == 0) {
+      rc = check_layout(c);
+      if (rc) return rc;
+    }
+  }
+  return VMLBM_OK;
+}
+
+int refine_level_cells(vmlbm_ctx* c, int level, size_t* cells) {
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  *cells = (size_t)f.lv[level].n_int * kBlockCells;
+  return VMLBM_OK;
+}
+
+static int read_level_raw(vmlbm_ctx* c, int level, std::vector<double>& out, std::vector<uint8_t>& fl) {
+  Forest& f = *c->forest;
+  Forest::Lev& V = f.lv[level];
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t S = storage_bytes(c->cfg.storage);
+  const size_t cells = (size_t)V.n_int * kBlockCells;
+  out.assign(kQ * cells, 0.0);
+  fl.assign(cells, 0);
+  std::vector<char> raw(cells * S);
+  for (int q = 0; q < kQ; ++q) {
+    // interior slots are 0..n_int-1, contiguous at the front of the pool
+    HIP_TRY(c, hipMemcpy(raw.data(), c->ws + V.off_pdf[V.cur] + ((size_t)q * V.cap * kBlockCells) * S, cells * S,
+                         hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cells; ++i) {
+      double d;
+      if (c->cfg.storage == VMLBM_F64) d = ((const double*)raw.data())[i];
+      else if (c->cfg.storage == VMLBM_F32) d = ((const float*)raw.data())[i];
+      else d = __half2float(((const __half*)raw.data())[i]);
+      out[q * cells + i] = w_of(q) + d;
+    }
+  }
+  HIP_TRY(c, hipMemcpy(fl.data(), c->ws + V.off_flags, cells, hipMemcpyDeviceToHost));
+  return VMLBM_OK;
+}
+
+int refine_read_populations(vmlbm_ctx* c, int level, double* out) {
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  std::vector<double> v;
+  std::vector<uint8_t> fl;
+  int rc = read_level_raw(c, level, v, fl);
+  if (rc) return rc;
+  const size_t cells = fl.size();
+  for (int q = 0; q < kQ; ++q)
+    for (size_t i = 0; i < cells; ++i) out[q * cells + i] = (fl[i] & kSolid) ? 0.0 : v[q * cells + i];
+  return VMLBM_OK;
+}
+
+int refine_write_populations(vmlbm_ctx* c, int level, const double* in) {
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  Forest::Lev& V = f.lv[level];
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t S = storage_bytes(c->cfg.storage);
+  const size_t cells = (size_t)V.n_int * kBlockCells;
+  std::vector<char> raw(cells * S);
+  for (int q = 0; q < kQ; ++q) {
+    for (size_t i = 0; i < cells; ++i) {
+      const double d = in[q * cells + i] - w_of(q);
+      if (c->cfg.storage == VMLBM_F64) ((double*)raw.data())[i] = d;
+      else if (c->cfg.storage == VMLBM_F32) ((float*)raw.data())[i] = (float)d;
+      else ((__half*)raw.data())[i] = __float2half_rn((float)d);
+    }
+    HIP_TRY(c, hipMemcpy(c->ws + V.off_pdf[V.cur] + ((size_t)q * V.cap * kBlockCells) * S, raw.data(), cells * S,
+                         hipMemcpyHostToDevice));
+  }
+  return VMLBM_OK;
+}
+
+int refine_read_owner(vmlbm_ctx* c, int level, int* out) {
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  Forest::Lev& V = f.lv[level];
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t cells = (size_t)V.n_int * kBlockCells;
+  std::vector<uint8_t> fl(cells);
+  std::vector<uint16_t> ow(cells, 0);
+  HIP_TRY(c, hipMemcpy(fl.data(), c->ws + V.off_flags, cells, hipMemcpyDeviceToHost));
+  if (level == f.L && !c->spheres.empty())
+    HIP_TRY(c, hipMemcpy(ow.data(), c->ws + f.off_owner, cells * 2, hipMemcpyDeviceToHost));
+  for (size_t i = 0; i < cells; ++i) out[i] = (fl[i] & kSolid) ? (int)ow[i] : -1;
+  return VMLBM_OK;
+}
+
+int refine_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* interior) {
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  Forest::Lev& V = f.lv[level];
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t cells = (size_t)V.n_int * kBlockCells;
+  std::vector<uint8_t> fl(cells);
+  HIP_TRY(c, hipMemcpy(fl.data(), c->ws + V.off_flags, cells, hipMemcpyDeviceToHost));
+  long long nf = 0, ni = 0;
+  for (size_t i = 0; i < cells; ++i) { nf += !(fl[i] & kSolid); ni += fl[i] == 0; }
+  if (fluid) *fluid = nf;
+  if (interior) *interior = ni;
+  return VMLBM_OK;
+}
+
 void refine_destroy(vmlbm_ctx*) {}
 
 void level_force(const vmlbm_ctx* c, int level, double F[3]) {
@@ -25,17 +1135,54 @@ void level_force(const vmlbm_ctx* c, int level, double F[3]) {
   for (int a = 0; a < 3; ++a) F[a] = c->F[a] * s;
 }
 
-}  // namespace vm
-
-extern "C" {
-int vmlbm_level_blocks(vmlbm_ctx* c, int, int*, int*) {
-  if (!c) return VMLBM_EINVAL;
-  c->err = "not a block-structured grid";
-  return VMLBM_ESTATE;
-}
-int vmlbm_refinements(vmlbm_ctx* c, int* count) {
-  if (!c || !count) return VMLBM_EINVAL;
-  *count = 0;
+int refine_add_region(vmlbm_ctx* c, const int lo[3], const int hi[3], int level) {
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  const int s = 1 << f.L;
+  for (int k = 0; k < f.nbL[2]; ++k)
+    for (int j = 0; j < f.nbL[1]; ++j)
+      for (int i = 0; i < f.nbL[0]; ++i) {
+        const int p[3] = {i, j, k};
+        bool in = true;
+        for (int a = 0; a < 3; ++a) {
+          const double b0 = (double)p[a] * kBlock / s, b1 = (double)(p[a] + 1) * kBlock / s;
+          if (!(b1 > lo[a] && b0 < hi[a])) in = false;
+        }
+        if (in) f.base[f.lpos(i, j, k)] = (int8_t)std::max<int>(f.base[f.lpos(i, j, k)], level);
+      }
   return VMLBM_OK;
 }
+
+}  // namespace vm
+
+using namespace vm;
+
+extern "C" {
+
+int vmlbm_add_refine_region(vmlbm_ctx* c, const int lo[3], const int hi[3], int level) {
+  if (!c || !lo || !hi) return VMLBM_EINVAL;
+  if (c->cfg.block <= 0 || !c->forest) return fail(c, VMLBM_ESTATE, "not a block-structured grid");
+  if (c->ws) return fail(c, VMLBM_ESTATE, "regions must be added before the workspace is bound");
+  return refine_add_region(c, lo, hi, level);
 }
+
+int vmlbm_level_blocks(vmlbm_ctx* c, int level, int* count, int* origin) {
+  if (!c || !count) return VMLBM_EINVAL;
+  if (c->cfg.block <= 0 || !c->forest) return fail(c, VMLBM_ESTATE, "not a block-structured grid");
+  Forest& f = *c->forest;
+  if (level < 0 || level > f.L) return fail(c, VMLBM_EINVAL, "bad level");
+  const Forest::Lev& V = f.lv[level];
+  *count = (int)V.interior.size();
+  if (origin)
+    for (size_t i = 0; i < V.interior.size(); ++i)
+      for (int a = 0; a < 3; ++a) origin[3 * i + a] = V.pos[3 * V.interior[i] + a] * kBlock;
+  return VMLBM_OK;
+}
+
+int vmlbm_refinements(vmlbm_ctx* c, int* count) {
+  if (!c || !count) return VMLBM_EINVAL;
+  *count = c->forest ? c->forest->refinements : 0;
+  return VMLBM_OK;
+}
+
+}  // extern "C"

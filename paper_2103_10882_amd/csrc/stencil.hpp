@@ -56,119 +56,50 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Slow path for a fluid cell with wall or particle links: builds the 19
-// incoming populations with Eq. 10 (CLI) on particle links and halfway
-// bounce-back on walls, and accumulates the link forces of Eq. 11 and their
-// torques (Eq. 12) in FP64.  The constant part 2 w_q c_q of each link force
-// is left out: summed over the closed surface of a body it vanishes exactly
-// (every lattice line enters and leaves the body equally often), and so does
-// its torque (entry and exit points of a line differ by a multiple of c_q).
-template <typename S>
-__device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restrict__ flags,
-                              const uint16_t* __restrict__ owner, const DevParticle* __restrict__ parts,
-                              const SweepParams& p, int x, int y, int z, uint32_t c,
-                              typename Store<S>::T (&d)[kQ], int& pid, double (&Fl)[3], double (&Tl)[3],
-                              int* __restrict__ status, uint32_t* link_mask = nullptr,
-                              typename Store<S>::T* kappa_out = nullptr) {
-  using T = typename Store<S>::T;
-  const uint32_t N = p.N;
-  const int n[3] = {p.nx, p.ny, p.nz};
-  // pass 1: pull source of every direction and its flag, loads issued together
-  uint32_t sidx[kQ];
-  int8_t wall[kQ];          // -1: inside the domain, else 2*axis + side of the wall crossed
-  uint8_t sfl[kQ];
-#pragma unroll
-  for (int q = 1; q < kQ; ++q) {
-    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
-    int s3[3] = {x - cq[0], y - cq[1], z - cq[2]};
-    wall[q] = -1;
+// Addressing of a lattice of one level: locate() maps (possibly out-of-range)
+// cell coordinates to a cell index; populations of cell c, direction q live
+// at q * N + c.
+//
+// Uniform grid: cells [z][y][x]; periodic axes wrap, other axes end in walls.
+struct UAddr {
+  int n[3];
+  int per[3];
+  uint32_t N;
+  // 1: stored cell c; 0: outside through the wall (axis wa, side ws)
+  __device__ __forceinline__ int locate(int x, int y, int z, uint32_t& c, int& wa, int& ws) const {
+    int s[3] = {x, y, z};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      if (s3[a] < 0 || s3[a] >= n[a]) {
-        if (p.per[a]) s3[a] = s3[a] < 0 ? s3[a] + n[a] : s3[a] - n[a];
-        else if (wall[q] < 0) { wall[q] = (int8_t)(2 * a + (s3[a] < 0 ? 0 : 1)); s3[a] = 0; }
-        else s3[a] = 0;
+      if (s[a] < 0 || s[a] >= n[a]) {
+        if (per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
+        else { wa = a; ws = s[a] < 0 ? 0 : 1; return 0; }
       }
     }
-    sidx[q] = ((uint32_t)s3[2] * n[1] + s3[1]) * n[0] + s3[0];
+    c = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
+    return 1;
   }
-#pragma unroll
-  for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;
-  // pass 2: plain streaming where the source is fluid
-  d[0] = Store<S>::load(src[c]);
-#pragma unroll
-  for (int q = 1; q < kQ; ++q)
-    if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = Store<S>::load(src[(size_t)q * N + sidx[q]]);
-  // pass 3: links
-  if (link_mask) *link_mask = 0;
-#pragma unroll
-  for (int q = 1; q < kQ; ++q) {
-    if (kappa_out) kappa_out[q] = T(0);
-    if (wall[q] < 0 && !(sfl[q] & kSolid)) continue;
-    if (link_mask) *link_mask |= 1u << q;
-    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
-    const int qq = opp_of(q);
-    const double w = w_of(q);
-    const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
-    if (wall[q] >= 0) {
-      // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
-      const int wa = wall[q] >> 1, ws = wall[q] & 1;
-      double cv = 0.0;
-      if (wa == p.wall_axis)
-        cv = -(cq[0] * p.wall_v[ws][0] + cq[1] * p.wall_v[ws][1] + cq[2] * p.wall_v[ws][2]);
-      d[q] = own_qq - T(6.0 * w * cv);
-      continue;
-    }
-    // particle link in direction qq (c_qq = -c_q points into the solid)
-    const int pi = owner[sidx[q]];
-    const DevParticle& P = parts[pi];
-    double off[3];
-    sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
-    const double delta = ray_delta(off, -cq[0], -cq[1], -cq[2], P.r);
-    double rb[3] = {off[0] - delta * cq[0], off[1] - delta * cq[1], off[2] - delta * cq[2]};
-    double v[3] = {P.u[0] + (P.w[1] * rb[2] - P.w[2] * rb[1]),
-                   P.u[1] + (P.w[2] * rb[0] - P.w[0] * rb[2]),
-                   P.u[2] + (P.w[0] * rb[1] - P.w[1] * rb[0])};
-    double kappa = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
-    double alpha = 4.0 / (1.0 + 2.0 * delta);
-    // second node x - c_qq = x + c_q
-    int t[3] = {x + cq[0], y + cq[1], z + cq[2]};
-    bool second_ok = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      if (t[a] < 0 || t[a] >= n[a]) {
-        if (p.per[a]) t[a] = t[a] < 0 ? t[a] + n[a] : t[a] - n[a];
-        else second_ok = false;
-      }
-    }
-    uint32_t tidx = 0;
-    if (second_ok) {
-      tidx = ((uint32_t)t[2] * n[1] + t[1]) * n[0] + t[0];
-      if (flags[tidx] & kSolid) second_ok = false;
-    }
-    if (!second_ok) { kappa = 0.0; alpha = 2.0; }
-    if (kappa_out) kappa_out[q] = T(kappa);
-    // c_qq . v with c_qq = -c_q
-    const double cqv = -(cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2]);
-    T val = own_qq - T(3.0 * alpha * w * cqv);
-    if (second_ok) {
-      const T sec = Store<S>::load(src[(size_t)qq * N + tidx]);
-      const T own_q = Store<S>::load(src[(size_t)q * N + c]);
-      val = val + T(kappa) * (sec - own_q);
-    }
-    d[q] = val;
-    // link force: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
-    const double a0 = (double)own_qq, a1 = (double)val;
-    double Fq[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Fq[a] = (-cq[a] - v[a]) * a0 + (-cq[a] + v[a]) * a1;
-    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
-    pid = pi;
-    Fl[0] += Fq[0]; Fl[1] += Fq[1]; Fl[2] += Fq[2];
-    Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
-    Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
-    Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
+};
+
+// One level of the block-structured grid: 16^3-cell blocks in slots
+// (cell index = slot * 4096 + local), periodic; a dense table gives the slot
+// of every block position of the level (negative: not stored at this level).
+constexpr int kBlock = 16;
+constexpr int kBlockCells = kBlock * kBlock * kBlock;
+struct BAddr {
+  int n[3];            // cells of the level per axis
+  int nb[3];           // block positions of the level per axis
+  const int* slot_of;  // [nb2][nb1][nb0]
+  uint32_t N;          // population stride: slot capacity * 4096
+  // 1: stored cell c; -1: not stored at this level
+  __device__ __forceinline__ int locate(int x, int y, int z, uint32_t& c, int&, int&) const {
+    x = x < 0 ? x + n[0] : (x >= n[0] ? x - n[0] : x);
+    y = y < 0 ? y + n[1] : (y >= n[1] ? y - n[1] : y);
+    z = z < 0 ? z + n[2] : (z >= n[2] ? z - n[2] : z);
+    const int s = slot_of[((z >> 4) * nb[1] + (y >> 4)) * nb[0] + (x >> 4)];
+    if (s < 0) return -1;
+    c = (uint32_t)s * kBlockCells + (uint32_t)((((z & 15) << 4) | (y & 15)) << 4 | (x & 15));
+    return 1;
   }
-}
+};
 
 }  // namespace vm

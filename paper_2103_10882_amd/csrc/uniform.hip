@@ -13,10 +13,19 @@
 #include "common.hpp"
 #include "uniform.hpp"
 #include "stencil.hpp"
+#include "particle.hpp"
 
 namespace vm {
 
 namespace {
+
+__host__ __device__ UAddr uaddr(const SweepParams& p) {
+  UAddr a;
+  a.n[0] = p.nx; a.n[1] = p.ny; a.n[2] = p.nz;
+  for (int i = 0; i < 3; ++i) a.per[i] = p.per[i];
+  a.N = p.N;
+  return a;
+}
 
 // Interior sweep: every fluid cell without a wall or particle link.  Cells
 // with a nonzero flag are left to the boundary kernels below (solid cells are
@@ -41,64 +50,6 @@ __global__ __launch_bounds__(512) void k_sweep(const S* __restrict__ src, S* __r
   // streaming stores: the new state is not read again within this sweep
 #pragma unroll
   for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], Store<S>::store(d[q]));
-}
-
-// cell k of a sphere's box (edge p.box) -> grid cell; false if outside the domain
-__device__ __forceinline__ bool box_cell(const int* lo, int k, int edge, const SweepParams& p,
-                                         int& x, int& y, int& z) {
-  const int i = k % edge, j = (k / edge) % edge, l = k / (edge * edge);
-  int s[3] = {lo[0] + i, lo[1] + j, lo[2] + l};
-  const int n[3] = {p.nx, p.ny, p.nz};
-  for (int a = 0; a < 3; ++a) {
-    if (p.per[a]) s[a] = ((s[a] % n[a]) + n[a]) % n[a];
-    else if (s[a] < 0 || s[a] >= n[a]) return false;
-  }
-  x = s[0]; y = s[1]; z = s[2];
-  return true;
-}
-
-// Particle-link cells: one grid row per sphere over its box; a cell is
-// handled in the pass of the sphere it links to (owner array).  Every wave
-// writes its FP64 partial force/torque (zero if it holds no link) to its own
-// slot, so the per-sphere reduction reads a fixed set in a fixed order.
-template <typename S>
-__global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict__ src, S* __restrict__ dst,
-                                                            const uint8_t* __restrict__ flags,
-                                                            const uint16_t* __restrict__ owner,
-                                                            const DevParticle* __restrict__ parts,
-                                                            double* __restrict__ slots, int* __restrict__ status,
-                                                            SweepParams p) {
-  using T = typename Store<S>::T;
-  const int pi = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int edge = p.box;
-  int x = 0, y = 0, z = 0;
-  bool active = k < edge * edge * edge && box_cell(parts[pi].box_lo, k, edge, p, x, y, z);
-  uint32_t c = 0;
-  if (active) {
-    c = ((uint32_t)z * p.ny + y) * p.nx + x;
-    const uint8_t fl = flags[c];
-    active = (fl & kNearP) && owner[c] == pi;
-  }
-  int pid = -1;
-  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
-  if (active) {
-    T d[kQ];
-    boundary_cell<S>(src, flags, owner, parts, p, x, y, z, c, d, pid, Fl, Tl, status);
-    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
-    const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
-    if (!(drho == drho)) status[kStatusUnstable] = 1;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
-  }
-  double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
-#pragma unroll
-  for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
-  if ((threadIdx.x & 63) == 0) {
-    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(k >> 6) * 6;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) o[j] = v[j];
-  }
 }
 
 // Wall-link cells without particle links: the two boundary planes of each
@@ -127,7 +78,8 @@ __global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ sr
   int pid = -1;
   double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
   T d[kQ];
-  boundary_cell<S>(src, flags, owner, parts, p, r[0], r[1], r[2], c, d, pid, Fl, Tl, status);
+  const UAddr ad = uaddr(p);
+  boundary_cell<S, UAddr>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, status);
   const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
 #pragma unroll
@@ -158,179 +110,13 @@ __global__ __launch_bounds__(256) void k_init(S* __restrict__ dst, const uint8_t
   for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
 }
 
-// ---------------------------------------------------------------------------
-// mapping (Sec. 2.3): flags and owner of the cells of a region, from the
-// particle positions; region = whole grid (init) or a sphere's re-mapping box
-// ---------------------------------------------------------------------------
-__device__ int cell_owner(int x, int y, int z, const DevParticle* __restrict__ parts, int np,
-                          const SweepParams& p) {
-  for (int i = 0; i < np; ++i) {
-    double off[3];
-    sphere_offset(parts[i].x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
-    if (inside_sphere(off, parts[i].r)) return i;
-  }
-  return -1;
-}
-
-__device__ void map_cell(int x, int y, int z, uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
-                         const DevParticle* __restrict__ parts, int np, const SweepParams& p,
-                         int* __restrict__ status) {
-  const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
-  const int o = cell_owner(x, y, z, parts, np, p);
-  uint8_t f = 0;
-  int link = -1;
-  if (o >= 0) {
-    f = kSolid;
-    link = o;
-  } else {
-    const int n[3] = {p.nx, p.ny, p.nz};
-    for (int q = 1; q < kQ; ++q) {
-      int s[3] = {x + cx_of(q), y + cy_of(q), z + cz_of(q)};
-      bool wall = false;
-      for (int a = 0; a < 3; ++a)
-        if (s[a] < 0 || s[a] >= n[a]) {
-          if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-          else wall = true;
-        }
-      if (wall) { f |= kNearW; continue; }
-      const int so = cell_owner(s[0], s[1], s[2], parts, np, p);
-      if (so >= 0) {
-        if (link >= 0 && link != so) status[kStatusRange] = 4;
-        if (link < 0) link = so;
-        f |= kNearP;
-      }
-    }
-  }
-  flags[c] = f;
-  owner[c] = link < 0 ? 0 : (uint16_t)link;
-}
-
 __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
                                                  const DevParticle* __restrict__ parts, int np, SweepParams p,
                                                  int* __restrict__ status) {
   const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= p.N) return;
   const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / ((uint32_t)p.nx * p.ny);
-  map_cell(x, y, z, flags, owner, parts, np, p, status);
-}
-
-__global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
-                                               const DevParticle* __restrict__ parts, int np, SweepParams p,
-                                               int* __restrict__ status) {
-  const int pi = blockIdx.y;
-  const DevParticle& P = parts[pi];
-  if (P.fixed) return;
-  const int rb = p.box + 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= rb * rb * rb) return;
-  int x, y, z;
-  if (!box_cell(P.remap_lo, k, rb, p, x, y, z)) return;
-  map_cell(x, y, z, flags, owner, parts, np, p, status);
-}
-
-// ---------------------------------------------------------------------------
-// refill of cells uncovered by a moving sphere (Sec. 2.3, after Dorschner):
-// rho = mean density of the D3Q19 neighbours that held fluid before the
-// re-mapping; v = rigid-body velocity; strain rate S from central differences
-// over the axis neighbours (fluid velocity where the neighbour held fluid,
-// rigid-body velocity of its sphere or the wall velocity otherwise);
-// f = f^eq(rho, v) - 3 w_q / s+ (c c - I/3) : S, then collided.  Runs before
-// the flags are updated, so flags/owner still describe the old mapping.
-// ---------------------------------------------------------------------------
-template <typename S>
-__global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uint8_t* __restrict__ flags,
-                                                const uint16_t* __restrict__ owner,
-                                                const DevParticle* __restrict__ parts, int np, SweepParams p) {
-  using T = typename Store<S>::T;
-  const int pi = blockIdx.y;
-  const DevParticle& P = parts[pi];
-  if (P.fixed) return;
-  const int rb = p.box + 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= rb * rb * rb) return;
-  int x, y, z;
-  if (!box_cell(P.remap_lo, k, rb, p, x, y, z)) return;
-  const uint32_t N = p.N;
-  const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
-  if (!(flags[c] & kSolid) || owner[c] != pi) return;
-  if (cell_owner(x, y, z, parts, np, p) >= 0) return;   // still covered
-  const int n[3] = {p.nx, p.ny, p.nz};
-  // density from old-fluid neighbours
-  double rsum = 0.0;
-  int cnt = 0;
-  for (int q = 1; q < kQ; ++q) {
-    int s[3] = {x + cx_of(q), y + cy_of(q), z + cz_of(q)};
-    bool out = false;
-    for (int a = 0; a < 3; ++a)
-      if (s[a] < 0 || s[a] >= n[a]) {
-        if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-        else out = true;
-      }
-    if (out) continue;
-    const uint32_t sc = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
-    if (flags[sc] & kSolid) continue;
-    double r = 0.0;
-    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + sc]);
-    rsum += 1.0 + r;
-    ++cnt;
-  }
-  const double rho = cnt ? rsum / cnt : 1.0;
-  double off[3];
-  sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
-  const double v[3] = {P.u[0] + (P.w[1] * off[2] - P.w[2] * off[1]),
-                       P.u[1] + (P.w[2] * off[0] - P.w[0] * off[2]),
-                       P.u[2] + (P.w[0] * off[1] - P.w[1] * off[0])};
-  // velocity at the six axis neighbours
-  double Vn[3][2][3];
-  for (int a = 0; a < 3; ++a)
-    for (int side = 0; side < 2; ++side) {
-      int s[3] = {x, y, z};
-      s[a] += side ? 1 : -1;
-      double* V = Vn[a][side];
-      if (s[a] < 0 || s[a] >= n[a]) {
-        if (p.per[a]) s[a] = s[a] < 0 ? s[a] + n[a] : s[a] - n[a];
-        else {
-          for (int b = 0; b < 3; ++b) V[b] = (a == p.wall_axis) ? p.wall_v[side][b] : 0.0;
-          continue;
-        }
-      }
-      const uint32_t sc = ((uint32_t)s[2] * n[1] + s[1]) * n[0] + s[0];
-      if (!(flags[sc] & kSolid)) {
-        double j[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < kQ; ++q) {
-          const double dq = (double)Store<S>::load(state[(size_t)q * N + sc]);
-          j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
-        }
-        // post-collision momentum minus F/2 is the macroscopic velocity
-        for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
-      } else {
-        const DevParticle& Q = parts[owner[sc]];
-        double o2[3];
-        sphere_offset(Q.x, x + 0.5 + (a == 0 ? (side ? 1 : -1) : 0), y + 0.5 + (a == 1 ? (side ? 1 : -1) : 0),
-                      z + 0.5 + (a == 2 ? (side ? 1 : -1) : 0), n[0], n[1], n[2], p.per, o2);
-        V[0] = Q.u[0] + (Q.w[1] * o2[2] - Q.w[2] * o2[1]);
-        V[1] = Q.u[1] + (Q.w[2] * o2[0] - Q.w[0] * o2[2]);
-        V[2] = Q.u[2] + (Q.w[0] * o2[1] - Q.w[1] * o2[0]);
-      }
-    }
-  double Sab[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      Sab[a][b] = 0.25 * ((Vn[a][1][b] - Vn[a][0][b]) + (Vn[b][1][a] - Vn[b][0][a]));
-  const double trS = Sab[0][0] + Sab[1][1] + Sab[2][2];
-  const double usq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-  T d[kQ];
-  for (int q = 0; q < kQ; ++q) {
-    const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
-    const double cu = cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2];
-    double QS = -trS / 3.0;
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) QS += cq[a] * cq[b] * Sab[a][b];
-    const double w = w_of(q);
-    d[q] = T(w * (rho - 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) - 3.0 * w / p.sp * QS);
-  }
-  trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
-  for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store(d[q]);
+  map_cell<UAddr>(x, y, z, c, flags, owner, parts, np, p, uaddr(p), status);
 }
 
 // ---------------------------------------------------------------------------
@@ -454,8 +240,8 @@ hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, con
   hipError_t e = hipSuccess;
   if (np > 0) {
     const int cells = p.box * p.box * p.box;
-    k_boundary_particles<S><<<dim3((cells + 255) / 256, np), dim3(256), 0, st>>>(
-        (const S*)src, (S*)dst, flags, owner, parts, slots, status, p);
+    k_boundary_particles<S, UAddr><<<dim3((cells + 255) / 256, np), dim3(256), 0, st>>>(
+        (const S*)src, (S*)dst, flags, owner, parts, slots, status, p, uaddr(p));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -494,10 +280,10 @@ hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, con
                                const SweepParams& p, int* status, hipStream_t st) {
   const int rb = p.box + 1;
   dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
-  k_refill<S><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p);
+  k_refill<S, UAddr><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p, uaddr(p), status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  k_remap<<<grid, block, 0, st>>>(flags, owner, parts, np, p, status);
+  k_remap<UAddr><<<grid, block, 0, st>>>(flags, owner, parts, np, p, uaddr(p), status);
   return hipGetLastError();
 }
 
