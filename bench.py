@@ -112,6 +112,36 @@ def run_rising(pkg, steps):
     return out
 
 
+def run_refined(pkg, coarse_steps=500):
+    """Adaptive refinement workload: coarse 128x128x512, 3 levels (16^3
+    blocks), light sphere r=16 finest cells (density ratio 0.1, C_v 0.5,
+    Ga 250) rising from rest; layout checked every 4 coarse steps.  MLUPS
+    counts cell updates of all levels (2^l per coarse step on level l)."""
+    import torch
+    import synth
+    w = synth.refined()
+    out = {}
+    for st in ("f64", "f32"):
+        sim = pkg.Sim(w["config"], w["spheres"], storage=st, history=4 * coarse_steps)
+        sim.init()
+        blocks = [int(sim.level_blocks(l).shape[0]) for l in range(3)]
+        sim.step(2)
+        sim.sync()
+        cu0, _ = sim.stats()
+        t = timed_steps(sim, coarse_steps)
+        cu1, _ = sim.stats()
+        h = sim.history(0, 4 * coarse_steps)
+        out[st] = {"mlups": (cu1 - cu0) / t / 1e6, "ms_per_coarse_step": 1e3 * t / coarse_steps,
+                   "cell_updates_per_coarse_step": (cu1 - cu0) / coarse_steps, "blocks_at_start": blocks,
+                   "refinements": sim.refinements(), "z_rise": float(h[-1, 8] - w["spheres"][0]["x"][2]),
+                   "uz_final": float(h[-1, 11])}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["coarse_steps"] = coarse_steps
+    return out
+
+
 def run_adjoint(pkg, storage="f32"):
     """Drag gradient on a fixed sphere (128^3, r=10, 2000 steps, window
     1500..1999, checkpoints every 50): forward-with-checkpoints time vs
@@ -238,6 +268,8 @@ def main():
     if not args.no_extra:
         log("rising sphere 256^3")
         line["rising"] = run_rising(pkg, 2000)
+        log("refined 128x128x512, 3 levels")
+        line["refined"] = run_refined(pkg)
         log("adjoint 128^3")
         line["adjoint"] = run_adjoint(pkg)
         line["adjoint_cost"] = round(line["adjoint"]["cost_ratio"], 3)

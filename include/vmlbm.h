@@ -151,6 +151,15 @@ int vmlbm_stats(vmlbm_ctx* ctx, double* cell_updates, double* seconds);
 int vmlbm_profile(vmlbm_ctx* ctx, int enable);
 int vmlbm_sweep_time(vmlbm_ctx* ctx, double* seconds, long long* launches);
 
+/* Totals of the post-collision state over fluid cells: mass sum f~ and
+ * momentum sum c f~ (refined grid: every level weighted by its cell volume
+ * 8^-l in coarse units).  Deterministic device reduction; synchronises. */
+int vmlbm_totals(vmlbm_ctx* ctx, double* mass, double mom[3]);
+
+/* Uniform grid: post-collision populations of the cells of a box (periodic
+ * wrap), FP64 host array [19][size2][size1][size0]; solid cells read 0. */
+int vmlbm_read_box(vmlbm_ctx* ctx, const int lo[3], const int size[3], double* out);
+
 /* Cells of a level that are fluid, and fluid cells without any wall or
  * particle link (those the interior sweep updates). */
 int vmlbm_cell_counts(vmlbm_ctx* ctx, int level, long long* fluid, long long* interior);

@@ -116,7 +116,7 @@ struct RForest {
   }
 
   // leaf level of every finest block position from target levels, refined
-  // until neighbouring leaves differ by at most one level
+  // until leaves that touch (face, edge or corner) differ by at most one level
   std::vector<int> balance(std::vector<int> t) const {
     const long NB = (long)nb[0] * nb[1] * nb[2];
     std::vector<int> lf(NB);
@@ -147,16 +147,14 @@ struct RForest {
             const int l = lf[bpos(i, j, k)];
             const int s = 1 << (L - l);
             const int ni = (i / s) * s, nj = (j / s) * s, nk = (k / s) * s;   // leaf node origin
+            // deepest leaf touching this one: the positions of the one-wide
+            // shell around the leaf node
             int mx = 0;
-            for (int dz = -1; dz <= 1; ++dz)
-              for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                  if (!dx && !dy && !dz) continue;
-                  for (int c = 0; c < s; ++c)
-                    for (int bb = 0; bb < s; ++bb)
-                      for (int a = 0; a < s; ++a)
-                        mx = std::max(mx, lf[bpos(wrap(ni + dx * s + a, nb[0]), wrap(nj + dy * s + bb, nb[1]),
-                                                  wrap(nk + dz * s + c, nb[2]))]);
+            for (int c = -1; c <= s; ++c)
+              for (int bb = -1; bb <= s; ++bb)
+                for (int a = -1; a <= s; ++a) {
+                  if (a >= 0 && a < s && bb >= 0 && bb < s && c >= 0 && c < s) continue;
+                  mx = std::max(mx, lf[bpos(wrap(ni + a, nb[0]), wrap(nj + bb, nb[1]), wrap(nk + c, nb[2]))]);
                 }
             if (mx > l + 1 && t[bpos(i, j, k)] < mx - 1) {
               t[bpos(i, j, k)] = mx - 1;
@@ -170,12 +168,13 @@ struct RForest {
   std::vector<int> targets() const {
     std::vector<int> t = base;
     // Sec. 4.2.1: blocks intersecting the sphere's bounding box grown by one
-    // finest block edge are on the finest level
+    // finest block edge are on the finest level (reading: the open box, so a
+    // block that only touches its face is not included)
     for (const Sph& s : sph) {
       int lo[3], hi[3];
       for (int a = 0; a < 3; ++a) {
         lo[a] = (int)std::floor((s.x[a] - s.r - b) / b);
-        hi[a] = (int)std::floor((s.x[a] + s.r + b) / b);
+        hi[a] = (int)std::ceil((s.x[a] + s.r + b) / b) - 1;
       }
       for (int k = lo[2]; k <= hi[2]; ++k)
         for (int j = lo[1]; j <= hi[1]; ++j)

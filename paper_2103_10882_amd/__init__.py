@@ -24,7 +24,7 @@ EXPORTS = [
     "vmlbm_set_stream", "vmlbm_init_equilibrium", "vmlbm_step", "vmlbm_sync", "vmlbm_get_particle",
     "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
-    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
+    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
 ]
 
@@ -82,6 +82,8 @@ def lib():
             "vmlbm_profile": [vp, ctypes.c_int],
             "vmlbm_sweep_time": [vp, vp, vp],
             "vmlbm_cell_counts": [vp, ctypes.c_int, vp, vp],
+            "vmlbm_totals": [vp, vp, vp],
+            "vmlbm_read_box": [vp, vp, vp, vp],
             "vmlbm_level_blocks": [vp, ctypes.c_int, vp, vp],
             "vmlbm_refinements": [vp, vp],
             "vmlbm_set_params": [vp, ctypes.c_double, ctypes.c_double],
@@ -263,6 +265,19 @@ class Sim:
         s, n = ctypes.c_double(), ctypes.c_longlong()
         self._check(self.L.vmlbm_sweep_time(self.h, ctypes.byref(s), ctypes.byref(n)), "sweep_time")
         return s.value, n.value
+
+    def totals(self):
+        m = np.zeros(1)
+        j = np.zeros(3)
+        self._check(self.L.vmlbm_totals(self.h, _ptr(m), _ptr(j)), "totals")
+        return float(m[0]), j
+
+    def read_box(self, lo, size):
+        lo = np.ascontiguousarray(lo, dtype=np.int32)
+        size = np.ascontiguousarray(size, dtype=np.int32)
+        out = np.zeros((19, int(size[2]), int(size[1]), int(size[0])))
+        self._check(self.L.vmlbm_read_box(self.h, _ptr(lo), _ptr(size), _ptr(out)), "read_box")
+        return out
 
     def cell_counts(self, level=0):
         f, i = ctypes.c_longlong(), ctypes.c_longlong()

@@ -55,6 +55,7 @@ void plan_uniform(vmlbm_ctx* c) {
   c->off_parts = take(std::max(np, 1) * sizeof(DevParticle));
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
   c->off_hist = take((size_t)std::max(g.history, 1) * std::max(np, 1) * 12 * sizeof(double));
+  c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
   adjoint_plan(c, take);
   c->ws_needed = off;
 }
@@ -544,6 +545,73 @@ int vmlbm_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* inte
   }
   if (fluid) *fluid = nf;
   if (interior) *interior = ni;
+  return VMLBM_OK;
+}
+
+int vmlbm_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (c->cfg.block > 0) return refine_totals(c, mass, mom);
+  const uint32_t N = (uint32_t)((size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2]);
+  double* part = (double*)(c->ws + c->off_totals);
+  HIP_TRY(c, launch_totals(c->cfg.storage, c->ws + c->off_pdf[c->cur], c->use_flags ? c->flags() : nullptr, N, N,
+                           nullptr, 0, part, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::vector<double> h((size_t)kTotalsGroups * 8);
+  HIP_TRY(c, hipMemcpy(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  long double n = 0, m = 0, j[3] = {0, 0, 0};
+  for (int g = 0; g < kTotalsGroups; ++g) {
+    n += h[8 * g]; m += h[8 * g + 1];
+    for (int a = 0; a < 3; ++a) j[a] += h[8 * g + 2 + a];
+  }
+  if (mass) *mass = (double)(n + m);
+  if (mom) for (int a = 0; a < 3; ++a) mom[a] = (double)j[a];
+  return VMLBM_OK;
+}
+
+int vmlbm_read_box(vmlbm_ctx* c, const int lo[3], const int size[3], double* out) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!lo || !size || !out) return VMLBM_EINVAL;
+  if (c->cfg.block > 0) return fail(c, VMLBM_EINVAL, "box read-back is for the uniform grid");
+  const int* n = c->cfg.n;
+  for (int a = 0; a < 3; ++a)
+    if (size[a] <= 0 || size[a] > n[a]) return fail(c, VMLBM_EINVAL, "bad box size");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t N = (size_t)n[0] * n[1] * n[2];
+  const size_t S = storage_bytes(c->cfg.storage);
+  const char* base = c->ws + c->off_pdf[c->cur];
+  std::vector<char> row((size_t)size[0] * S);
+  std::vector<uint8_t> frow(size[0], 0);
+  const size_t cells = (size_t)size[0] * size[1] * size[2];
+  for (int q = 0; q < 19; ++q)
+    for (int k = 0; k < size[2]; ++k)
+      for (int j = 0; j < size[1]; ++j) {
+        const int z = ((lo[2] + k) % n[2] + n[2]) % n[2], y = ((lo[1] + j) % n[1] + n[1]) % n[1];
+        const int x0 = ((lo[0] % n[0]) + n[0]) % n[0];
+        const int first = std::min(size[0], n[0] - x0);
+        const size_t r = ((size_t)z * n[1] + y) * n[0];
+        HIP_TRY(c, hipMemcpy(row.data(), base + (q * N + r + x0) * S, first * S, hipMemcpyDeviceToHost));
+        if (first < size[0])
+          HIP_TRY(c, hipMemcpy(row.data() + first * S, base + (q * N + r) * S, (size[0] - first) * S,
+                               hipMemcpyDeviceToHost));
+        if (q == 0 && c->use_flags) {
+          HIP_TRY(c, hipMemcpy(frow.data(), c->flags() + r + x0, first, hipMemcpyDeviceToHost));
+          if (first < size[0]) HIP_TRY(c, hipMemcpy(frow.data() + first, c->flags() + r, size[0] - first,
+                                                    hipMemcpyDeviceToHost));
+        }
+        for (int i = 0; i < size[0]; ++i) {
+          const size_t o = (size_t)q * cells + ((size_t)k * size[1] + j) * size[0] + i;
+          out[o] = w_of(q) + dev_to_double(row.data(), c->cfg.storage, i);
+        }
+        if (q == 0)
+          for (int i = 0; i < size[0]; ++i)
+            if (frow[i] & kSolid) out[((size_t)k * size[1] + j) * size[0] + i] = -1.0;
+      }
+  // solid cells: all 19 read 0 (marked through q = 0 above)
+  for (size_t cc = 0; cc < cells; ++cc)
+    if (out[cc] == -1.0)
+      for (int q = 0; q < 19; ++q) out[q * cells + cc] = 0.0;
   return VMLBM_OK;
 }
 

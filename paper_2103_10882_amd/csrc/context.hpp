@@ -34,7 +34,7 @@ struct vmlbm_ctx {
 
   // uniform-grid workspace carving
   size_t off_status = 0, off_pdf[2] = {0, 0}, off_flags = 0, off_owner = 0, off_parts = 0, off_slots = 0,
-         off_hist = 0;
+         off_hist = 0, off_totals = 0;
   int cur = 0;
   int box = 0;
   size_t slot_stride = 0;
@@ -87,6 +87,13 @@ int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEven
 size_t storage_bytes(int storage);
 
 int uniform_step(vmlbm_ctx* c, int nsteps);
+
+// deterministic sums over cells: kTotalsGroups workgroup partials of
+// (fluid cells, sum d, sum c d) per call
+constexpr int kTotalsGroups = 1024;
+hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uint32_t N, uint32_t cells,
+                         const int* slot_list, int nslots, double* partials, hipStream_t st);
+int refine_totals(vmlbm_ctx* c, double* mass, double mom[3]);
 
 // adjoint (adjoint.hip)
 void adjoint_plan(vmlbm_ctx* c, const Take& take);

@@ -20,8 +20,10 @@
 // check_every coarse steps and data moves between levels by copying a cell to
 // its children or averaging them.  Domains are periodic.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "common.hpp"
@@ -56,6 +58,7 @@ struct Forest {
   int nb0[3] = {0, 0, 0};     // coarse block positions
   int nbL[3] = {0, 0, 0};     // finest block positions
   std::vector<int8_t> leaf, base;
+  std::vector<int> boxes;     // sphere block ranges the current layout was built for
   int refinements = 0;
   long long coarse_steps = 0;
   struct Lev {
@@ -86,34 +89,105 @@ struct Forest {
     const int s = L - l;
     return lf[lpos(bi << s, bj << s, bk << s)];
   }
-  // leaf level of the region holding level-l cell (i, j, k)
-  int leaf_cell(const std::vector<int8_t>& lf, int l, int i, int j, int k) const {
-    return leaf_block(lf, l, wrap(i, lv[l].n[0]) >> 4, wrap(j, lv[l].n[1]) >> 4, wrap(k, lv[l].n[2]) >> 4);
-  }
 };
 
 namespace {
 
 enum CellKind { K_INTERIOR, K_GHOST, K_COARSER, K_FINER };
 
-int cell_kind(const Forest& f, int l, int i, int j, int k) {
-  const int lf = f.leaf_cell(f.leaf, l, i, j, k);
-  if (lf == l) return K_INTERIOR;
-  if (lf > l) return K_FINER;
-  if (l >= 1 && lf == l - 1) {
-    const int pi = f.wrap(i, f.lv[l].n[0]) >> 1, pj = f.wrap(j, f.lv[l].n[1]) >> 1,
-              pk = f.wrap(k, f.lv[l].n[2]) >> 1;
-    for (int dz = -1; dz <= 1; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx)
-          if (f.leaf_cell(f.leaf, l - 1, pi + dx, pj + dy, pk + dz) == l) return K_GHOST;
+// Cell kinds of every level for the current leaf field and slot tables.
+// Leaves per block position are cached (octree: all finest positions under a
+// block agree on "== l" and "> l").  A cell inside a level-(l-1) leaf is a
+// ghost when its parent has a level-l leaf among its 27 neighbours; the parent
+// neighbourhood of local cell x spans level-l cells 2(x>>1)-2 .. 2(x>>1)+3,
+// i.e. the own block and the block below for x < 2, above for x > 13.  Only
+// ghost blocks hold ghost cells; their kinds are tabulated once per layout.
+struct Kinds {
+  const Forest& f;
+  std::vector<std::vector<int8_t>> lb;
+  std::vector<std::vector<uint8_t>> gk;   // per level: [ghost slot - n_int][4096]
+  explicit Kinds(const Forest& fr) : f(fr), lb(fr.L + 1), gk(fr.L + 1) {
+    for (int l = 0; l <= f.L; ++l) {
+      const Forest::Lev& V = f.lv[l];
+      lb[l].resize((size_t)V.npos);
+      for (int k = 0; k < V.nb[2]; ++k)
+        for (int j = 0; j < V.nb[1]; ++j)
+          for (int i = 0; i < V.nb[0]; ++i)
+            lb[l][((size_t)k * V.nb[1] + j) * V.nb[0] + i] = (int8_t)f.leaf_block(f.leaf, l, i, j, k);
+    }
   }
-  return K_COARSER;
-}
+  static int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+  size_t bpos(int l, int bi, int bj, int bk) const {
+    const Forest::Lev& V = f.lv[l];
+    bi = wrap1(bi, V.nb[0]); bj = wrap1(bj, V.nb[1]); bk = wrap1(bk, V.nb[2]);
+    return ((size_t)bk * V.nb[1] + bj) * V.nb[0] + bi;
+  }
+  int block(int l, int bi, int bj, int bk) const { return lb[l][bpos(l, bi, bj, bk)]; }
+  // after the slot tables of every level are set
+  void tabulate_ghosts() {
+    for (int l = 1; l <= f.L; ++l) {
+      const Forest::Lev& V = f.lv[l];
+      const size_t n_int = V.interior.size();
+      gk[l].assign(V.ghost.size() * kBlockCells, K_COARSER);
+      for (size_t g = 0; g < V.ghost.size(); ++g) {
+        const int s = V.ghost[g];
+        const int bi = V.pos[3 * s], bj = V.pos[3 * s + 1], bk = V.pos[3 * s + 2];
+        bool nb[27];
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx)
+              nb[(dz + 1) * 9 + (dy + 1) * 3 + dx + 1] = block(l, bi + dx, bj + dy, bk + dz) == l;
+        uint8_t* out = gk[l].data() + (size_t)(s - n_int) * kBlockCells;
+        for (int z = 0; z < kBlock; ++z) {
+          const int z0 = z < 2 ? 0 : 1, z1 = z > 13 ? 2 : 1;
+          for (int y = 0; y < kBlock; ++y) {
+            const int y0 = y < 2 ? 0 : 1, y1 = y > 13 ? 2 : 1;
+            for (int x = 0; x < kBlock; ++x) {
+              const int x0 = x < 2 ? 0 : 1, x1 = x > 13 ? 2 : 1;
+              bool g2 = false;
+              for (int c = z0; c <= z1 && !g2; ++c)
+                for (int b = y0; b <= y1 && !g2; ++b)
+                  for (int a = x0; a <= x1 && !g2; ++a) g2 = nb[c * 9 + b * 3 + a];
+              out[(z * kBlock + y) * kBlock + x] = g2 ? K_GHOST : K_COARSER;
+            }
+          }
+        }
+      }
+    }
+  }
+  int kind(int l, int i, int j, int k) const {
+    const Forest::Lev& V = f.lv[l];
+    i = wrap1(i, V.n[0]); j = wrap1(j, V.n[1]); k = wrap1(k, V.n[2]);
+    const size_t p = ((size_t)(k >> 4) * V.nb[1] + (j >> 4)) * V.nb[0] + (i >> 4);
+    const int lf = lb[l][p];
+    if (lf == l) return K_INTERIOR;
+    if (lf > l) return K_FINER;
+    if (lf < l - 1) return K_COARSER;
+    const int s = V.slot_of[p];
+    if (s < 0) return K_COARSER;
+    return gk[l][(size_t)(s - (int)V.interior.size()) * kBlockCells + (((k & 15) * kBlock + (j & 15)) * kBlock + (i & 15))];
+  }
+  // any level-l cell in [i-2, i+2]^3 inside a finer leaf
+  bool near_finer(int l, int i, int j, int k) const {
+    const Forest::Lev& V = f.lv[l];
+    int b0[3], b1[3];
+    const int c[3] = {i, j, k};
+    for (int a = 0; a < 3; ++a) {
+      b0[a] = wrap1(c[a] - 2, V.n[a]) >> 4;
+      b1[a] = wrap1(c[a] + 2, V.n[a]) >> 4;
+    }
+    for (int z = 0; z < 2; ++z)
+      for (int y = 0; y < 2; ++y)
+        for (int x = 0; x < 2; ++x)
+          if (block(l, x ? b1[0] : b0[0], y ? b1[1] : b0[1], z ? b1[2] : b0[2]) > l) return true;
+    return false;
+  }
+};
 
 // Leaf level per finest block position from targets: a node of level l is
-// split when any target inside exceeds l; nodes whose 26 neighbours hold
-// leaves more than one level finer are split too, until nothing changes.
+// split when any target inside exceeds l; leaves touched (face, edge or
+// corner) by leaves more than one level finer are split too, until nothing
+// changes.
 std::vector<int8_t> balance_layout(const Forest& f, std::vector<int8_t> t) {
   const int L = f.L;
   const long NB = (long)f.nbL[0] * f.nbL[1] * f.nbL[2];
@@ -149,77 +223,228 @@ std::vector<int8_t> balance_layout(const Forest& f, std::vector<int8_t> t) {
           }
           lf[f.lpos(i, j, k)] = (int8_t)l;
         }
-    // 2:1 over the 26 neighbours of every leaf node, with a pyramid of the
-    // finest leaf level inside each node
-    std::vector<std::vector<int8_t>> lm(L + 1);
-    lm[L] = lf;
-    for (int l = L - 1; l >= 0; --l) {
-      int d[3], e[3];
-      node_dims(l, d);
-      node_dims(l + 1, e);
-      lm[l].assign((long)d[0] * d[1] * d[2], 0);
-      for (int k = 0; k < e[2]; ++k)
-        for (int j = 0; j < e[1]; ++j)
-          for (int i = 0; i < e[0]; ++i) {
-            int8_t& m = lm[l][((long)(k >> 1) * d[1] + (j >> 1)) * d[0] + (i >> 1)];
-            m = std::max(m, lm[l + 1][((long)k * e[1] + j) * e[0] + i]);
-          }
-    }
+    // 2:1: the deepest leaf touching each leaf node (face, edge or corner)
+    // lies in the one-position shell around it
     bool changed = false;
     for (int k = 0; k < f.nbL[2]; ++k)
       for (int j = 0; j < f.nbL[1]; ++j)
         for (int i = 0; i < f.nbL[0]; ++i) {
           const int l = lf[f.lpos(i, j, k)];
-          const int s = L - l;
-          if ((i & ((1 << s) - 1)) || (j & ((1 << s) - 1)) || (k & ((1 << s) - 1))) continue;  // node origin only
-          int d[3];
-          node_dims(l, d);
+          const int S = 1 << (L - l);
+          if ((i & (S - 1)) || (j & (S - 1)) || (k & (S - 1))) continue;   // node origin only
           int m = 0;
-          for (int dz = -1; dz <= 1; ++dz)
-            for (int dy = -1; dy <= 1; ++dy)
-              for (int dx = -1; dx <= 1; ++dx) {
-                if (!dx && !dy && !dz) continue;
-                const int ni = f.wrap((i >> s) + dx, d[0]), nj = f.wrap((j >> s) + dy, d[1]),
-                          nk = f.wrap((k >> s) + dz, d[2]);
-                m = std::max(m, (int)lm[l][((long)nk * d[1] + nj) * d[0] + ni]);
+          for (int c = -1; c <= S; ++c)
+            for (int b = -1; b <= S; ++b)
+              for (int a = -1; a <= S; ++a) {
+                if (a >= 0 && a < S && b >= 0 && b < S && c >= 0 && c < S) continue;
+                m = std::max(m, (int)lf[f.lpos(f.wrap(i + a, f.nbL[0]), f.wrap(j + b, f.nbL[1]),
+                                               f.wrap(k + c, f.nbL[2]))]);
               }
-          if (m > l + 1) {
-            const int S = 1 << s;
+          if (m > l + 1)
             for (int c = 0; c < S; ++c)
-              for (int bb = 0; bb < S; ++bb)
+              for (int b = 0; b < S; ++b)
                 for (int a = 0; a < S; ++a) {
-                  int8_t& tv = t[f.lpos(i + a, j + bb, k + c)];
+                  int8_t& tv = t[f.lpos(i + a, j + b, k + c)];
                   if (tv < m - 1) { tv = (int8_t)(m - 1); changed = true; }
                 }
-          }
         }
     if (!changed) return lf;
   }
   return lf;
 }
 
-std::vector<int8_t> layout_targets(const vmlbm_ctx* c, const Forest& f, const std::vector<vmlbm_sphere>& sph) {
-  std::vector<int8_t> t = f.base;
+// finest block ranges [lo, hi] meeting the open box (x - r - b, x + r + b) of
+// every sphere: the layout is a function of these ranges and the static
+// regions only
+std::vector<int> sphere_boxes(const std::vector<vmlbm_sphere>& sph) {
   const int b = kBlock;
+  std::vector<int> box;
+  box.reserve(6 * sph.size());
   for (const auto& s : sph) {
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      lo[a] = (int)std::floor((s.x[a] - s.radius - b) / b);
-      hi[a] = (int)std::floor((s.x[a] + s.radius + b) / b);
-    }
+    for (int a = 0; a < 3; ++a) box.push_back((int)std::floor((s.x[a] - s.radius - b) / b));
+    for (int a = 0; a < 3; ++a) box.push_back((int)std::ceil((s.x[a] + s.radius + b) / b) - 1);
+  }
+  return box;
+}
+
+std::vector<int8_t> layout_targets(const Forest& f, const std::vector<int>& box) {
+  std::vector<int8_t> t = f.base;
+  for (size_t s = 0; s < box.size(); s += 6) {
+    const int* lo = &box[s];
+    const int* hi = &box[s + 3];
     for (int k = lo[2]; k <= hi[2]; ++k)
       for (int j = lo[1]; j <= hi[1]; ++j)
         for (int i = lo[0]; i <= hi[0]; ++i)
           t[f.lpos(f.wrap(i, f.nbL[0]), f.wrap(j, f.nbL[1]), f.wrap(k, f.nbL[2]))] = (int8_t)f.L;
   }
-  (void)c;
   return t;
+}
+
+// Coalescence entries of one interior level-l block next to the finer
+// region.  Returns 0, 1 (a cell pulls from an uncovered coarser cell) or 2
+// (children of a coalescence cell are not in a ghost block).
+int iface_block(const Kinds& K, const Forest& f, int l, int s, std::vector<IfaceEntry>& out) {
+  const Forest::Lev& V = f.lv[l];
+  const Forest::Lev& Fl = f.lv[l + 1];
+  const int bi = V.pos[3 * s], bj = V.pos[3 * s + 1], bk = V.pos[3 * s + 2];
+  for (int lz = 0; lz < kBlock; ++lz)
+    for (int ly = 0; ly < kBlock; ++ly)
+      for (int lx = 0; lx < kBlock; ++lx) {
+        const int i = bi * kBlock + lx, j = bj * kBlock + ly, k = bk * kBlock + lz;
+        if (!K.near_finer(l, i, j, k)) continue;
+        IfaceEntry e{};
+        bool special = false, anymask = false;
+        int child_kind[8];
+        for (int m = 0; m < 8; ++m)
+          child_kind[m] = K.kind(l + 1, 2 * i + (m & 1), 2 * j + ((m >> 1) & 1), 2 * k + (m >> 2));
+        for (int q = 0; q < kQ; ++q) {
+          const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+          const int si = i - cq[0], sj = j - cq[1], sk = k - cq[2];
+          const int ks = K.kind(l, si, sj, sk);
+          float wgt = 1.0f;
+          if (ks == K_INTERIOR) {
+            int nin = 0;
+            for (int m = 0; m < 8; ++m) {
+              const int gi = 2 * si + (m & 1), gj = 2 * sj + ((m >> 1) & 1), gk = 2 * sk + (m >> 2);
+              if (K.kind(l + 1, gi + cq[0], gj + cq[1], gk + cq[2]) == K_INTERIOR) ++nin;
+            }
+            wgt = 1.0f - nin / 8.0f;
+          } else if (ks == K_FINER) {
+            wgt = 0.0f;
+          } else if (ks == K_COARSER) {
+            return 1;
+          }
+          uint8_t mask = 0;
+          for (int m = 0; m < 8; ++m) {
+            if (child_kind[m] != K_GHOST) continue;
+            const int gi = 2 * i + (m & 1), gj = 2 * j + ((m >> 1) & 1), gk = 2 * k + (m >> 2);
+            const int k1 = K.kind(l + 1, gi - cq[0], gj - cq[1], gk - cq[2]);
+            if (k1 == K_INTERIOR ||
+                (k1 == K_GHOST && K.kind(l + 1, gi - 2 * cq[0], gj - 2 * cq[1], gk - 2 * cq[2]) == K_INTERIOR))
+              mask |= (uint8_t)(1u << m);
+          }
+          e.weight[q] = wgt;
+          e.mask[q] = mask;
+          special = special || wgt != 1.0f || mask;
+          anymask = anymask || mask;
+        }
+        if (!special) continue;
+        e.slot = s;
+        e.local = (lz * kBlock + ly) * kBlock + lx;
+        e.fine_slot = -1;
+        e.fine_local = 0;
+        if (anymask) {
+          const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
+          const long fp = ((long)(fk >> 4) * Fl.nb[1] + (fj >> 4)) * Fl.nb[0] + (fi >> 4);
+          const int fs = Fl.slot_of[fp];
+          if (fs < (int)Fl.interior.size()) return 2;
+          e.fine_slot = fs;
+          e.fine_local = (((fk & 15) * kBlock) + (fj & 15)) * kBlock + (fi & 15);
+        }
+        out.push_back(e);
+      }
+  return 0;
+}
+
+// Per-level block-slot and coalescence-table capacities for every position
+// the spheres can reach.  The layout around one sphere is unchanged by a
+// shift of a whole coarse node (2^L finest blocks), it grows with the width
+// of the sphere's block range, and for a box of targets the 2:1 balance acts
+// on each axis separately.  Hence the per-axis extent of each level's region
+// (leaves of that level or finer), maximised over the 2^L offsets of the
+// widest block range within a coarse node, bounds the region for any
+// position; slots lie within one block of it, coalescence cells in the
+// blocks next to the finer region.  Spheres add their bounds to the blocks
+// the static regions need.
+void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<long>& icap) {
+  const int L = f.L, b = kBlock;
+  cap.assign(L + 1, 0);
+  icap.assign(L + 1, 0);
+  // blocks of the static regions alone
+  {
+    const std::vector<int8_t> keep = f.leaf;
+    f.leaf = balance_layout(f, f.base);
+    Kinds K(f);
+    for (int l = 0; l <= L; ++l) {
+      const Forest::Lev& V = f.lv[l];
+      for (int k = 0; k < V.nb[2]; ++k)
+        for (int j = 0; j < V.nb[1]; ++j)
+          for (int i = 0; i < V.nb[0]; ++i) {
+            const int lf = K.block(l, i, j, k);
+            bool slot = lf == l, near = false;
+            for (int dz = -1; dz <= 1; ++dz)
+              for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                  const int m = K.block(l, i + dx, j + dy, k + dz);
+                  if (l >= 1 && lf == l - 1 && m == l) slot = true;
+                  if (lf == l && m > l) near = true;
+                }
+            cap[l] += slot;
+            icap[l] += near ? kBlockCells : 0;
+          }
+    }
+    f.leaf = keep;
+  }
+  const int node = 1 << L;   // coarse node edge in finest blocks
+  for (const auto& s : c->spheres) {
+    const int w = (int)std::ceil(2.0 * (s.radius + b) / b) + 1;   // widest block range
+    std::vector<std::array<int, 3>> ext(L + 1, {0, 0, 0}), iext(L + 1, {0, 0, 0});
+    for (int o = 0; o < node; ++o) {
+      std::vector<int8_t> t(f.base.size(), 0);
+      int lo[3];
+      for (int a = 0; a < 3; ++a) lo[a] = (f.nbL[a] / 2 / node) * node + o;
+      for (int k = 0; k < w; ++k)
+        for (int j = 0; j < w; ++j)
+          for (int i = 0; i < w; ++i)
+            t[f.lpos(f.wrap(lo[0] + i, f.nbL[0]), f.wrap(lo[1] + j, f.nbL[1]), f.wrap(lo[2] + k, f.nbL[2]))] =
+                (int8_t)L;
+      const std::vector<int8_t> lf = balance_layout(f, t);
+      for (int l = 1; l <= L; ++l) {
+        // projections of {leaf >= l} onto the axes, in level-l and level-(l-1) blocks
+        const int sh = L - l;
+        std::vector<std::vector<char>> pl(3), pc(3);
+        for (int a = 0; a < 3; ++a) {
+          pl[a].assign(f.lv[l].nb[a], 0);
+          pc[a].assign(f.lv[l - 1].nb[a], 0);
+        }
+        for (int k = 0; k < f.nbL[2]; ++k)
+          for (int j = 0; j < f.nbL[1]; ++j)
+            for (int i = 0; i < f.nbL[0]; ++i)
+              if (lf[f.lpos(i, j, k)] >= l) {
+                const int q[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                  pl[a][q[a] >> sh] = 1;
+                  pc[a][q[a] >> (sh + 1)] = 1;
+                }
+              }
+        for (int a = 0; a < 3; ++a) {
+          ext[l][a] = std::max(ext[l][a], (int)std::count(pl[a].begin(), pl[a].end(), 1));
+          iext[l - 1][a] = std::max(iext[l - 1][a], (int)std::count(pc[a].begin(), pc[a].end(), 1));
+        }
+      }
+    }
+    for (int l = 1; l <= L; ++l) {
+      long n = 1;
+      for (int a = 0; a < 3; ++a) n *= std::min(f.lv[l].nb[a], ext[l][a] + 2);
+      cap[l] += n;
+    }
+    for (int l = 0; l < L; ++l) {
+      long n = 1;
+      for (int a = 0; a < 3; ++a) n *= std::min(f.lv[l].nb[a], iext[l][a] + 2);
+      icap[l] += n * kBlockCells;
+    }
+  }
+  for (int l = 0; l <= L; ++l) {
+    cap[l] = std::min<long>(f.lv[l].npos, cap[l] + 64);
+    icap[l] = std::min<long>((long)cap[l] * kBlockCells, icap[l] + 4096);
+  }
 }
 
 // slot lists, ghost blocks, explosion map and coalescence table of every
 // level for the current leaf field
 int build_tables(vmlbm_ctx* c, Forest& f) {
   const int L = f.L;
+  Kinds K(f);
   for (int l = 0; l <= L; ++l) {
     Forest::Lev& V = f.lv[l];
     V.slot_of.assign(V.npos, -1);
@@ -231,7 +456,7 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
       for (int j = 0; j < V.nb[1]; ++j)
         for (int i = 0; i < V.nb[0]; ++i) {
           const long p = ((long)k * V.nb[1] + j) * V.nb[0] + i;
-          const int lf = f.leaf_block(f.leaf, l, i, j, k);
+          const int lf = K.block(l, i, j, k);
           if (lf == l) {
             V.slot_of[p] = (int)V.interior.size();
             V.interior.push_back(V.slot_of[p]);
@@ -243,7 +468,7 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
             for (int dz = -1; dz <= 1 && !g; ++dz)
               for (int dy = -1; dy <= 1 && !g; ++dy)
                 for (int dx = -1; dx <= 1 && !g; ++dx)
-                  if (f.leaf_block(f.leaf, l, i + dx, j + dy, k + dz) == l) g = true;
+                  if (K.block(l, i + dx, j + dy, k + dz) == l) g = true;
             if (g) gpos.insert(gpos.end(), {i, j, k});
           }
         }
@@ -257,6 +482,7 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
     if (V.cap && nslots > V.cap)
       return fail(c, VMLBM_ERANGE, "level %d needs %d block slots, capacity %d", l, nslots, V.cap);
   }
+  K.tabulate_ghosts();
   // explosion: ghost block of level l+1 -> parent interior block of level l
   for (int l = 1; l <= L; ++l) {
     Forest::Lev& V = f.lv[l];
@@ -272,78 +498,34 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
     }
   }
   // coalescence table: interior cells of level l within two cells of the
-  // level-(l+1) region whose pull differs from plain streaming
+  // level-(l+1) region whose pull differs from plain streaming; blocks are
+  // independent and split over host threads, entries kept in block order
   for (int l = 0; l < L; ++l) {
     Forest::Lev& V = f.lv[l];
-    const Forest::Lev& Fl = f.lv[l + 1];
-    V.iface.clear();
+    std::vector<int> near;
     for (int s : V.interior) {
       const int bi = V.pos[3 * s], bj = V.pos[3 * s + 1], bk = V.pos[3 * s + 2];
-      bool near = false;
-      for (int dz = -1; dz <= 1 && !near; ++dz)
-        for (int dy = -1; dy <= 1 && !near; ++dy)
-          for (int dx = -1; dx <= 1 && !near; ++dx)
-            if (f.leaf_block(f.leaf, l, bi + dx, bj + dy, bk + dz) > l) near = true;
-      if (!near) continue;
-      for (int lz = 0; lz < kBlock; ++lz)
-        for (int ly = 0; ly < kBlock; ++ly)
-          for (int lx = 0; lx < kBlock; ++lx) {
-            const int i = bi * kBlock + lx, j = bj * kBlock + ly, k = bk * kBlock + lz;
-            bool cand = false;
-            for (int dz = -2; dz <= 2 && !cand; ++dz)
-              for (int dy = -2; dy <= 2 && !cand; ++dy)
-                for (int dx = -2; dx <= 2 && !cand; ++dx)
-                  if (f.leaf_cell(f.leaf, l, i + dx, j + dy, k + dz) > l) cand = true;
-            if (!cand) continue;
-            IfaceEntry e{};
-            bool special = false;
-            for (int q = 0; q < kQ; ++q) {
-              const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
-              const int si = i - cq[0], sj = j - cq[1], sk = k - cq[2];
-              const int ks = cell_kind(f, l, si, sj, sk);
-              float wgt = 1.0f;
-              if (ks == K_INTERIOR) {
-                int nin = 0;
-                for (int m = 0; m < 8; ++m) {
-                  const int gi = 2 * si + (m & 1), gj = 2 * sj + ((m >> 1) & 1), gk = 2 * sk + (m >> 2);
-                  if (cell_kind(f, l + 1, gi + cq[0], gj + cq[1], gk + cq[2]) == K_INTERIOR) ++nin;
-                }
-                wgt = 1.0f - nin / 8.0f;
-              } else if (ks == K_FINER) {
-                wgt = 0.0f;
-              } else if (ks == K_COARSER) {
-                return fail(c, VMLBM_ERANGE, "level %d cell pulls from an uncovered coarser cell", l);
-              }
-              uint8_t mask = 0;
-              for (int m = 0; m < 8; ++m) {
-                const int gi = 2 * i + (m & 1), gj = 2 * j + ((m >> 1) & 1), gk = 2 * k + (m >> 2);
-                if (cell_kind(f, l + 1, gi, gj, gk) != K_GHOST) continue;
-                const int k1 = cell_kind(f, l + 1, gi - cq[0], gj - cq[1], gk - cq[2]);
-                const int k2 = cell_kind(f, l + 1, gi - 2 * cq[0], gj - 2 * cq[1], gk - 2 * cq[2]);
-                if (k1 == K_INTERIOR || (k1 == K_GHOST && k2 == K_INTERIOR)) mask |= (uint8_t)(1u << m);
-              }
-              e.weight[q] = wgt;
-              e.mask[q] = mask;
-              if (wgt != 1.0f || mask) special = true;
-            }
-            if (!special) continue;
-            e.slot = s;
-            e.local = (lz * kBlock + ly) * kBlock + lx;
-            e.fine_slot = -1;
-            e.fine_local = 0;
-            const int fi = 2 * i, fj = 2 * j, fk = 2 * k;
-            const long fp = ((long)(fk >> 4) * Fl.nb[1] + (fj >> 4)) * Fl.nb[0] + (fi >> 4);
-            const int fs = Fl.slot_of[fp];
-            bool anymask = false;
-            for (int q = 0; q < kQ; ++q) anymask = anymask || e.mask[q];
-            if (anymask) {
-              if (fs < (int)Fl.interior.size())
-                return fail(c, VMLBM_ERANGE, "coalescence children of level %d not in a ghost block", l);
-              e.fine_slot = fs;
-              e.fine_local = (((fk & 15) * kBlock) + (fj & 15)) * kBlock + (fi & 15);
-            }
-            V.iface.push_back(e);
-          }
+      bool any = false;
+      for (int dz = -1; dz <= 1 && !any; ++dz)
+        for (int dy = -1; dy <= 1 && !any; ++dy)
+          for (int dx = -1; dx <= 1 && !any; ++dx)
+            if (K.block(l, bi + dx, bj + dy, bk + dz) > l) any = true;
+      if (any) near.push_back(s);
+    }
+    std::vector<std::vector<IfaceEntry>> part(near.size());
+    std::vector<int> err(near.size(), 0);
+    const int nt = (int)std::max<size_t>(1, std::min<size_t>({near.size(), 16, (size_t)std::max(1u, std::thread::hardware_concurrency())}));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+      pool.emplace_back([&, t]() {
+        for (size_t n = t; n < near.size(); n += nt) err[n] = iface_block(K, f, l, near[n], part[n]);
+      });
+    for (auto& th : pool) th.join();
+    V.iface.clear();
+    for (size_t n = 0; n < near.size(); ++n) {
+      if (err[n] == 1) return fail(c, VMLBM_ERANGE, "level %d cell pulls from an uncovered coarser cell", l);
+      if (err[n] == 2) return fail(c, VMLBM_ERANGE, "coalescence children of level %d not in a ghost block", l);
+      V.iface.insert(V.iface.end(), part[n].begin(), part[n].end());
     }
     if (V.iface_cap && (int)V.iface.size() > V.iface_cap)
       return fail(c, VMLBM_ERANGE, "level %d coalescence table needs %zu entries, capacity %d", l, V.iface.size(),
@@ -828,8 +1010,13 @@ int check_layout(vmlbm_ctx* c) {
     for (int i = 0; i < np; ++i)
       for (int a = 0; a < 3; ++a) sph[i].x[a] = hp[i].x[a];
   }
-  std::vector<int8_t> nl = balance_layout(f, layout_targets(c, f, sph));
-  if (nl == f.leaf) return VMLBM_OK;
+  std::vector<int> box = sphere_boxes(sph);
+  if (box == f.boxes) return VMLBM_OK;
+  std::vector<int8_t> nl = balance_layout(f, layout_targets(f, box));
+  if (nl == f.leaf) {
+    f.boxes = box;
+    return VMLBM_OK;
+  }
   // the old layout stays readable on the device: leaf array, slot_of tables
   // and populations of the current buffers
   MigrateArgs m{};
@@ -867,6 +1054,7 @@ int check_layout(vmlbm_ctx* c) {
   for (int l = 0; l <= f.L; ++l) f.lv[l].cur = 1 - f.lv[l].cur;
   rc = mark_flags(c);
   if (rc) return rc;
+  f.boxes = box;
   f.refinements += 1;
   return VMLBM_OK;
 }
@@ -911,10 +1099,13 @@ int refine_create(vmlbm_ctx* c) {
 int refine_plan(vmlbm_ctx* c) {
   Forest& f = *c->forest;
   // layout from the spheres' initial positions and the static regions
-  f.leaf = balance_layout(f, layout_targets(c, f, c->spheres));
+  f.boxes = sphere_boxes(c->spheres);
+  f.leaf = balance_layout(f, layout_targets(f, f.boxes));
   for (auto& V : f.lv) { V.cap = 0; V.iface_cap = 0; }
   int rc = build_tables(c, f);
   if (rc) return rc;
+  std::vector<long> cap, icap;
+  plan_capacity(c, f, cap, icap);
   const size_t S = storage_bytes(c->cfg.storage);
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
@@ -927,11 +1118,11 @@ int refine_plan(vmlbm_ctx* c) {
   c->off_parts = take(std::max(np, 1) * sizeof(DevParticle));
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
   c->off_hist = take((size_t)std::max(c->cfg.history, 1) * std::max(np, 1) * 12 * sizeof(double));
+  c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
   for (int l = 0; l <= f.L; ++l) {
     Forest::Lev& V = f.lv[l];
-    const int n = (int)(V.pos.size() / 3);
-    V.cap = (int)std::min<long>(V.npos, 2L * n + 64);
-    V.iface_cap = 2 * (int)V.iface.size() + 4096;
+    V.cap = (int)std::max<long>(cap[l], (long)(V.pos.size() / 3));
+    V.iface_cap = (int)std::max<long>(icap[l], (long)V.iface.size());
     for (int b = 0; b < 2; ++b) V.off_pdf[b] = take((size_t)kQ * V.cap * kBlockCells * S);
     V.off_flags = take((size_t)V.cap * kBlockCells);
     for (int b = 0; b < 2; ++b) V.off_slot_of[b] = take(V.npos * sizeof(int));
@@ -950,7 +1141,8 @@ int refine_plan(vmlbm_ctx* c) {
 int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
   Forest& f = *c->forest;
   const int np = (int)c->spheres.size();
-  f.leaf = balance_layout(f, layout_targets(c, f, c->spheres));
+  f.boxes = sphere_boxes(c->spheres);
+  f.leaf = balance_layout(f, layout_targets(f, f.boxes));
   int rc = build_tables(c, f);
   if (rc) return rc;
   for (auto& V : f.lv) { V.tab = 0; V.cur = 0; }
@@ -1128,6 +1320,34 @@ int refine_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* int
 }
 
 void refine_destroy(vmlbm_ctx*) {}
+
+// volume-weighted totals over the interior fluid cells of every level
+int refine_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
+  Forest& f = *c->forest;
+  long double m = 0, j[3] = {0, 0, 0};
+  double* part = (double*)(c->ws + c->off_totals);
+  std::vector<double> h((size_t)kTotalsGroups * 8);
+  for (int l = 0; l <= f.L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    if (!V.n_int) continue;
+    HIP_TRY(c, launch_totals(c->cfg.storage, c->ws + V.off_pdf[V.cur], (const uint8_t*)(c->ws + V.off_flags),
+                             (uint32_t)V.cap * kBlockCells, 0, (const int*)(c->ws + V.off_int), V.n_int, part,
+                             c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    long double n = 0, ml = 0, jl[3] = {0, 0, 0};
+    for (int g = 0; g < kTotalsGroups; ++g) {
+      n += h[8 * g]; ml += h[8 * g + 1];
+      for (int a = 0; a < 3; ++a) jl[a] += h[8 * g + 2 + a];
+    }
+    const long double vol = 1.0L / (long double)(1L << (3 * l));
+    m += (n + ml) * vol;
+    for (int a = 0; a < 3; ++a) j[a] += jl[a] * vol;
+  }
+  if (mass) *mass = (double)m;
+  if (mom) for (int a = 0; a < 3; ++a) mom[a] = (double)j[a];
+  return VMLBM_OK;
+}
 
 void level_force(const vmlbm_ctx* c, int level, double F[3]) {
   const int L = c->cfg.block > 0 ? c->cfg.levels - 1 : 0;

@@ -14,6 +14,7 @@
 #include "uniform.hpp"
 #include "stencil.hpp"
 #include "particle.hpp"
+#include "context.hpp"
 
 namespace vm {
 
@@ -208,7 +209,48 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
   for (int a = 0; a < 3; ++a) { h[a] = F[a]; h[3 + a] = T[a]; h[6 + a] = P.x[a]; h[9 + a] = P.u[a]; }
 }
 
+// fixed-order partial sums over fluid cells: count, sum of deviations and
+// their first moment; grid-stride over the cell range (or the listed 16^3
+// slots of a block level)
+template <typename S>
+__global__ __launch_bounds__(256) void k_totals(const S* __restrict__ pdf, const uint8_t* __restrict__ flags,
+                                                uint32_t N, uint32_t cells, const int* __restrict__ slots,
+                                                int nslots, double* __restrict__ part) {
+  double v[5] = {0, 0, 0, 0, 0};
+  const uint32_t total = slots ? (uint32_t)nslots * 4096u : cells;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+    const uint32_t c = slots ? (uint32_t)slots[t >> 12] * 4096u + (t & 4095u) : t;
+    if (flags && (flags[c] & kSolid)) continue;
+    v[0] += 1.0;
+    for (int q = 0; q < kQ; ++q) {
+      const double d = (double)Store<S>::load(pdf[(size_t)q * N + c]);
+      v[1] += d;
+      v[2] += cx_of(q) * d;
+      v[3] += cy_of(q) * d;
+      v[4] += cz_of(q) * d;
+    }
+  }
+  __shared__ double red[5][4];
+  for (int k = 0; k < 5; ++k) v[k] = wave_sum(v[k]);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x >> 6] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 5; ++k) part[8 * blockIdx.x + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+}
+
 }  // namespace
+
+hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uint32_t N, uint32_t cells,
+                         const int* slot_list, int nslots, double* partials, hipStream_t st) {
+  if (storage == 0)
+    k_totals<double><<<kTotalsGroups, 256, 0, st>>>((const double*)pdf, flags, N, cells, slot_list, nslots, partials);
+  else if (storage == 1)
+    k_totals<float><<<kTotalsGroups, 256, 0, st>>>((const float*)pdf, flags, N, cells, slot_list, nslots, partials);
+  else
+    k_totals<__half><<<kTotalsGroups, 256, 0, st>>>((const __half*)pdf, flags, N, cells, slot_list, nslots, partials);
+  return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // launchers
