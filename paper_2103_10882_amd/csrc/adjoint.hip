@@ -392,7 +392,9 @@ int vmlbm_adjoint(vmlbm_ctx* c, double dJ, double grad[2]) {
     HIP_TRY(c, hipMemcpyAsync(segbuf, c->ws + A.off_ckpt + (size_t)seg * A.state_bytes, A.state_bytes,
                               hipMemcpyDeviceToDevice, c->stream));
     for (int j = 1; j < K; ++j) {
-      int rc = sweep_once(c, p, segbuf + (size_t)(j - 1) * A.state_bytes, segbuf + (size_t)j * A.state_bytes,
+      SweepParams pr = p;
+      pr.seed = step_seed((long long)seg * K + j - 1);
+      int rc = sweep_once(c, pr, segbuf + (size_t)(j - 1) * A.state_bytes, segbuf + (size_t)j * A.state_bytes,
                           nullptr, nullptr);
       if (rc) return rc;
     }

@@ -155,9 +155,10 @@ int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEven
 }
 
 int uniform_step(vmlbm_ctx* c, int nsteps) {
-  const SweepParams p = sweep_params(c);
+  SweepParams p = sweep_params(c);
   const int np = (int)c->spheres.size();
   for (int s = 0; s < nsteps; ++s) {
+    p.seed = step_seed(c->steps_done);
     void* src = c->ws + c->off_pdf[c->cur];
     void* dst = c->ws + c->off_pdf[1 - c->cur];
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -297,7 +298,8 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
   if (!c) return VMLBM_EINVAL;
   if (!c->ws) return fail(c, VMLBM_ESTATE, "workspace not bound");
   if (c->cfg.block > 0) return refine_init(c, rho, u0);
-  const SweepParams p0 = sweep_params(c);
+  SweepParams p0 = sweep_params(c);
+  p0.seed = kInitSeed;
   const int np = (int)c->spheres.size();
   HIP_TRY(c, hipMemsetAsync(c->status(), 0, kStatusWords * sizeof(int), c->stream));
   // particle records

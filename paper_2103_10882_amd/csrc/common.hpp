@@ -56,21 +56,68 @@ constexpr int kStatusWords = 16;
 // ---------------------------------------------------------------------------
 // storage precision: load/store of deviations
 // ---------------------------------------------------------------------------
+// Random bits for stochastic rounding: one counter-based stream per (cell,
+// sweep).  An integer hash of the cell index and the sweep's seed (the
+// "lowbias32" mixer of C. Wellons' hash-prospector) starts a 32-bit linear
+// congruential sequence (PCG32's multiplier and increment) advanced once per
+// stored population; its high bits are used.
+__host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+struct SrBits {
+  uint32_t h;
+  __device__ __forceinline__ SrBits(uint32_t cell, uint32_t seed) : h(mix32(cell ^ mix32(seed + 0x9e3779b9u))) {}
+  __device__ __forceinline__ uint32_t next() {
+    h = h * 747796405u + 2891336453u;
+    return h;
+  }
+};
+
+// FP32 -> FP16 rounding up or down with probability proportional to the
+// distance to the two neighbours (unbiased in expectation).  r: 32 random
+// bits.  FP16 normals keep 10 of FP32's 23 mantissa bits: add 13 random bits
+// below the kept ones and truncate; subnormals (|v| < 2^-14) are multiples
+// of 2^-24: scale, add a uniform [0,1) and take the floor.
+__device__ __forceinline__ __half half_sr(float v, uint32_t r) {
+  const uint32_t b = __float_as_uint(v);
+  const uint32_t sgn = b & 0x80000000u, mag = b & 0x7fffffffu;
+  if (mag >= 0x38800000u) {
+    const uint32_t m = (mag + (r >> 19)) & ~0x1fffu;
+    return __float2half_rn(__uint_as_float(sgn | m));
+  }
+  const float k = floorf(__uint_as_float(mag) * 16777216.0f + (float)(r >> 8) * (1.0f / 16777216.0f));
+  return __float2half_rn(__uint_as_float(sgn | __float_as_uint(k * (1.0f / 16777216.0f))));
+}
+
+// Storage formats (reduced-precision storage is not part of the paper's
+// method): the stored value is the deviation d = f - w, T the arithmetic
+// type.  store() rounds to nearest and serves exact copies; store_sr() is
+// used wherever a new value is produced (for FP16 the bias of rounding to
+// nearest accumulates over steps when per-step changes are near half an FP16
+// ulp, as the body-force increments are).
 template <typename S> struct Store;
 template <> struct Store<double> {
   using T = double;
   static __device__ __forceinline__ double load(double v) { return v; }
   static __device__ __forceinline__ double store(double v) { return v; }
+  static __device__ __forceinline__ double store_sr(double v, uint32_t) { return v; }
 };
 template <> struct Store<float> {
   using T = float;
   static __device__ __forceinline__ float load(float v) { return v; }
   static __device__ __forceinline__ float store(float v) { return v; }
+  static __device__ __forceinline__ float store_sr(float v, uint32_t) { return v; }
 };
 template <> struct Store<__half> {
   using T = float;
   static __device__ __forceinline__ float load(__half v) { return __half2float(v); }
   static __device__ __forceinline__ __half store(float v) { return __float2half_rn(v); }
+  static __device__ __forceinline__ __half store_sr(float v, uint32_t r) { return half_sr(v, r); }
 };
 
 // streaming (nontemporal) store of one stored population

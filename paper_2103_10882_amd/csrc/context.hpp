@@ -66,6 +66,16 @@ struct vmlbm_ctx {
 namespace vm {
 using Take = std::function<size_t(size_t)>;
 
+// Seeds of the stochastic-rounding streams: the sweep that produces state
+// n+1 from state n uses step_seed(n) (a recomputation from a checkpoint
+// reproduces the forward states bit for bit); level l of the refined grid
+// uses level_seed(finest steps done, l); initial states and data migrated
+// between levels use their own streams.
+inline uint32_t step_seed(long long n) { return (uint32_t)n; }
+inline uint32_t level_seed(long long fine_steps, int l) { return (uint32_t)(fine_steps * 8 + l); }
+constexpr uint32_t kInitSeed = 0xa511e9b3u;
+constexpr uint32_t kMigrateSeed = 0x63d83595u;
+
 int fail(vmlbm_ctx* c, int code, const char* fmt, ...);
 #define HIP_TRY(ctx, expr)                                                                           \
   do {                                                                                               \

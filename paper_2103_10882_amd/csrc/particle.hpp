@@ -153,8 +153,9 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
     if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
     const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
+    SrBits rb(c, p.seed);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * ad.N + c] = Store<S>::store(d[q]);
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * ad.N + c] = Store<S>::store_sr(d[q], rb.next());
   }
   double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
 #pragma unroll
@@ -325,7 +326,8 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
     d[q] = T(w * (rho - 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) - 3.0 * w / p.sp * QS);
   }
   trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
-  for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store(d[q]);
+  SrBits sr(c, ~p.seed);
+  for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store_sr(d[q], sr.next());
 }
 
 }  // namespace vm

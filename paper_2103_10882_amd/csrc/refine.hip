@@ -543,6 +543,7 @@ struct LevelArgs {
   const int* pos;      // per slot: block position x, y, z
   uint32_t N;          // population stride (cap * 4096)
   double sp, sm, F[3];
+  uint32_t seed;       // stochastic-rounding stream of this sweep
 };
 
 __device__ __forceinline__ int nbr_slot(const LevelArgs& a, const int* pos3, int dx, int dy, int dz) {
@@ -610,8 +611,9 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
     }
     const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
+    SrBits rb(c, a.seed);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * a.N + c], Store<S>::store(d[q]));
+    for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * a.N + c], Store<S>::store_sr(d[q], rb.next()));
   }
 }
 
@@ -691,7 +693,8 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
   const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   const uint32_t c = (uint32_t)e.slot * kBlockCells + (uint32_t)e.local;
-  for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+  SrBits rb(c, a.seed);
+  for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store_sr(d[q], rb.next());
 }
 
 __global__ void k_mark_iface(uint8_t* __restrict__ flags, const IfaceEntry* __restrict__ tab, int count) {
@@ -725,8 +728,9 @@ __global__ __launch_bounds__(256) void k_init_level(S* __restrict__ dst, const d
     }
     trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+    SrBits rb(c, a.seed);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store_sr(d[q], rb.next());
   }
 }
 
@@ -754,6 +758,7 @@ struct MigrateArgs {
   const int* old_slot_of[4];
   int nb[4][3];
   uint32_t oldN[4];
+  uint32_t seed;
 };
 
 template <typename S>
@@ -797,7 +802,8 @@ __global__ __launch_bounds__(256) void k_migrate(S* __restrict__ dst, const int*
       for (int q = 0; q < kQ; ++q) v[q] *= inv;
     }
     if (!ok) status[kStatusRange] = 8;
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store((typename Store<S>::T)v[q]);
+    SrBits rb(c, m.seed);
+    for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store_sr((typename Store<S>::T)v[q], rb.next());
   }
 }
 
@@ -821,6 +827,7 @@ LevelArgs level_args(vmlbm_ctx* c, int l, int tab) {
   a.sp = V.lp.sp;
   a.sm = V.lp.sm;
   for (int i = 0; i < 3; ++i) a.F[i] = V.lp.F[i];
+  a.seed = level_seed(c->fine_steps_done, l);
   return a;
 }
 
@@ -847,6 +854,7 @@ SweepParams finest_params(vmlbm_ctx* c) {
   p.N = (uint32_t)V.cap * kBlockCells;
   p.box = c->box;
   p.slot_stride = c->slot_stride;
+  p.seed = level_seed(c->fine_steps_done, f.L);
   return p;
 }
 
@@ -1021,6 +1029,7 @@ int check_layout(vmlbm_ctx* c) {
   // and populations of the current buffers
   MigrateArgs m{};
   m.L = f.L;
+  m.seed = kMigrateSeed + (uint32_t)f.refinements;
   for (int a = 0; a < 3; ++a) m.nbL[a] = f.nbL[a];
   m.old_leaf = (const int8_t*)(c->ws + f.off_leaf[f.leaf_tab]);
   for (int l = 0; l <= f.L; ++l) {
@@ -1189,8 +1198,10 @@ int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
       Forest::Lev& V = f.lv[l];
       const int ns = V.n_int + V.n_ghost;
       if (!ns) continue;
+      LevelArgs ai = level_args(c, l, 0);
+      ai.seed = kInitSeed + (uint32_t)l;
       k_init_level<S><<<ns, 256, 0, c->stream>>>((S*)(c->ws + V.off_pdf[0]), u0d, l, c->cfg.n[0], c->cfg.n[1], N0,
-                                                 rho - 1.0, level_args(c, l, 0));
+                                                 rho - 1.0, ai);
       HIP_TRY(c, hipGetLastError());
     }
     return VMLBM_OK;

@@ -8,6 +8,7 @@
 // [z][y][x] (read only for solid cells).  One thread per cell, one wave per
 // 64 consecutive x cells of a row, so every population load and store of a
 // wave is a contiguous run shifted by at most one element.
+#include <type_traits>
 #include <utility>
 
 #include "common.hpp"
@@ -49,8 +50,9 @@ __global__ __launch_bounds__(512) void k_sweep(const S* __restrict__ src, S* __r
   const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   // streaming stores: the new state is not read again within this sweep
+  SrBits rb(c, p.seed);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], Store<S>::store(d[q]));
+  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], Store<S>::store_sr(d[q], rb.next()));
 }
 
 // Wall-link cells without particle links: the two boundary planes of each
@@ -83,8 +85,9 @@ __global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ sr
   boundary_cell<S, UAddr>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, status);
   const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
+  SrBits rb(c, p.seed);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
+  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store_sr(d[q], rb.next());
 }
 
 // ---------------------------------------------------------------------------
@@ -107,8 +110,9 @@ __global__ __launch_bounds__(256) void k_init(S* __restrict__ dst, const uint8_t
     d[q] = T(w_of(q) * (drho + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
   }
   trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  SrBits rb(c, p.seed);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store(d[q]);
+  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store_sr(d[q], rb.next());
 }
 
 __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
@@ -258,9 +262,11 @@ hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uin
 template <typename S>
 hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int* status, const SweepParams& p,
                            bool with_flags, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  // one workgroup per grid row (up to 512 cells): the x-shifted loads of a
-  // row stay within one workgroup's cache lines
-  const int bx = p.nx >= 512 ? 512 : ((p.nx + 63) / 64) * 64;
+  // one workgroup per grid row segment: the x-shifted loads of a row stay
+  // within one workgroup's cache lines.  Segment length by measurement on
+  // 512^3: 256 cells for FP32 storage, 512 for FP64 and FP16.
+  const int wmax = std::is_same<S, float>::value ? 256 : 512;
+  const int bx = p.nx >= wmax ? wmax : ((p.nx + 63) / 64) * 64;
   dim3 grid((p.nx + bx - 1) / bx, p.ny, p.nz), block(bx);
   if (e0) {
     hipError_t er = hipEventRecord(e0, st);

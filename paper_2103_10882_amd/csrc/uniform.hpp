@@ -18,6 +18,7 @@ struct SweepParams {
   uint32_t N;             // cells
   int box;                // edge of a sphere's box (cells); holds all its link cells
   size_t slot_stride;     // doubles per sphere in the force-slot array (6 per wave)
+  uint32_t seed;          // stochastic-rounding stream of this sweep
 };
 
 struct UpdateParams {

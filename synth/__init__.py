@@ -153,7 +153,10 @@ def adjoint(n=128, radius=10.0, steps=2000, avg_from=1500, ckpt_every=50):
 
 
 def refined(coarse=(128, 128, 512), levels=3, block=16, radius=16.0, ga=250.0,
-            density_ratio=0.1, cv=0.5, centre_coarse=(64.0, 64.0, 64.0)):
+            density_ratio=0.1, cv=0.5, centre_coarse=(64.3, 63.8, 63.0)):
+    """Rising light sphere on a 3-level grid.  The centre sits off block
+    boundaries: with r + b a whole number of blocks, a centre on a block face
+    makes the refinement box flip with round-off-sized lateral motion."""
     _, omega_f, g = _ga_params(ga, density_ratio, 2.0 * radius)
     scale = 2 ** (levels - 1)
     cfg = base_config(coarse, omega=omega_f, gravity=(0.0, 0.0, -g))
