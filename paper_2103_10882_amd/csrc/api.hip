@@ -43,8 +43,8 @@ void plan_uniform(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  // one slot of 6 doubles per wave of the boundary pass over a sphere's box
-  c->slot_stride = (((size_t)box * box * box + 255) / 256) * 4 * 6;
+  // one slot of 6 doubles per wave of the link-cell pass of a sphere
+  c->slot_stride = (size_t)kLinkGroups * 4 * 6;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   c->off_status = take(kStatusWords * sizeof(int));
@@ -56,6 +56,9 @@ void plan_uniform(vmlbm_ctx* c) {
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
   c->off_hist = take((size_t)std::max(g.history, 1) * std::max(np, 1) * 12 * sizeof(double));
   c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
+  c->off_lcount = take((size_t)std::max(np, 1) * link_chunks(box) * sizeof(int));
+  c->off_links = take((size_t)std::max(np, 1) * box * box * box * sizeof(uint32_t));
+  c->off_llen = take((size_t)std::max(np, 1) * sizeof(int));
   adjoint_plan(c, take);
   c->ws_needed = off;
 }
@@ -141,8 +144,8 @@ int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEven
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
     if (flags)
-      HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->slots(), c->status(), p,
-                                    c->side));
+      HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->links(), c->slots(),
+                                    c->status(), p, c->side));
     HIP_TRY(c, launch_interior<S>(src, dst, c->flags(), c->status(), p, flags, c->stream, e0, e1));
     return VMLBM_OK;
   });
@@ -179,7 +182,8 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
       if (c->moving) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;
-          HIP_TRY(c, launch_refill_remap<S>(dst, c->flags(), c->owner(), c->parts(), np, p, c->status(), c->stream));
+          HIP_TRY(c, launch_refill_remap<S>(dst, c->flags(), c->owner(), c->parts(), np, c->links(), p, c->status(),
+                                            c->stream));
           return VMLBM_OK;
         });
         if (rc) return rc;
@@ -324,7 +328,8 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
   }
   if (np) HIP_TRY(c, hipMemcpyAsync(c->parts(), hp.data(), np * sizeof(DevParticle), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * 12 * sizeof(double), c->stream));
-  if (c->use_flags) HIP_TRY(c, launch_map_all(c->flags(), c->owner(), c->parts(), np, p0, c->status(), c->stream));
+  if (c->use_flags)
+    HIP_TRY(c, launch_map_all(c->flags(), c->owner(), c->parts(), np, c->links(), p0, c->status(), c->stream));
   double* u0d = nullptr;
   if (u0) {
     u0d = (double*)(c->ws + c->off_pdf[1]);   // staging in the second population buffer

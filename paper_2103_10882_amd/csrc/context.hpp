@@ -10,6 +10,7 @@
 
 #include "vmlbm.h"
 #include "common.hpp"
+#include "uniform.hpp"
 
 namespace vm {
 struct Forest;     // block-structured grid state (refine.hip)
@@ -34,7 +35,7 @@ struct vmlbm_ctx {
 
   // uniform-grid workspace carving
   size_t off_status = 0, off_pdf[2] = {0, 0}, off_flags = 0, off_owner = 0, off_parts = 0, off_slots = 0,
-         off_hist = 0, off_totals = 0;
+         off_hist = 0, off_totals = 0, off_lcount = 0, off_links = 0, off_llen = 0;
   int cur = 0;
   int box = 0;
   size_t slot_stride = 0;
@@ -60,6 +61,7 @@ struct vmlbm_ctx {
   vm::DevParticle* parts() { return (vm::DevParticle*)(ws + off_parts); }
   double* slots() { return (double*)(ws + off_slots); }
   double* hist() { return (double*)(ws + off_hist); }
+  vm::LinkLists links() { return {(int*)(ws + off_lcount), (uint32_t*)(ws + off_links), (int*)(ws + off_llen)}; }
   long long particle_steps() const { return cfg.block > 0 ? fine_steps_done : steps_done; }
 };
 

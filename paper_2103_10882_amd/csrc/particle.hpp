@@ -125,29 +125,110 @@ __device__ __forceinline__ bool box_cell(const int* lo, int k, int edge, const S
   return true;
 }
 
-// Particle-link cells: one grid row per sphere over its box; a cell is
-// handled in the pass of the sphere it links to (owner array).  Every wave
-// writes its FP64 partial force/torque (zero if it holds no link) to its own
-// slot, so the per-sphere reduction reads a fixed set in a fixed order.
+// Box cell k of sphere pi is a link cell of that sphere: a fluid cell with a
+// particle link whose owner is pi.
+template <typename A>
+__device__ __forceinline__ bool link_cell(const uint8_t* __restrict__ flags, const uint16_t* __restrict__ owner,
+                                          const DevParticle* __restrict__ parts, int pi, int k,
+                                          const SweepParams& p, const A& ad, int& x, int& y, int& z,
+                                          uint32_t& c) {
+  const int edge = p.box;
+  int wa = 0, ws = 0;
+  if (k >= edge * edge * edge || !box_cell(parts[pi].box_lo, k, edge, p, x, y, z) ||
+      ad.locate(x, y, z, c, wa, ws) != 1)
+    return false;
+  return (flags[c] & kNearP) && owner[c] == pi;
+}
+
+// Link-cell lists, in box order: count per 256-cell chunk, then each chunk
+// writes its cells at the offset of the chunks before it.  links[pi][i] is
+// the box index of the i-th link cell of sphere pi, llen[pi] their number.
+template <typename A>
+__global__ __launch_bounds__(256) void k_link_count(const uint8_t* __restrict__ flags,
+                                                    const uint16_t* __restrict__ owner,
+                                                    const DevParticle* __restrict__ parts, SweepParams p, A ad,
+                                                    int* __restrict__ count) {
+  const int pi = blockIdx.y;
+  int x, y, z;
+  uint32_t c;
+  const bool in = link_cell<A>(flags, owner, parts, pi, blockIdx.x * 256 + threadIdx.x, p, ad, x, y, z, c);
+  const int n = __syncthreads_count(in);
+  if (threadIdx.x == 0) count[(size_t)pi * gridDim.x + blockIdx.x] = n;
+}
+
+template <typename A>
+__global__ __launch_bounds__(256) void k_link_write(const uint8_t* __restrict__ flags,
+                                                    const uint16_t* __restrict__ owner,
+                                                    const DevParticle* __restrict__ parts, SweepParams p, A ad,
+                                                    const int* __restrict__ count, uint32_t* __restrict__ links,
+                                                    int* __restrict__ llen) {
+  const int pi = blockIdx.y;
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  __shared__ int part[4];
+  __shared__ int wsum[4];
+  // offset: cells of the chunks before this one
+  const int* cnt = count + (size_t)pi * gridDim.x;
+  int before = 0;
+  for (int j = threadIdx.x; j < (int)blockIdx.x; j += 256) before += cnt[j];
+  for (int m = 32; m >= 1; m >>= 1) before += __shfl_xor(before, m, 64);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[wave] = before;
+  int x, y, z;
+  uint32_t c;
+  const bool in = link_cell<A>(flags, owner, parts, pi, k, p, ad, x, y, z, c);
+  const unsigned long long m = __ballot(in);
+  if (lane == 0) wsum[wave] = __popcll(m);
+  __syncthreads();
+  const int offset = part[0] + part[1] + part[2] + part[3];
+  int base = offset;
+  for (int w = 0; w < wave; ++w) base += wsum[w];
+  if (in) {
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    links[(size_t)pi * ((size_t)p.box * p.box * p.box) + base + rank] = (uint32_t)k;
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+    llen[pi] = offset + wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+template <typename A>
+inline hipError_t launch_link_lists(const uint8_t* flags, const uint16_t* owner, const DevParticle* parts, int np,
+                                    const SweepParams& p, const A& ad, int* count, uint32_t* links, int* llen,
+                                    hipStream_t st) {
+  if (np <= 0) return hipSuccess;
+  const dim3 grid(link_chunks(p.box), np), block(256);
+  k_link_count<A><<<grid, block, 0, st>>>(flags, owner, parts, p, ad, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_link_write<A><<<grid, block, 0, st>>>(flags, owner, parts, p, ad, count, links, llen);
+  return hipGetLastError();
+}
+
+// Particle-link cells: kLinkGroups workgroups per sphere stride over its
+// link list.  Every wave writes its FP64 partial force/torque (zero if it
+// held no link) to its own slot, so the per-sphere reduction reads a fixed
+// set in a fixed order.
 template <typename S, typename A>
 __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict__ src, S* __restrict__ dst,
                                                             const uint8_t* __restrict__ flags,
                                                             const uint16_t* __restrict__ owner,
                                                             const DevParticle* __restrict__ parts,
+                                                            const uint32_t* __restrict__ links,
+                                                            const int* __restrict__ llen,
                                                             double* __restrict__ slots, int* __restrict__ status,
                                                             SweepParams p, A ad) {
   using T = typename Store<S>::T;
   const int pi = blockIdx.y;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int edge = p.box;
-  int x = 0, y = 0, z = 0, wa = 0, ws = 0;
-  uint32_t c = 0;
-  bool active = k < edge * edge * edge && box_cell(parts[pi].box_lo, k, edge, p, x, y, z) &&
-                ad.locate(x, y, z, c, wa, ws) == 1;
-  if (active) active = (flags[c] & kNearP) && owner[c] == pi;
-  int pid = -1;
+  const int len = llen[pi];
+  const uint32_t* list = links + (size_t)pi * ((size_t)p.box * p.box * p.box);
   double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
-  if (active) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < len; i += gridDim.x * 256) {
+    int x, y, z;
+    uint32_t c;
+    if (!link_cell<A>(flags, owner, parts, pi, (int)list[i], p, ad, x, y, z, c)) {
+      status[kStatusRange] = 9;
+      continue;
+    }
+    int pid = -1;
     T d[kQ];
     boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status);
     if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
@@ -161,7 +242,7 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
 #pragma unroll
   for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
   if ((threadIdx.x & 63) == 0) {
-    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(k >> 6) * 6;
+    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * 6;
 #pragma unroll
     for (int j = 0; j < 6; ++j) o[j] = v[j];
   }

@@ -903,6 +903,10 @@ int mark_flags(vmlbm_ctx* c) {
                                                 c->parts(), np, finest_params(c), finest_addr(c),
                                                 (const int*)(c->ws + V.off_pos), c->status());
     HIP_TRY(c, hipGetLastError());
+    const LinkLists ll = c->links();
+    HIP_TRY(c, launch_link_lists<BAddr>((const uint8_t*)(c->ws + V.off_flags), (const uint16_t*)(c->ws + f.off_owner),
+                                        c->parts(), np, finest_params(c), finest_addr(c), ll.count, ll.links, ll.len,
+                                        c->stream));
   }
   return VMLBM_OK;
 }
@@ -949,10 +953,10 @@ int sweep_level(vmlbm_ctx* c, int l) {
     }
     if (l == f.L && np) {
       const SweepParams p = finest_params(c);
-      const int cells = p.box * p.box * p.box;
-      k_boundary_particles<S, BAddr><<<dim3((cells + 255) / 256, np), dim3(256), 0, c->stream>>>(
+      const LinkLists ll = c->links();
+      k_boundary_particles<S, BAddr><<<dim3(kLinkGroups, np), dim3(256), 0, c->stream>>>(
           (const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags), (const uint16_t*)(c->ws + f.off_owner),
-          c->parts(), c->slots(), c->status(), p, finest_addr(c));
+          c->parts(), ll.links, ll.len, c->slots(), c->status(), p, finest_addr(c));
       HIP_TRY(c, hipGetLastError());
     }
     return VMLBM_OK;
@@ -983,6 +987,10 @@ int sweep_level(vmlbm_ctx* c, int l) {
                                                         (uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
                                                         finest_addr(c), c->status());
           HIP_TRY(c, hipGetLastError());
+          const LinkLists ll = c->links();
+          HIP_TRY(c, launch_link_lists<BAddr>((const uint8_t*)(c->ws + V.off_flags),
+                                              (const uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
+                                              finest_addr(c), ll.count, ll.links, ll.len, c->stream));
           return VMLBM_OK;
         });
         if (rc) return rc;
@@ -1119,7 +1127,7 @@ int refine_plan(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  c->slot_stride = (((size_t)box * box * box + 255) / 256) * 4 * 6;
+  c->slot_stride = (size_t)kLinkGroups * 4 * 6;
   const int np = (int)c->spheres.size();
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };
@@ -1128,6 +1136,9 @@ int refine_plan(vmlbm_ctx* c) {
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
   c->off_hist = take((size_t)std::max(c->cfg.history, 1) * std::max(np, 1) * 12 * sizeof(double));
   c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
+  c->off_lcount = take((size_t)std::max(np, 1) * link_chunks(box) * sizeof(int));
+  c->off_links = take((size_t)std::max(np, 1) * box * box * box * sizeof(uint32_t));
+  c->off_llen = take((size_t)std::max(np, 1) * sizeof(int));
   for (int l = 0; l <= f.L; ++l) {
     Forest::Lev& V = f.lv[l];
     V.cap = (int)std::max<long>(cap[l], (long)(V.pos.size() / 3));

@@ -262,10 +262,11 @@ hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uin
 template <typename S>
 hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int* status, const SweepParams& p,
                            bool with_flags, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  // one workgroup per grid row segment: the x-shifted loads of a row stay
-  // within one workgroup's cache lines.  Segment length by measurement on
-  // 512^3: 256 cells for FP32 storage, 512 for FP64 and FP16.
-  const int wmax = std::is_same<S, float>::value ? 256 : 512;
+  // one workgroup per grid row segment: the x-shifted loads of a segment
+  // stay within one workgroup's cache lines.  Segment length by measurement
+  // on 512^3: 256 cells for FP32 and FP16 storage, whole 512-cell rows for
+  // FP64.
+  const int wmax = std::is_same<S, double>::value ? 512 : 256;
   const int bx = p.nx >= wmax ? wmax : ((p.nx + 63) / 64) * 64;
   dim3 grid((p.nx + bx - 1) / bx, p.ny, p.nz), block(bx);
   if (e0) {
@@ -283,13 +284,12 @@ hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int
 
 template <typename S>
 hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
-                           const DevParticle* parts, int np, double* slots, int* status, const SweepParams& p,
-                           hipStream_t st) {
+                           const DevParticle* parts, int np, const LinkLists& ll, double* slots, int* status,
+                           const SweepParams& p, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (np > 0) {
-    const int cells = p.box * p.box * p.box;
-    k_boundary_particles<S, UAddr><<<dim3((cells + 255) / 256, np), dim3(256), 0, st>>>(
-        (const S*)src, (S*)dst, flags, owner, parts, slots, status, p, uaddr(p));
+    k_boundary_particles<S, UAddr><<<dim3(kLinkGroups, np), dim3(256), 0, st>>>(
+        (const S*)src, (S*)dst, flags, owner, parts, ll.links, ll.len, slots, status, p, uaddr(p));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -316,23 +316,27 @@ hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double
   return hipGetLastError();
 }
 
-hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np, const SweepParams& p,
-                          int* status, hipStream_t st) {
+hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
+                          const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st) {
   dim3 grid((p.N + 255) / 256), block(256);
   k_map_all<<<grid, block, 0, st>>>(flags, owner, parts, np, p, status);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_link_lists<UAddr>(flags, owner, parts, np, p, uaddr(p), ll.count, ll.links, ll.len, st);
 }
 
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                               const SweepParams& p, int* status, hipStream_t st) {
+                               const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st) {
   const int rb = p.box + 1;
   dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
   k_refill<S, UAddr><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p, uaddr(p), status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   k_remap<UAddr><<<grid, block, 0, st>>>(flags, owner, parts, np, p, uaddr(p), status);
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_link_lists<UAddr>(flags, owner, parts, np, p, uaddr(p), ll.count, ll.links, ll.len, st);
 }
 
 hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
@@ -344,23 +348,23 @@ hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, doubl
 template hipError_t launch_interior<double>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<double>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                            int, double*, int*, const SweepParams&, hipStream_t);
+                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
 template hipError_t launch_interior<float>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<float>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                            int, double*, int*, const SweepParams&, hipStream_t);
+                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
 template hipError_t launch_interior<__half>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<__half>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                            int, double*, int*, const SweepParams&, hipStream_t);
+                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
 template hipError_t launch_init<double>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_init<float>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_init<__half>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_refill_remap<double>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                                const SweepParams&, int*, hipStream_t);
+                                                const LinkLists&, const SweepParams&, int*, hipStream_t);
 template hipError_t launch_refill_remap<float>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                               const SweepParams&, int*, hipStream_t);
+                                               const LinkLists&, const SweepParams&, int*, hipStream_t);
 template hipError_t launch_refill_remap<__half>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                                const SweepParams&, int*, hipStream_t);
+                                                const LinkLists&, const SweepParams&, int*, hipStream_t);
 
 }  // namespace vm

@@ -21,6 +21,20 @@ struct SweepParams {
   uint32_t seed;          // stochastic-rounding stream of this sweep
 };
 
+// Workgroups per sphere of the link-cell pass; each of their waves owns one
+// force/torque slot of 6 doubles.
+constexpr int kLinkGroups = 32;
+inline int link_chunks(int box) { return (box * box * box + 255) / 256; }
+
+// Per-sphere lists of link cells in box order: counts per 256-cell chunk of
+// the box, box indices (box^3 per sphere), list lengths.  Rebuilt after
+// every (re-)mapping.
+struct LinkLists {
+  int* count;
+  uint32_t* links;
+  int* len;
+};
+
 struct UpdateParams {
   double g[3];
   int step;
@@ -37,16 +51,16 @@ hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int
 // interior sweep, so both may run concurrently
 template <typename S>
 hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
-                           const DevParticle* parts, int np, double* slots, int* status, const SweepParams& p,
-                           hipStream_t st);
+                           const DevParticle* parts, int np, const LinkLists& ll, double* slots, int* status,
+                           const SweepParams& p, hipStream_t st);
 template <typename S>
 hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double drho, const SweepParams& p,
                        hipStream_t st);
 hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                          const SweepParams& p, int* status, hipStream_t st);
+                          const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st);
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                               const SweepParams& p, int* status, hipStream_t st);
+                               const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st);
 hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
                                 const SweepParams& p, const UpdateParams& u, hipStream_t st);
 

@@ -194,6 +194,57 @@ def test_reduced_storage_drag(env, storage, tol):
     assert err < tol
 
 
+def pulled(f, c):
+    """f[q] at x - c_q for every cell (periodic), arrays [q][z][y][x]."""
+    return np.stack([np.roll(f[q], shift=(c[q, 2], c[q, 1], c[q, 0]), axis=(0, 1, 2)) for q in range(19)])
+
+
+@pytest.mark.parametrize("case", ["box130", "sphere32"])
+def test_reduced_storage_one_step(env, case):
+    """One FP16 / FP32 sweep from a rough state (per-cell random velocities
+    of amplitude 0.02, so neighbouring cells differ by far more than a
+    storage ulp): every cell without links equals the oracle's collision of
+    its pulled populations to within one storage ulp of the deviation plus
+    FP32 round-off, at the periodic row ends and next to flagged cells."""
+    pkg, ora = env
+    c, w, _ = ora.lattice()
+    if case == "box130":
+        n = (130, 6, 5)
+        cfg = synth.base_config(n, omega=1.4, body_force=(2e-5, -1e-5, 3e-5))
+        sph = []
+    else:
+        wk = synth.tiny()
+        cfg, sph = wk["config"], wk["spheres"]
+        n = tuple(cfg["n"])
+    u0 = synth.velocity_perturbation(n, seed=11, amplitude=0.02)
+    F = np.array(cfg["body_force"])
+    for storage, ulp in (("f16", 2.0 ** -10), ("f32", 2.0 ** -23)):
+        say(f"case {case} one step {storage}")
+        sim = pkg.Sim(cfg, sph, storage=storage)
+        sim.init(1.0, u0)
+        sim.step(2)
+        sim.sync()
+        f0 = sim.populations()
+        sim.step(1)
+        sim.sync()
+        f1 = sim.populations()
+        sim.close()
+        pre = pulled(f0, c)
+        zz, yy, xx = np.meshgrid(*[np.arange(m) for m in (n[2], n[1], n[0])], indexing="ij")
+        keep = np.ones(f0.shape[1:], dtype=bool)
+        for s_ in sph:
+            d = np.stack([xx + 0.5 - s_["x"][0], yy + 0.5 - s_["x"][1], zz + 0.5 - s_["x"][2]])
+            keep &= np.sqrt((d ** 2).sum(axis=0)) > s_["radius"] + 2.5
+        worst = 0.0
+        for k, j, i in zip(*np.nonzero(keep)):
+            out = ora.collide_cell(pre[:, k, j, i], cfg["omega"], cfg["magic"], F)
+            dev = out - w
+            err = np.abs(f1[:, k, j, i] - out)
+            worst = max(worst, float((err / (ulp * np.abs(dev) + 2e-7)).max()))
+        say(f"  {int(keep.sum())} cells, worst error / (ulp |d| + 2e-7) = {worst:.3f}")
+        assert worst <= 1.0
+
+
 @pytest.mark.parametrize("storage", ["f16", "f32"])
 def test_forcing_momentum_unbiased(env, storage):
     """Obstacle-free periodic 16^3 box driven by F = 1e-5 for 3000 steps:
