@@ -30,6 +30,12 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & %HBM roofline, FP16/FP32-store vs FP64 at drag err<1e-3; adjoint cost"
 PEAK_GBS = 8000.0
 BYTES = {"f64": 8, "f32": 4, "f16": 2}
+# sources of the interior sweep kernel; the HBM counter figures in
+# TRAFFIC_FILE hold for the build whose sources hash to its source_sha256
+SWEEP_SOURCES = ["paper_2103_10882_amd/csrc/common.hpp", "paper_2103_10882_amd/csrc/stencil.hpp",
+                 "paper_2103_10882_amd/csrc/uniform.hpp", "paper_2103_10882_amd/csrc/uniform.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_precision512.md")
+COPY_BYTES = 1 << 30
 
 
 def log(*a):
@@ -164,6 +170,44 @@ def run_adjoint(pkg, storage="f32"):
             "forward_s": t1 - t0, "reverse_s": t2 - t1, "cost_ratio": (t2 - t1) / (t1 - t0)}
 
 
+def sweep_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(storage):
+    """HBM bytes per launch of the interior sweep from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a plain copy of known size), or None if there is none
+    for this storage or the kernel sources changed since it was taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+        blob = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != sweep_source_hash() or storage not in blob.get("kernels", {}):
+        return None
+    k = blob["kernels"][storage]
+    return k["fetch_kib"] * 1024 * blob["fetch_scale"] + k["write_kib"] * 1024 * blob["write_scale"]
+
+
+def copy_reference():
+    """A plain device copy of COPY_BYTES, five times: the reference whose
+    FETCH_SIZE / WRITE_SIZE readings scale the sweep's counters."""
+    import torch
+    n = COPY_BYTES // 4
+    x = torch.ones(n, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}), flush=True)
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle on a bounded sample of the headline workload: a 128^3
     periodic box holding one of its fixed r=20 spheres, same omega and body
@@ -199,6 +243,8 @@ def main():
     ap.add_argument("--storages", default="f64,f32,f16")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run the plain copy used to scale HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -206,9 +252,12 @@ def main():
         sys.exit(2)
 
     import torch
+    torch.cuda.set_device(0)
+    if args.copy_ref:
+        copy_reference()
+        return
     import synth
     import paper_2103_10882_amd as pkg
-    torch.cuda.set_device(0)
     pkg.lib()
     w = synth.precision(n=args.n)
     drag_window = 200
@@ -227,6 +276,7 @@ def main():
     ok = [st for st, r in res.items() if r["drag_err"] is not None and r["drag_err"] < 1e-3]
     best = max(ok, key=lambda s: res[s]["mlups"]) if ok else max(res, key=lambda s: res[s]["mlups"])
     b = res[best]
+    traffic = measured_traffic(best) if args.n == 512 else None
     line = {
         "metric": METRIC,
         "value": round(b["mlups"], 1),
@@ -255,7 +305,8 @@ def main():
             "peak": PEAK_GBS,
             "unit": "GB/s",
             "frac": round(b["sweep_gbs"] / PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": None if traffic is None else round(traffic),
+            "traffic_over_algorithmic": None if traffic is None else round(traffic / b["sweep_bytes"], 3),
             "bytes_per_launch": b["sweep_bytes"],
             "launch_ms": round(b["sweep_ms"], 4),
         },
