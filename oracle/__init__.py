@@ -87,6 +87,9 @@ def lib():
                                        ctypes.c_void_p, ctypes.c_void_p]
         L.ora_equilibrium.restype = None
         L.ora_equilibrium.argtypes = [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_refill_populations.restype = None
+        L.ora_refill_populations.argtypes = [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                             ctypes.c_void_p]
         L.ora_lattice.restype = None
         L.ora_lattice.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         if hasattr(L, "orf_create"):
@@ -148,6 +151,14 @@ def equilibrium(rho, u):
     u = np.ascontiguousarray(u, dtype=np.float64)
     out = np.zeros(19)
     lib().ora_equilibrium(float(rho), u.ctypes.data, out.ctypes.data)
+    return out
+
+
+def refill_populations(rho, v, S, omega):
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    S = np.ascontiguousarray(S, dtype=np.float64).reshape(9)
+    out = np.zeros(19)
+    lib().ora_refill_populations(float(rho), v.ctypes.data, S.ctypes.data, float(omega), out.ctypes.data)
     return out
 
 

@@ -9,6 +9,14 @@
 //   mass terms of Sec. 3.3, Algorithm 1) -> re-mapping and refill (Sec. 2.3).
 // Readings of points the paper leaves open are marked "reading:".
 //
+// Pins (tests/test_oracle_pins.py, tests/test_oracle_refine.py): every
+// function is checked against closed forms, invariants or brute force,
+// except one part: the estimate of the velocity gradient used by the refill
+// (central differences over the axis neighbours) is parity unpinned -- the
+// paper only cites the refill scheme.  The refill populations for a given
+// strain rate are pinned by their moments (density, momentum, and the
+// Chapman-Enskog first-order stress).
+//
 // Only tests/, the smoke check and the benchmark's CPU-baseline leg load this
 // library.  It shares no code with the GPU library.
 #include "oracle.h"
@@ -387,6 +395,13 @@ void ora_collide_cell(const double f[19], double omega, double magic, const doub
 }
 
 void ora_equilibrium(double rho, const double u[3], double out[19]) { equilibrium(rho, u, out); }
+
+void ora_refill_populations(double rho, const double v[3], const double S[9], double omega, double out[19]) {
+  double M[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) M[a][b] = S[3 * a + b];
+  refill_populations(rho, v, M, omega, out);
+}
 
 double ora_link_delta(const double d[3], const int c[3], double radius) { return link_delta(d, c, radius); }
 

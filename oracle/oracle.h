@@ -7,6 +7,11 @@
  * the smoke check and the benchmark's CPU-baseline leg load it.  It shares no
  * code, header, table or helper with the GPU library.
  *
+ * Parity unpinned: the estimate of the velocity gradient that the refill of
+ * an uncovered cell uses (central differences over the axis neighbours, a
+ * reading of a scheme the paper only cites).  The refill populations given
+ * a strain rate are pinned by their moments.
+ *
  * Conventions: lattice units of the finest level; cell (i,j,k) has its centre
  * at (i+1/2, j+1/2, k+1/2); population arrays are [19][nz][ny][nx] C order.
  * All functions return 0 on success and a negative value on error.
@@ -42,6 +47,9 @@ void ora_collide_cell(const double f[19], double omega, double magic,
                       const double F[3], double out[19]);
 /* incompressible equilibrium f^eq(rho, u) */
 void ora_equilibrium(double rho, const double u[3], double out[19]);
+/* populations of a refilled cell from density, velocity and a strain rate
+ * S[3][3] (row-major): f^eq(rho, v) - 3 w_q / omega (c_q c_q - I/3) : S */
+void ora_refill_populations(double rho, const double v[3], const double S[9], double omega, double out[19]);
 /* boundary distance ratio along c from a fluid point at offset d from a
  * sphere centre; returns -1 if the segment does not enter the sphere */
 double ora_link_delta(const double d[3], const int c[3], double radius);

@@ -284,6 +284,29 @@ def test_comoving_uniform_flow_invariant(ora):
     assert np.abs(F).max() < 1e-13
 
 
+def test_refill_populations_moments(ora):
+    """Refill of an uncovered cell (Sec. 2.3): in the incompressible form
+    sum f = rho and sum c f = v exactly; the second moment carries the Chapman-Enskog first-order
+    stress of the strain rate, sum c_a c_b f = rho/3 delta + v v
+    - 2 c_s^2 / omega S with c_s^2 = 1/3."""
+    c, _, _ = ora.lattice()
+    rng = np.random.default_rng(4)
+    for _ in range(5):
+        rho = 1.0 + rng.uniform(-0.02, 0.02)
+        v = rng.uniform(-0.05, 0.05, 3)
+        A = rng.uniform(-1e-2, 1e-2, (3, 3))
+        S = 0.5 * (A + A.T)
+        omega = rng.uniform(0.6, 1.9)
+        f = ora.refill_populations(rho, v, S, omega)
+        assert abs(f.sum() - rho) < 1e-15
+        assert np.abs(c.T @ f - v).max() < 1e-16
+        Pi = np.einsum("qa,qb,q->ab", c, c, f)
+        exact = rho / 3.0 * np.eye(3) + np.outer(v, v) - 2.0 / (3.0 * omega) * S
+        assert np.abs(Pi - exact).max() < 1e-15
+        # zero strain: the equilibrium itself
+        assert np.abs(ora.refill_populations(rho, v, np.zeros((3, 3)), omega) - ora.equilibrium(rho, v)).max() == 0.0
+
+
 # --------------------------------------------------------------------------
 # particle update (Sec. 2.2, Sec. 3.3, Algorithm 1): closed forms
 # --------------------------------------------------------------------------

@@ -185,3 +185,29 @@ def test_comoving_sphere_across_rerefinement(ora):
     x, uu, _ = R.particle(0)
     assert np.abs(uu - U).max() < 1e-13
     assert abs(x[2] - (40.0 + 40 * 4 * 0.06)) < 1e-9
+
+
+def test_migration_conserves_mass_and_momentum(ora):
+    """A sphere of radius 0.2 moving on the line x = 16.3, y = 15.7 never
+    covers a cell centre (the nearest centres lie 0.28 away), so there are
+    no links and no refill, yet the layout follows it.  Data moved between
+    levels (copies to children, averages of children) must then conserve the
+    volume-weighted mass and momentum of a rough state exactly, as streaming
+    and the interface transfers do."""
+    U = np.array([0.0, 0.0, 0.06])
+    c = cfg_of((8, 8, 48), 3, 4, omega=1.5)
+    s = synth.sphere((16.3, 15.7, 40.0), 0.2, density_ratio=1e9, fixed=False, u=tuple(U))
+    R = ora.Refined(c, spheres=[s], check_every=1)
+    R.init(1.0, synth.velocity_perturbation((8, 8, 48), seed=7, amplitude=0.02))
+    leaf0 = R.leaf()
+    m0, J0 = volume_totals(ora, R, 3)
+    for _ in range(4):
+        R.step(10)
+        m, J = volume_totals(ora, R, 3)
+        assert abs(m - m0) < 1e-11 * m0
+        assert np.abs(J - J0).max() < 1e-12 * m0
+    _, _, nref = R.counters()
+    assert nref >= 2
+    assert not np.array_equal(R.leaf(), leaf0)
+    x, _, _ = R.particle(0)
+    assert abs(x[2] - (40.0 + 40 * 4 * 0.06)) < 1e-9
