@@ -13,7 +13,8 @@ Workloads (lattice units of the finest level, cell (i,j,k) has its centre at
                 sphere (density ratio 0.5, r=12, C_v=0.5) released at rest at
                 (128,128,64); Galileo number 150 (Eq. 13 with u_g=0.01).
 * ``refined``   3-level block grid (16^3 blocks), coarse 128x128x512, periodic,
-                sphere r=16 finest cells, density ratio 0.1, C_v=0.5, Ga=250.
+                sphere r=16 finest cells, density ratio 0.1, C_v=0.5, Ga=250,
+                centre (64.3, 63.8, 63.0) in coarse cells (off block faces).
 * ``precision`` 512^3 periodic, 8 fixed spheres r=20 at seeded positions,
                 body force 1e-5 along z.
 * ``adjoint``   128^3 periodic, fixed sphere r=10 in the centre, body force
