@@ -42,6 +42,7 @@ struct IfaceEntry {
   int slot, local;      // the coarse cell
   int fine_slot;        // level-(l+1) slot holding its 8 children (-1 if unused)
   int fine_local;       // local index of child (0,0,0)
+  uint32_t src[kQ];     // pull source x - c_q as slot * 4096 + local (unused where weight is 0)
   float weight[kQ];     // weight of the plain pull from the coarse source
   uint8_t mask[kQ];     // children whose value is added with weight 1/8
   uint8_t pad[1];
@@ -69,11 +70,13 @@ struct Forest {
     std::vector<int> interior, ghost; // slot lists
     std::vector<int> pos;             // per slot: x, y, z block position
     std::vector<int> explode;         // per ghost slot: ghost slot, parent slot, ox, oy, oz
+    std::vector<uint16_t> band;       // ghost cells (local index) of each ghost block, in ghost order
+    std::vector<int> band_off;        // per ghost block: start in band; one extra end entry
     std::vector<IfaceEntry> iface;
     LevelParams lp{};
     // device
     size_t off_pdf[2] = {0, 0}, off_flags = 0, off_slot_of[2] = {0, 0}, off_pos = 0, off_int = 0, off_ghost = 0,
-           off_explode = 0, off_iface = 0;
+           off_explode = 0, off_iface = 0, off_band = 0, off_band_off = 0;
     int cur = 0, tab = 0;
     int n_int = 0, n_ghost = 0, n_iface = 0;
   };
@@ -302,6 +305,13 @@ int iface_block(const Kinds& K, const Forest& f, int l, int s, std::vector<Iface
           const int si = i - cq[0], sj = j - cq[1], sk = k - cq[2];
           const int ks = K.kind(l, si, sj, sk);
           float wgt = 1.0f;
+          e.src[q] = 0;
+          if (ks == K_INTERIOR || ks == K_GHOST) {
+            const int wi = Kinds::wrap1(si, V.n[0]), wj = Kinds::wrap1(sj, V.n[1]), wk = Kinds::wrap1(sk, V.n[2]);
+            const int ss = V.slot_of[K.bpos(l, wi >> 4, wj >> 4, wk >> 4)];
+            if (ss < 0) return 1;
+            e.src[q] = (uint32_t)ss * kBlockCells + (uint32_t)(((wk & 15) * 16 + (wj & 15)) * 16 + (wi & 15));
+          }
           if (ks == K_INTERIOR) {
             int nin = 0;
             for (int m = 0; m < 8; ++m) {
@@ -483,6 +493,19 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
       return fail(c, VMLBM_ERANGE, "level %d needs %d block slots, capacity %d", l, nslots, V.cap);
   }
   K.tabulate_ghosts();
+  // ghost cells of each ghost block
+  for (int l = 0; l <= L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    V.band.clear();
+    V.band_off.assign(1, 0);
+    if (l == 0) continue;
+    for (size_t g = 0; g < V.ghost.size(); ++g) {
+      const uint8_t* kd = K.gk[l].data() + g * kBlockCells;
+      for (int c = 0; c < kBlockCells; ++c)
+        if (kd[c] == K_GHOST) V.band.push_back((uint16_t)c);
+      V.band_off.push_back((int)V.band.size());
+    }
+  }
   // explosion: ghost block of level l+1 -> parent interior block of level l
   for (int l = 1; l <= L; ++l) {
     Forest::Lev& V = f.lv[l];
@@ -591,7 +614,8 @@ __device__ __forceinline__ void load_neighbours(const LevelArgs& a, int slot, in
   __syncthreads();
 }
 
-// interior blocks of a level: pull + collide, cells with flags left out
+// interior blocks of a level: pull + collide, cells with flags left out.
+// gridDim.y workgroups share a block, each taking kBlock / gridDim.y planes.
 template <typename S>
 __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
                                                      const uint8_t* __restrict__ flags, const int* __restrict__ list,
@@ -601,7 +625,8 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
   const int slot = list[blockIdx.x];
   load_neighbours(a, slot, nbs);
   const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  for (int z = 0; z < kBlock; ++z) {
+  const int planes = kBlock / gridDim.y, z0 = blockIdx.y * planes;
+  for (int z = z0; z < z0 + planes; ++z) {
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
     if (flags[c]) continue;
     T d[kQ];
@@ -617,17 +642,23 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
   }
 }
 
-// ghost blocks: stream only (sources not stored at this level give 0)
+// ghost cells (the band of each ghost block listed in band[band_off[g] ..
+// band_off[g+1]) as local cell indices): stream only; sources not stored at
+// this level give 0.  Cells of a ghost block outside its band are never
+// read by an update of this level's region within the two substeps.
 template <typename S>
 __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src, S* __restrict__ dst,
-                                                      const int* __restrict__ list, LevelArgs a) {
+                                                      const int* __restrict__ list, const int* __restrict__ band_off,
+                                                      const uint16_t* __restrict__ band, LevelArgs a) {
   using T = typename Store<S>::T;
   __shared__ int nbs[27];
   const int slot = list[blockIdx.x];
   load_neighbours(a, slot, nbs);
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  for (int z = 0; z < kBlock; ++z) {
-    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+  const int b1 = band_off[blockIdx.x + 1];
+  for (int i = band_off[blockIdx.x] + threadIdx.x; i < b1; i += blockDim.x) {
+    const int local = band[i];
+    const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)local;
     T d[kQ];
     ghost_pull<S>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
 #pragma unroll
@@ -635,16 +666,19 @@ __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src,
   }
 }
 
-// explosion: every cell of a ghost block of level l+1 takes its parent's
-// populations (level l, current state)
+// explosion: every ghost cell of level l+1 takes its parent's populations
+// (level l, current state); ghost block g is explode entry g
 template <typename S>
 __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S* __restrict__ fine,
-                                                 const int* __restrict__ ex, uint32_t Nc, uint32_t Nf) {
+                                                 const int* __restrict__ ex, const int* __restrict__ band_off,
+                                                 const uint16_t* __restrict__ band, uint32_t Nc, uint32_t Nf) {
   const int* e = ex + 5 * blockIdx.x;
   const int gs = e[0], ps = e[1], ox = e[2], oy = e[3], oz = e[4];
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  for (int z = 0; z < kBlock; ++z) {
-    const uint32_t cf = (uint32_t)gs * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+  const int b1 = band_off[blockIdx.x + 1];
+  for (int i = band_off[blockIdx.x] + threadIdx.x; i < b1; i += blockDim.x) {
+    const int local = band[i];
+    const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
+    const uint32_t cf = (uint32_t)gs * kBlockCells + (uint32_t)local;
     const uint32_t cc = (uint32_t)ps * kBlockCells +
                         (uint32_t)(((oz + (z >> 1)) * 16 + (oy + (y >> 1))) * 16 + (ox + (x >> 1)));
 #pragma unroll
@@ -652,48 +686,49 @@ __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S
   }
 }
 
-// coalescence cells of level l
+// coalescence cells of level l, kIfaceCells per workgroup: first one thread
+// per (cell, q) gathers the weighted coarse pull and the 1/8-weighted fine
+// ghost children into LDS, then one thread per cell collides and stores.
+constexpr int kIfaceCells = 64;
+
 template <typename S>
 __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __restrict__ dst,
                                                const S* __restrict__ fine, const IfaceEntry* __restrict__ tab,
                                                int count, int* __restrict__ status, LevelArgs a, uint32_t Nf) {
   using T = typename Store<S>::T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
-  const IfaceEntry& e = tab[t];
-  const int* p3 = a.pos + 3 * e.slot;
-  const int x = e.local & 15, y = (e.local >> 4) & 15, z = e.local >> 8;
-  T d[kQ];
-  for (int q = 0; q < kQ; ++q) {
+  __shared__ double pre[kIfaceCells][kQ];
+  const int e0 = blockIdx.x * kIfaceCells;
+  const int n = min(kIfaceCells, count - e0);
+  for (int p = threadIdx.x; p < n * kQ; p += blockDim.x) {
+    const int j = p / kQ, q = p - j * kQ;
+    const IfaceEntry& e = tab[e0 + j];
     double v = 0.0;
-    if (e.weight[q] != 0.0f) {
-      int xs = x - cx_of(q), ys = y - cy_of(q), zs = z - cz_of(q);
-      const int bx = xs < 0 ? -1 : (xs > 15 ? 1 : 0), by = ys < 0 ? -1 : (ys > 15 ? 1 : 0),
-                bz = zs < 0 ? -1 : (zs > 15 ? 1 : 0);
-      const int s = (bx | by | bz) ? nbr_slot(a, p3, bx, by, bz) : e.slot;
-      if (s < 0) {
-        status[kStatusRange] = 7;
-      } else {
-        const uint32_t c = (uint32_t)s * kBlockCells + (uint32_t)(((zs & 15) * 16 + (ys & 15)) * 16 + (xs & 15));
-        v = (double)e.weight[q] * (double)Store<S>::load(src[(size_t)q * a.N + c]);
-      }
-    }
-    if (e.mask[q]) {
+    const float wq = e.weight[q];
+    if (wq != 0.0f) v = (double)wq * (double)Store<S>::load(src[(size_t)q * a.N + e.src[q]]);
+    const unsigned mk = e.mask[q];
+    if (mk) {
       double acc = 0.0;
       for (int m = 0; m < 8; ++m)
-        if (e.mask[q] & (1u << m)) {
+        if (mk & (1u << m)) {
           const uint32_t cf = (uint32_t)e.fine_slot * kBlockCells + (uint32_t)e.fine_local +
                               (uint32_t)(((m >> 2) * 16 + ((m >> 1) & 1)) * 16 + (m & 1));
           acc += (double)Store<S>::load(fine[(size_t)q * Nf + cf]);
         }
       v += 0.125 * acc;
     }
-    d[q] = T(v);
+    pre[j][q] = v;
   }
+  __syncthreads();
+  if ((int)threadIdx.x >= n) return;
+  const IfaceEntry& e = tab[e0 + threadIdx.x];
+  T d[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) d[q] = T(pre[threadIdx.x][q]);
   const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   const uint32_t c = (uint32_t)e.slot * kBlockCells + (uint32_t)e.local;
   SrBits rb(c, a.seed);
+#pragma unroll
   for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store_sr(d[q], rb.next());
 }
 
@@ -876,6 +911,11 @@ int upload_tables(vmlbm_ctx* c) {
     if (!V.iface.empty())
       HIP_TRY(c, hipMemcpy(c->ws + V.off_iface, V.iface.data(), V.iface.size() * sizeof(IfaceEntry),
                            hipMemcpyHostToDevice));
+    if (!V.band.empty())
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_band, V.band.data(), V.band.size() * sizeof(uint16_t),
+                           hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(c->ws + V.off_band_off, V.band_off.data(), V.band_off.size() * sizeof(int),
+                         hipMemcpyHostToDevice));
     V.n_int = (int)V.interior.size();
     V.n_ghost = (int)V.ghost.size();
     V.n_iface = (int)V.iface.size();
@@ -920,6 +960,8 @@ int explode(vmlbm_ctx* c, int l) {
     using S = std::remove_pointer_t<decltype(tag)>;
     k_explode<S><<<F.n_ghost, 256, 0, c->stream>>>((const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]),
                                                    (const int*)(c->ws + F.off_explode),
+                                                   (const int*)(c->ws + F.off_band_off),
+                                                   (const uint16_t*)(c->ws + F.off_band),
                                                    (uint32_t)C.cap * kBlockCells, (uint32_t)F.cap * kBlockCells);
     HIP_TRY(c, hipGetLastError());
     return VMLBM_OK;
@@ -936,19 +978,24 @@ int sweep_level(vmlbm_ctx* c, int l) {
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
     if (V.n_int) {
-      k_level_sweep<S><<<V.n_int, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
-                                                       (const int*)(c->ws + V.off_int), c->status(), a);
+      // levels with few blocks: four workgroups per block (4 planes each)
+      // so that the launch still covers every compute unit several times
+      const dim3 grid(V.n_int, V.n_int < 1024 ? 4 : 1);
+      k_level_sweep<S><<<grid, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
+                                                    (const int*)(c->ws + V.off_int), c->status(), a);
       HIP_TRY(c, hipGetLastError());
     }
     if (V.n_iface) {
       Forest::Lev& F = f.lv[l + 1];
-      k_iface<S><<<(V.n_iface + 255) / 256, 256, 0, c->stream>>>(
+      k_iface<S><<<(V.n_iface + kIfaceCells - 1) / kIfaceCells, 256, 0, c->stream>>>(
           (const S*)src, (S*)dst, (const S*)(c->ws + F.off_pdf[F.cur]), (const IfaceEntry*)(c->ws + V.off_iface),
           V.n_iface, c->status(), a, (uint32_t)F.cap * kBlockCells);
       HIP_TRY(c, hipGetLastError());
     }
     if (V.n_ghost) {
-      k_ghost_stream<S><<<V.n_ghost, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const int*)(c->ws + V.off_ghost), a);
+      k_ghost_stream<S><<<V.n_ghost, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const int*)(c->ws + V.off_ghost),
+                                                          (const int*)(c->ws + V.off_band_off),
+                                                          (const uint16_t*)(c->ws + V.off_band), a);
       HIP_TRY(c, hipGetLastError());
     }
     if (l == f.L && np) {
@@ -1151,6 +1198,8 @@ int refine_plan(vmlbm_ctx* c) {
     V.off_ghost = take((size_t)V.cap * sizeof(int));
     V.off_explode = take((size_t)V.cap * 5 * sizeof(int));
     V.off_iface = take((size_t)V.iface_cap * sizeof(IfaceEntry));
+    V.off_band = take((size_t)V.cap * kBlockCells * sizeof(uint16_t));
+    V.off_band_off = take((size_t)(V.cap + 1) * sizeof(int));
   }
   f.off_owner = take((size_t)f.lv[f.L].cap * kBlockCells * sizeof(uint16_t));
   for (int b = 0; b < 2; ++b) f.off_leaf[b] = take(f.leaf.size());
