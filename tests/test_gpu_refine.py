@@ -134,3 +134,34 @@ def test_moving_sphere_rerefinement(env):
     oo = ref.owner()
     for b, (x, y, z) in enumerate(org):
         assert (og[b] == oo[z:z + 16, y:y + 16, x:x + 16]).all()
+
+
+def test_refined_layout_across_periodic_boundary(env):
+    """Two-level grid, sphere near x = 0: its refined region wraps around the
+    periodic boundary (coarse nodes 3 and 0 of 4 along x) and grows to node 1
+    once the sphere's grown box crosses x = 48 (after 2 cells of motion);
+    layouts, forces and populations follow the oracle throughout."""
+    pkg, oracle = env
+    n0 = (64, 32, 32)
+    c = cfg_of(n0, 2, omega=1.7, F=(0.0, 0.0, 2e-6))
+    s = synth.sphere((8.0, 31.3, 33.7), 6.0, density_ratio=2e3, cv=0.5, fixed=False, u=(0.05, 0.0, 0.01))
+    u0 = synth.velocity_perturbation(n0, seed=12)
+    say("case refined64x32x32 L2 periodic wrap f64")
+    sim = pkg.Sim(c, [s], storage="f64", history=8, check_every=4)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, spheres=[s], check_every=4)
+    ref.init(1.0, u0)
+    leaf = ref.leaf()
+    assert leaf[:, :, 0].max() == 1 and leaf[:, :, -1].max() == 1 and leaf.min() == 0   # wraps
+    for k in range(1, 25):
+        sim.step(1)
+        ref.step(1)
+        Fg, Tg = sim.force_torque(0)
+        Fo, To = ref.force_torque(0)
+        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), 6.0 * np.abs(Fo).max()), (k, Tg, To)
+    sim.sync()
+    assert sim.refinements() == ref.counters()[2] >= 1
+    rel = compare_levels(sim, ref, 2)
+    say(f"  refinements {sim.refinements()}; population rel err {rel:.2e}")
+    assert rel <= 1e-11

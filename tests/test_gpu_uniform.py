@@ -286,3 +286,64 @@ def test_nan_injection_flags_unstable(env):
     with pytest.raises(pkg.VmlbmError) as e:
         sim.sync()
     assert e.value.code == -5
+
+
+def run_parity(pkg, oracle, cfg, sph, steps, radius, tag, tol_ft=1e-9, tol_pop=1e-11, owner_every=1):
+    say(f"case {tag}")
+    sim = pkg.Sim(cfg, sph, storage="f64", history=4)
+    sim.init()
+    ref = oracle.Uniform(cfg, sph)
+    ref.init()
+    for k in range(1, steps + 1):
+        sim.step(1)
+        ref.step(1)
+        if k % owner_every == 0:
+            flips = int((sim.owner() != ref.owner()).sum())
+            assert flips == 0, f"step {k}: {flips} mapping differences"
+        check_ft(sim, ref, len(sph), radius, tol=tol_ft, where=f"step {k}")
+    sim.sync()
+    for i in range(len(sph)):
+        xg, ug, wg = sim.particle(i)
+        xo, uo, wo = ref.particle(i)
+        assert np.abs(xg - xo).max() < 1e-11
+        assert np.abs(ug - uo).max() < 1e-12 and np.abs(wg - wo).max() < 1e-12
+    rel = pop_rel(sim.populations(), ref.post_collision())
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= tol_pop
+    sim.close()
+
+
+def test_spheres_across_periodic_corner(env):
+    """Ragged periodic box (30x28x26): a fixed sphere straddling the corner
+    where all three periodic boundaries meet, and a moving sphere that
+    crosses x = 0 during the run (minimum-image geometry, wrapped boxes,
+    re-mapping across the boundary)."""
+    pkg, oracle = env
+    n = (30, 28, 26)
+    cfg = synth.base_config(n, omega=1.5, body_force=(2e-5, -1e-5, 1e-5))
+    fixed = synth.sphere((0.4, 27.3, 25.8), 4.7, fixed=True)
+    moving = synth.sphere((2.2, 13.6, 12.7), 3.9, density_ratio=50.0, cv=0.5, fixed=False,
+                          u=(-0.06, 0.004, 0.0), w=(0.0, 0.0, 0.003))
+    run_parity(pkg, oracle, cfg, [fixed, moving], 90, 4.7, "corner30x28x26 f64")
+
+
+def test_tiny_sphere_cli_fallback(env):
+    """Sphere of radius 1.3: links whose second node x + c_q is solid use the
+    fallback kappa0 = 0, alpha = 2; cells link the sphere from opposite
+    sides.  Moving, so cells are covered and uncovered."""
+    pkg, oracle = env
+    n = (18, 16, 20)
+    cfg = synth.base_config(n, omega=1.2, body_force=(0.0, 0.0, 1e-5))
+    s = synth.sphere((8.7, 7.9, 10.3), 1.3, density_ratio=3.0, cv=0.5, fixed=False, u=(0.02, -0.01, 0.03))
+    run_parity(pkg, oracle, cfg, [s], 80, 1.3, "tiny-sphere18x16x20 f64")
+
+
+def test_sphere_next_to_wall(env):
+    """Moving sphere 1.5 cells above a no-slip wall: cells between them carry
+    wall links and particle links at once."""
+    pkg, oracle = env
+    n = (24, 22, 26)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.6, gravity=(0.0, 0.0, -2e-4),
+                            wall_velocity=((0.002, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    s = synth.sphere((11.6, 10.9, 5.5), 4.0, density_ratio=2.0, cv=0.5, fixed=False, u=(0.0, 0.0, -0.004))
+    run_parity(pkg, oracle, cfg, [s], 80, 4.0, "wall-sphere24x22x26 f64")
