@@ -40,23 +40,54 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     if (st < 0) { status[kStatusRange] = 5; sidx[q] = c; }
   }
 #pragma unroll
-  for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;
-  // pass 2: plain streaming where the source is fluid
+  for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;   // sidx = c across walls
+  // pass 2: plain streaming where the source is fluid (every source is a
+  // stored cell, so the loads need no guard)
   d[0] = Store<S>::load(src[c]);
 #pragma unroll
-  for (int q = 1; q < kQ; ++q)
-    if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = Store<S>::load(src[(size_t)q * N + sidx[q]]);
-  // pass 3: links
+  for (int q = 1; q < kQ; ++q) {
+    const T v = Store<S>::load(src[(size_t)q * N + sidx[q]]);
+    if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = v;
+  }
+  // pass 3: links.  Each stage issues its loads for all directions at once
+  // (non-link directions read the cell itself), so the dependent accesses
+  // of the directions overlap instead of following one another.
+  bool link[kQ];
+  T own[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) own[q] = Store<S>::load(src[(size_t)q * N + c]);
+  int pq[kQ];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    link[q] = wall[q] >= 0 || (sfl[q] & kSolid);
+    pq[q] = owner[(link[q] && wall[q] < 0) ? sidx[q] : c];
+  }
+  // second node x - c_qq = x + c_q of each particle link
+  uint32_t tidx[kQ];
+  bool tok[kQ];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    int wa2 = 0, ws2 = 0;
+    tidx[q] = c;
+    tok[q] = link[q] && wall[q] < 0 &&
+             ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), tidx[q], wa2, ws2) == 1;
+    if (!tok[q]) tidx[q] = c;
+  }
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) tok[q] = tok[q] && !(flags[tidx[q]] & kSolid);
+  T sec[kQ];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) sec[q] = Store<S>::load(src[(size_t)opp_of(q) * N + (tok[q] ? tidx[q] : c)]);
   if (link_mask) *link_mask = 0;
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
     if (kappa_out) kappa_out[q] = T(0);
-    if (wall[q] < 0 && !(sfl[q] & kSolid)) continue;
+    if (!link[q]) continue;
     if (link_mask) *link_mask |= 1u << q;
     const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
     const int qq = opp_of(q);
     const double w = w_of(q);
-    const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
+    const T own_qq = own[qq];
     if (wall[q] >= 0) {
       // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
       const int wa = wall[q] >> 1, ws = wall[q] & 1;
@@ -67,7 +98,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
       continue;
     }
     // particle link in direction qq (c_qq = -c_q points into the solid)
-    const int pi = owner[sidx[q]];
+    const int pi = pq[q];
     const DevParticle& P = parts[pi];
     double off[3];
     sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
@@ -78,21 +109,12 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
                    P.u[2] + (P.w[0] * rb[1] - P.w[1] * rb[0])};
     double kappa = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
     double alpha = 4.0 / (1.0 + 2.0 * delta);
-    // second node x - c_qq = x + c_q
-    uint32_t tidx = 0;
-    int wa2 = 0, ws2 = 0;
-    bool second_ok = ad.locate(x + cq[0], y + cq[1], z + cq[2], tidx, wa2, ws2) == 1;
-    if (second_ok && (flags[tidx] & kSolid)) second_ok = false;
-    if (!second_ok) { kappa = 0.0; alpha = 2.0; }
+    if (!tok[q]) { kappa = 0.0; alpha = 2.0; }
     if (kappa_out) kappa_out[q] = T(kappa);
     // c_qq . v with c_qq = -c_q
     const double cqv = -(cq[0] * v[0] + cq[1] * v[1] + cq[2] * v[2]);
     T val = own_qq - T(3.0 * alpha * w * cqv);
-    if (second_ok) {
-      const T sec = Store<S>::load(src[(size_t)qq * N + tidx]);
-      const T own_q = Store<S>::load(src[(size_t)q * N + c]);
-      val = val + T(kappa) * (sec - own_q);
-    }
+    if (tok[q]) val = val + T(kappa) * (sec[q] - own[q]);
     d[q] = val;
     // link force: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
     const double a0 = (double)own_qq, a1 = (double)val;
