@@ -208,6 +208,32 @@ def copy_reference():
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}), flush=True)
 
 
+def stream_reference(nbytes=4 << 30, reps=10):
+    """What PyTorch's own streaming kernels reach on this GPU: read (sum),
+    write (fill) and copy of nbytes, GB/s of bytes moved.  A 1:1 read/write
+    stream such as the interior sweep is bounded by the copy figure."""
+    import torch
+    n = nbytes // 4
+    x = torch.ones(n, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(x)
+    out = {}
+    for name, fn, moved in (("read", lambda: x.sum(), nbytes), ("write", lambda: y.fill_(1.5), nbytes),
+                            ("copy", lambda: y.copy_(x), 2 * nbytes)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_gbs"] = round(moved * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle on a bounded sample of the headline workload: a 128^3
     periodic box holding one of its fixed r=20 spheres, same omega and body
@@ -259,6 +285,9 @@ def main():
     import synth
     import paper_2103_10882_amd as pkg
     pkg.lib()
+    log("stream reference")
+    sref = stream_reference()
+    log(f"  {sref}")
     w = synth.precision(n=args.n)
     drag_window = 200
     drag_steps = max(args.drag_steps, args.warmup + args.steps + drag_window)
@@ -307,6 +336,8 @@ def main():
             "frac": round(b["sweep_gbs"] / PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
             "traffic_over_algorithmic": None if traffic is None else round(traffic / b["sweep_bytes"], 3),
+            "stream_reference_gbs": sref,
+            "frac_of_copy": round(b["sweep_gbs"] / sref["copy_gbs"], 3),
             "bytes_per_launch": b["sweep_bytes"],
             "launch_ms": round(b["sweep_ms"], 4),
         },

@@ -33,7 +33,7 @@ class Config(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("periodic", ctypes.c_int * 3),
                 ("wall_velocity", (ctypes.c_double * 3) * 2), ("omega", ctypes.c_double),
                 ("magic", ctypes.c_double), ("body_force", ctypes.c_double * 3),
-                ("gravity", ctypes.c_double * 3)]
+                ("gravity", ctypes.c_double * 3), ("bulk_factor", ctypes.c_double)]
 
 
 class Sphere(ctypes.Structure):
@@ -58,6 +58,7 @@ def lib():
         for name, args in [
             ("ora_add_sphere", [vp, ctypes.POINTER(Sphere)]),
             ("ora_init", [vp, ctypes.c_double, ctypes.c_void_p]),
+            ("ora_init_fields", [vp, ctypes.c_void_p, ctypes.c_void_p]),
             ("ora_step", [vp, ctypes.c_int]),
             ("ora_post_collision", [vp, ctypes.c_void_p]),
             ("ora_pre_collision", [vp, ctypes.c_void_p]),
@@ -87,6 +88,11 @@ def lib():
                                        ctypes.c_void_p, ctypes.c_void_p]
         L.ora_equilibrium.restype = None
         L.ora_equilibrium.argtypes = [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_collide_cell_mrt.restype = None
+        L.ora_collide_cell_mrt.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_void_p, ctypes.c_void_p]
+        L.ora_mrt_basis.restype = None
+        L.ora_mrt_basis.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.ora_refill_populations.restype = None
         L.ora_refill_populations.argtypes = [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                              ctypes.c_void_p]
@@ -114,6 +120,7 @@ def make_config(cfg):
             c.wall_velocity[s][a] = float(cfg["wall_velocity"][s][a])
     c.omega = float(cfg["omega"])
     c.magic = float(cfg["magic"])
+    c.bulk_factor = float(cfg.get("bulk_factor", 1.0))
     return c
 
 
@@ -162,6 +169,22 @@ def refill_populations(rho, v, S, omega):
     return out
 
 
+def collide_cell_mrt(f, omega, magic, bulk_factor, F):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros(19)
+    lib().ora_collide_cell_mrt(f.ctypes.data, float(omega), float(magic), float(bulk_factor), F.ctypes.data,
+                               out.ctypes.data)
+    return out
+
+
+def mrt_basis():
+    e = np.zeros((19, 19))
+    norm = np.zeros(19)
+    lib().ora_mrt_basis(e.ctypes.data, norm.ctypes.data)
+    return e, norm
+
+
 def link_delta(d, c, radius):
     d = np.ascontiguousarray(d, dtype=np.float64)
     c = np.ascontiguousarray(c, dtype=np.int32)
@@ -202,12 +225,17 @@ class Uniform:
             self.h = None
 
     def init(self, rho=1.0, u0=None):
+        """Equilibrium start; rho a number or a per-cell [nz][ny][nx] field."""
         if u0 is not None:
             u0 = np.ascontiguousarray(u0, dtype=np.float64)
             assert u0.size == 3 * self.N
-            _check(lib().ora_init(self.h, float(rho), u0.ctypes.data), "init")
+        up = u0.ctypes.data if u0 is not None else None
+        if np.ndim(rho) > 0:
+            r = np.ascontiguousarray(rho, dtype=np.float64)
+            assert r.size == self.N
+            _check(lib().ora_init_fields(self.h, r.ctypes.data, up), "init")
         else:
-            _check(lib().ora_init(self.h, float(rho), None), "init")
+            _check(lib().ora_init(self.h, float(rho), up), "init")
 
     def step(self, n=1):
         _check(lib().ora_step(self.h, int(n)), "step")
@@ -283,7 +311,8 @@ def num_threads():
 class RConfig(ctypes.Structure):
     _fields_ = [("n0", ctypes.c_int * 3), ("block", ctypes.c_int), ("levels", ctypes.c_int),
                 ("omega", ctypes.c_double), ("magic", ctypes.c_double), ("body_force", ctypes.c_double * 3),
-                ("gravity", ctypes.c_double * 3), ("check_every", ctypes.c_int)]
+                ("gravity", ctypes.c_double * 3), ("check_every", ctypes.c_int),
+                ("bulk_factor", ctypes.c_double)]
 
 
 def _bind_refine(L):
@@ -331,6 +360,7 @@ class Refined:
         c.omega = float(cfg["omega"])
         c.magic = float(cfg["magic"])
         c.check_every = int(check_every)
+        c.bulk_factor = float(cfg.get("bulk_factor", 1.0))
         self._c = c
         self.h = lib().orf_create(ctypes.byref(c))
         if not self.h:

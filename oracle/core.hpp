@@ -121,6 +121,91 @@ void collide(const T f[19], const T& sp, const T& sm, const T F[3], T out[19]) {
 }
 
 // ---------------------------------------------------------------------------
+// MRT collision (Sec. 2.1): C = M^-1 S M.  Moments in a D3Q19 basis that is
+// orthogonal with respect to the lattice weights (the basis of Duenweg,
+// Schiller and Ladd): density; momentum (3); bulk c^2 - 1; shear 3cx^2 - c^2,
+// cy^2 - cz^2, cx cy, cy cz, cz cx; odd ghosts (3c^2 - 5) c_a and
+// (cy^2 - cz^2) cx, (cz^2 - cx^2) cy, (cx^2 - cy^2) cz; even ghosts
+// 3c^4 - 6c^2 + 1, (2c^2 - 3)(3cx^2 - c^2), (2c^2 - 3)(cy^2 - cz^2).
+// Relaxation as the paper assigns it: conserved moments 0; the isotropic
+// pair (bulk and the isotropic even ghost) s_b; the shear moments and the
+// two tensor even ghosts s_nu; the six odd ghosts s-.  Reading: the rates
+// are shared within each isotropy sector, so the operator does not depend on
+// which orthogonal basis spans the sectors.  Forcing enters in moment space
+// with (I - S/2) (Guo).  s_b from the bulk factor:
+// 1/s_b - 1/2 = Lambda_b (1/s_nu - 1/2).
+// ---------------------------------------------------------------------------
+struct MrtBasis {
+  double e[19][19];   // e[a][q]: basis polynomial a at velocity q
+  double norm[19];    // sum_q w_q e[a][q]^2
+  int rate[19];       // 0 conserved, 1 s_b, 2 s_nu, 3 s-
+  MrtBasis() {
+    for (int q = 0; q < 19; ++q) {
+      const double x = CX[q], y = CY[q], z = CZ[q], c2 = x * x + y * y + z * z;
+      const double v[19] = {1.0, x, y, z, c2 - 1.0,
+                            3.0 * x * x - c2, y * y - z * z, x * y, y * z, z * x,
+                            (3.0 * c2 - 5.0) * x, (3.0 * c2 - 5.0) * y, (3.0 * c2 - 5.0) * z,
+                            (y * y - z * z) * x, (z * z - x * x) * y, (x * x - y * y) * z,
+                            3.0 * c2 * c2 - 6.0 * c2 + 1.0, (2.0 * c2 - 3.0) * (3.0 * x * x - c2),
+                            (2.0 * c2 - 3.0) * (y * y - z * z)};
+      for (int a = 0; a < 19; ++a) e[a][q] = v[a];
+    }
+    for (int a = 0; a < 19; ++a) {
+      norm[a] = 0.0;
+      for (int q = 0; q < 19; ++q) norm[a] += weight(q) * e[a][q] * e[a][q];
+    }
+    const int r[19] = {0, 0, 0, 0, 1, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 1, 2, 2};
+    for (int a = 0; a < 19; ++a) rate[a] = r[a];
+  }
+};
+
+inline const MrtBasis& mrt_basis() {
+  static const MrtBasis B;
+  return B;
+}
+
+inline double s_bulk(double snu, double bulk_factor) { return 1.0 / (0.5 + bulk_factor * (1.0 / snu - 0.5)); }
+
+inline void collide_mrt(const double f[19], double snu, double sm, double sb, const double F[3], double out[19]) {
+  const MrtBasis& B = mrt_basis();
+  double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < 19; ++q) {
+    rho += f[q];
+    j[0] += CX[q] * f[q];
+    j[1] += CY[q] * f[q];
+    j[2] += CZ[q] * f[q];
+  }
+  double u[3];
+  for (int a = 0; a < 3; ++a) u[a] = j[a] + 0.5 * F[a];
+  double feq[19], S[19];
+  equilibrium(rho, u, feq);
+  for (int q = 0; q < 19; ++q) {
+    const double cmu[3] = {CX[q] - u[0], CY[q] - u[1], CZ[q] - u[2]};
+    const double cu = CX[q] * u[0] + CY[q] * u[1] + CZ[q] * u[2];
+    const double cF = CX[q] * F[0] + CY[q] * F[1] + CZ[q] * F[2];
+    S[q] = weight(q) * (3.0 * (cmu[0] * F[0] + cmu[1] * F[1] + cmu[2] * F[2]) + 9.0 * cu * cF);
+  }
+  const double rates[4] = {0.0, sb, snu, sm};
+  double mpost[19];
+  for (int a = 0; a < 19; ++a) {
+    double m = 0.0, meq = 0.0, ms = 0.0;
+    for (int q = 0; q < 19; ++q) {
+      m += B.e[a][q] * f[q];
+      meq += B.e[a][q] * feq[q];
+      ms += B.e[a][q] * S[q];
+    }
+    const double s = rates[B.rate[a]];
+    mpost[a] = m - s * (m - meq) + (1.0 - 0.5 * s) * ms;
+  }
+  // f = M^-1 m with (M^-1)_{q a} = w_q e_a(q) / norm_a
+  for (int q = 0; q < 19; ++q) {
+    double v = 0.0;
+    for (int a = 0; a < 19; ++a) v += weight(q) * B.e[a][q] * mpost[a] / B.norm[a];
+    out[q] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // sphere geometry (Sec. 2.3): a cell is solid iff its centre lies in the
 // sphere (reading: |x_c - x_p|^2 <= r^2, minimum image on periodic axes);
 // the boundary distance ratio delta_q is the exact ray-sphere root.

@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 #include <omp.h>
 
@@ -45,6 +46,8 @@ struct Grid {
   std::vector<unsigned char> has_link;
   std::vector<Sph> sph;
   T sp, sm, F[3];
+  double sb = 0.0;              // MRT bulk rate (used when mrt)
+  bool mrt = false;
   int steps = 0;
   int wall_axis = -1;
 
@@ -59,6 +62,8 @@ struct Grid {
     sp = T(c.omega);
     sm = s_minus(sp, c.magic);
     for (int a = 0; a < 3; ++a) F[a] = T(c.body_force[a]);
+    mrt = c.bulk_factor > 0.0 && c.bulk_factor != 1.0;
+    if (mrt) sb = s_bulk(c.omega, c.bulk_factor);
   }
 
   // offset from a sphere centre to a point, minimum image on periodic axes
@@ -102,7 +107,7 @@ struct Grid {
     for (int a = 0; a < 3; ++a) v[a] = (axis == wall_axis) ? cfg.wall_velocity[side][a] : 0.0;
   }
 
-  void init(double rho, const double* u0) {
+  void init(double rho, const double* u0, const double* rho_field = nullptr) {
     map_all(own);
     f.assign(19 * N, T(0.0));
     ft.assign(19 * N, T(0.0));
@@ -113,7 +118,7 @@ struct Grid {
       T u[3];
       for (int a = 0; a < 3; ++a) u[a] = T(u0 ? u0[a * N + c] : 0.0);
       T feq[19];
-      equilibrium(T(rho), u, feq);
+      equilibrium(T(rho_field ? rho_field[c] : rho), u, feq);
       for (int q = 0; q < 19; ++q) f[q * N + c] = feq[q];
     }
     for (auto& s : sph) {
@@ -129,7 +134,12 @@ struct Grid {
       if (own[c] >= 0) continue;
       T a[19], b[19];
       for (int q = 0; q < 19; ++q) a[q] = src[q * N + c];
-      collide(a, sp, sm, F, b);
+      if constexpr (std::is_same<T, double>::value) {
+        if (mrt) collide_mrt(a, sp, sm, sb, F, b);
+        else collide(a, sp, sm, F, b);
+      } else {
+        collide(a, sp, sm, F, b);
+      }
       for (int q = 0; q < 19; ++q) dst[q * N + c] = b[q];
     }
   }
@@ -396,6 +406,19 @@ void ora_collide_cell(const double f[19], double omega, double magic, const doub
 
 void ora_equilibrium(double rho, const double u[3], double out[19]) { equilibrium(rho, u, out); }
 
+void ora_collide_cell_mrt(const double f[19], double omega, double magic, double bulk_factor, const double F[3],
+                          double out[19]) {
+  collide_mrt(f, omega, s_minus(omega, magic), s_bulk(omega, bulk_factor), F, out);
+}
+
+void ora_mrt_basis(double e[19][19], double norm[19]) {
+  const MrtBasis& B = mrt_basis();
+  for (int a = 0; a < 19; ++a) {
+    norm[a] = B.norm[a];
+    for (int q = 0; q < 19; ++q) e[a][q] = B.e[a][q];
+  }
+}
+
 void ora_refill_populations(double rho, const double v[3], const double S[9], double omega, double out[19]) {
   double M[3][3];
   for (int a = 0; a < 3; ++a)
@@ -426,6 +449,13 @@ int ora_init(void* h, double rho, const double* u0) {
   auto* G = static_cast<Grid<double>*>(h);
   if (!G) return -1;
   G->init(rho, u0);
+  return 0;
+}
+
+int ora_init_fields(void* h, const double* rho, const double* u0) {
+  auto* G = static_cast<Grid<double>*>(h);
+  if (!G || !rho) return -1;
+  G->init(1.0, u0, rho);
   return 0;
 }
 
@@ -519,6 +549,7 @@ void ora_destroy(void* h) { delete static_cast<Grid<double>*>(h); }
 int ora_drag_gradient(const ora_config* cfg, const ora_sphere* spheres, int nspheres, int n_steps,
                       int avg_from, double* J, double grad[2]) {
   if (!cfg || n_steps <= avg_from || avg_from < 0) return -1;
+  if (cfg->bulk_factor > 0.0 && cfg->bulk_factor != 1.0) return -1;   // TRT only
   D2 fmag(cfg->body_force[2]);
   fmag.d[0] = 1.0;
   D2 om(cfg->omega);

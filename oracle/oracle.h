@@ -31,6 +31,7 @@ typedef struct {
   double magic;             /* Lambda */
   double body_force[3];     /* fluid force density (Guo forcing) */
   double gravity[3];        /* acts on particles only */
+  double bulk_factor;       /* Lambda_b of the MRT collision; 0 or 1 = TRT */
 } ora_config;
 
 typedef struct {
@@ -45,6 +46,11 @@ void ora_lattice(int c[19][3], double w[19], int opp[19]);
 /* single-cell TRT collision with Guo forcing on full populations f[19] */
 void ora_collide_cell(const double f[19], double omega, double magic,
                       const double F[3], double out[19]);
+/* single-cell MRT collision (explicit moment basis) with bulk factor Lambda_b */
+void ora_collide_cell_mrt(const double f[19], double omega, double magic, double bulk_factor,
+                          const double F[3], double out[19]);
+/* the MRT moment basis: e[a][q] and the weighted norms sum_q w_q e[a][q]^2 */
+void ora_mrt_basis(double e[19][19], double norm[19]);
 /* incompressible equilibrium f^eq(rho, u) */
 void ora_equilibrium(double rho, const double u[3], double out[19]);
 /* populations of a refilled cell from density, velocity and a strain rate
@@ -58,6 +64,8 @@ double ora_link_delta(const double d[3], const int c[3], double radius);
 void* ora_create(const ora_config* cfg);
 int ora_add_sphere(void* h, const ora_sphere* s);
 int ora_init(void* h, double rho, const double* u0 /* [3][nz][ny][nx] or NULL */);
+/* same with a density per cell ([nz][ny][nx]) */
+int ora_init_fields(void* h, const double* rho, const double* u0);
 int ora_step(void* h, int nsteps);
 int ora_post_collision(void* h, double* out);  /* f~(n), solid cells = 0 */
 int ora_pre_collision(void* h, double* out);   /* f(n), solid cells = 0 */

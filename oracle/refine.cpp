@@ -44,6 +44,7 @@ typedef struct {
   double body_force[3];
   double gravity[3];
   int check_every;
+  double bulk_factor;   /* Lambda_b of the MRT collision; 0 or 1 = TRT */
 } orf_config;
 
 typedef struct {
@@ -63,7 +64,13 @@ struct RLevel {
   long N = 0;
   std::vector<double> cur, nxt, pre;   // [19][N]
   std::vector<uint8_t> kind;
-  double sp = 0, sm = 0, F[3] = {0, 0, 0};
+  double sp = 0, sm = 0, sb = 0, F[3] = {0, 0, 0};
+  bool mrt = false;
+  // TRT, or the MRT of Sec. 2.1 when the bulk factor differs from 1
+  void coll(const double a[19], const double Fl[3], double o[19]) const {
+    if (mrt) collide_mrt(a, sp, sm, sb, Fl, o);
+    else collide(a, sp, sm, Fl, o);
+  }
 };
 
 struct RForest {
@@ -324,7 +331,7 @@ struct RForest {
       double a[19], o[19];
       for (int q = 0; q < 19; ++q) a[q] = V.pre[q * V.N + c];
       double Fl[3] = {V.F[0], V.F[1], V.F[2]};
-      collide(a, V.sp, V.sm, Fl, o);
+      V.coll(a, Fl, o);
       for (int q = 0; q < 19; ++q) V.nxt[q * V.N + c] = o[q];
     }
     std::swap(V.cur, V.nxt);
@@ -511,6 +518,8 @@ void* orf_create(const orf_config* cfg) {
     V.N = (long)V.n[0] * V.n[1] * V.n[2];
     V.sp = 1.0 / tau;
     V.sm = s_minus(V.sp, cfg->magic);
+    V.mrt = cfg->bulk_factor > 0.0 && cfg->bulk_factor != 1.0;
+    if (V.mrt) V.sb = s_bulk(V.sp, cfg->bulk_factor);
     for (int a = 0; a < 3; ++a) V.F[a] = cfg->body_force[a] * (double)(1 << (R->L - l));
     tau = 0.5 + 0.5 * (tau - 0.5);
   }
@@ -571,7 +580,7 @@ int orf_init(void* h, double rho, const double* u0_coarse) {
           for (int a = 0; a < 3; ++a) u[a] = u0_coarse ? u0_coarse[a * C0.N + c0] : 0.0;
           double feq[19], o[19];
           equilibrium(rho, u, feq);
-          collide(feq, V.sp, V.sm, V.F, o);
+          V.coll(feq, V.F, o);
           for (int q = 0; q < 19; ++q) V.cur[q * V.N + c] = o[q];
         }
   }
@@ -594,7 +603,7 @@ int orf_set_level_velocity(void* h, int level, double rho, const double* u) {
     double uc[3] = {u[c], u[V.N + c], u[2 * V.N + c]};
     double feq[19], o[19];
     equilibrium(rho, uc, feq);
-    collide(feq, V.sp, V.sm, V.F, o);
+    V.coll(feq, V.F, o);
     for (int q = 0; q < 19; ++q) V.cur[q * V.N + c] = o[q];
   }
   return 0;

@@ -374,3 +374,111 @@ def test_drag_gradient_vs_finite_difference(ora):
     cm = dict(cfg, omega=1.6 - hw)
     fd = (ora.drag_value(cp, sph, steps, avg) - ora.drag_value(cm, sph, steps, avg)) / (2 * hw)
     assert abs(fd - g[1]) <= 1e-5 * abs(g[1])
+
+
+# --------------------------------------------------------------------------
+# MRT collision (Sec. 2.1): moment basis, reduction to TRT, rates per sector,
+# bulk viscosity from sound damping
+# --------------------------------------------------------------------------
+def test_mrt_basis_orthogonal(ora):
+    e, norm = ora.mrt_basis()
+    c, w, _ = ora.lattice()
+    G = (e * w[None, :]) @ e.T
+    assert np.abs(G - np.diag(norm)).max() < 1e-15
+    assert np.array_equal(e[0], np.ones(19)) and np.array_equal(e[1:4], c.T.astype(float))
+    assert np.linalg.matrix_rank(e) == 19
+
+
+def near_eq_state(ora, rng, amp=0.02):
+    c, _, _ = ora.lattice()
+    u = rng.uniform(-0.05, 0.05, 3)
+    f = ora.equilibrium(1.0 + rng.uniform(-0.02, 0.02), u)
+    return f * (1.0 + rng.uniform(-amp, amp, 19))
+
+
+def test_mrt_equals_trt_at_unit_bulk_factor(ora):
+    rng = np.random.default_rng(21)
+    for omega in (0.8, 1.6, 1.95):
+        for _ in range(4):
+            f = near_eq_state(ora, rng)
+            F = rng.uniform(-1e-4, 1e-4, 3)
+            a = ora.collide_cell_mrt(f, omega, 3.0 / 16.0, 1.0, F)
+            b = ora.collide_cell(f, omega, 3.0 / 16.0, F)
+            assert np.abs(a - b).max() < 2e-16
+
+
+def test_mrt_invariants_and_sector_rates(ora):
+    """Mass exact, momentum gains F exactly, equilibrium a fixed point; a
+    perturbation in one isotropy sector (zero density and momentum) is
+    scaled by 1 - s of that sector: the isotropic even part (a function of
+    |c|^2) by 1 - s_b, a shear pattern by 1 - s_nu, an odd third-order
+    pattern by 1 - s-."""
+    c, w, _ = ora.lattice()
+    rng = np.random.default_rng(22)
+    omega, magic, lb = 1.7, 3.0 / 16.0, 100.0
+    s_nu = omega
+    s_m = 1.0 / (0.5 + magic / (1.0 / omega - 0.5))
+    s_b = 1.0 / (0.5 + lb * (1.0 / omega - 0.5))
+    for _ in range(4):
+        f = near_eq_state(ora, rng)
+        F = rng.uniform(-1e-4, 1e-4, 3)
+        o = ora.collide_cell_mrt(f, omega, magic, lb, F)
+        assert abs(o.sum() - f.sum()) < 1e-15
+        assert np.abs(c.T @ o - c.T @ f - F).max() < 1e-16
+    feq = ora.equilibrium(1.01, np.array([0.02, -0.03, 0.01]))
+    assert np.abs(ora.collide_cell_mrt(feq, omega, magic, lb, np.zeros(3)) - feq).max() < 1e-15
+    c2 = (c ** 2).sum(axis=1).astype(float)
+    x, y, z = c[:, 0].astype(float), c[:, 1].astype(float), c[:, 2].astype(float)
+    iso = 3.0 * c2 * c2 - 6.0 * c2 + 1.0          # w-orthogonal to 1 and c^2 - 1's mass
+    iso = iso - (w @ iso)                          # zero density
+    for pattern, s in ((w * iso, s_b), (w * (c2 - 1.0), s_b), (w * x * y, s_nu), (w * (y * y - z * z), s_nu),
+                       (w * (3.0 * c2 - 5.0) * x, s_m), (w * (x * x - y * y) * z, s_m)):
+        d = 1e-3 * pattern / np.abs(pattern).max()
+        assert abs(d.sum()) < 1e-18 and np.abs(c.T @ d).max() < 1e-18
+        o = ora.collide_cell_mrt(feq + d, omega, magic, lb, np.zeros(3))
+        assert np.abs(o - feq - (1.0 - s) * d).max() < 1e-15
+
+
+@pytest.mark.parametrize("lb,n", [(1.0, 64), (10.0, 64), (100.0, 512)])
+def test_mrt_sound_and_shear_damping(ora, lb, n):
+    """Periodic line of n cells, omega = 1.6: a standing sound wave decays at
+    Gamma = k^2/2 (4 nu/3 + nu_b) with nu_b = 2/3 c_s^2 (1/s_b - 1/2) (the
+    bulk viscosity of Sec. 2.1), a shear wave at nu k^2 whatever the bulk
+    factor.  The density mode rho_k(t) is fitted to A exp(-Gamma t)
+    cos(w t + phi) over several periods.  The formula is the hydrodynamic
+    limit: the bulk relaxation time 1/s_b must be short against the wave
+    period (w / s_b <~ 0.1, hence 512 cells for the paper's Lambda_b = 100);
+    discretisation error is of order (k dx)^2 <~ 1e-2."""
+    from scipy.optimize import curve_fit
+    omega = 1.6
+    k = 2.0 * np.pi / n
+    nu = (1.0 / omega - 0.5) / 3.0
+    nub = 2.0 / 3.0 * (1.0 / 3.0) * lb * (1.0 / omega - 0.5)
+    exact = 0.5 * k * k * (4.0 * nu / 3.0 + nub)
+    xs = np.arange(n) + 0.5
+    cfg = synth.base_config((n, 1, 1), omega=omega)
+    cfg["bulk_factor"] = lb
+    o = ora.Uniform(cfg)
+    o.init((1.0 + 1e-4 * np.cos(k * xs)).reshape(1, 1, n))
+    T = max(600, int(3.0 / exact))
+    series = []
+    for t in range(T + 1):
+        rho, _ = o.fields()
+        series.append(((rho[0, 0] - 1.0) * np.cos(k * xs)).sum())
+        o.step(1)
+    ts = np.arange(T + 1, dtype=float)
+    model = lambda t, A, g, w, ph: A * np.exp(-g * t) * np.cos(w * t + ph)
+    p, _ = curve_fit(model, ts, np.array(series), p0=(series[0], exact, k / np.sqrt(3.0), 0.0))
+    assert abs(p[1] / exact - 1.0) < 0.02, (p[1], exact)
+    # shear: transverse velocity wave
+    u0 = np.zeros((3, 1, 1, n))
+    u0[1, 0, 0] = 1e-4 * np.cos(k * xs)
+    o3 = ora.Uniform(cfg)
+    o3.init(1.0, u0)
+    _, u = o3.fields()
+    a0 = (u[1, 0, 0] * np.cos(k * xs)).sum()
+    Ts = min(2000, int(1.0 / (nu * k * k)))
+    o3.step(Ts)
+    _, u = o3.fields()
+    a1 = (u[1, 0, 0] * np.cos(k * xs)).sum()
+    assert abs(-np.log(a1 / a0) / Ts / (nu * k * k) - 1.0) < 0.02

@@ -49,10 +49,13 @@ def test_single_level_equals_uniform(ora):
     assert np.array_equal(f, U.post_collision())
 
 
-@pytest.mark.parametrize("levels,regions", [(2, REGIONS2), (3, REGIONS3)])
-def test_mass_and_momentum_exact(ora, levels, regions):
+@pytest.mark.parametrize("levels,regions,lb", [(2, REGIONS2, 1.0), (3, REGIONS3, 1.0), (3, REGIONS3, 100.0)])
+def test_mass_and_momentum_exact(ora, levels, regions, lb):
+    """Exact volume-weighted mass and momentum + V 2^L F per coarse step,
+    with TRT and with the MRT collision (bulk factor 100 on every level)."""
     F = np.array([1e-5, -2e-5, 3e-5])
     c = cfg_of((16, 16, 16), levels, 4, omega=1.7, F=tuple(F))
+    c["bulk_factor"] = lb
     R = ora.Refined(c, regions=regions)
     R.init(1.0, synth.velocity_perturbation((16, 16, 16), seed=5))
     leaf = R.leaf()
