@@ -93,6 +93,18 @@ def run_precision(pkg, w, storage, warmup, steps, drag_steps, drag_window):
     }
 
 
+def run_mrt(pkg, w, storages, warmup, steps, bulk_factor=100.0):
+    """The headline workload with the paper's default collision: MRT with
+    bulk factor 100 (Sec. 2.1).  Throughput only."""
+    w2 = dict(w, config=dict(w["config"], bulk_factor=bulk_factor))
+    out = {"bulk_factor": bulk_factor}
+    for st in storages:
+        r = run_precision(pkg, w2, st, warmup, steps, warmup + steps, 10)
+        out[st] = {"mlups": round(r["mlups"], 1), "sweep_gbs": round(r["sweep_gbs"], 1),
+                   "hbm_frac": round(r["sweep_gbs"] / PEAK_GBS, 4)}
+    return out
+
+
 def run_rising(pkg, steps):
     """Moving light sphere between walls: FP64 vs FP32 trajectory."""
     import numpy as np
@@ -348,6 +360,8 @@ def main():
                             for st, r in res.items()},
     }
     if not args.no_extra:
+        log("MRT, bulk factor 100, on the precision workload")
+        line["mrt_bulk100"] = run_mrt(pkg, w, ["f32", "f16"], args.warmup, args.steps)
         log("rising sphere 256^3")
         line["rising"] = run_rising(pkg, 2000)
         log("refined 128x128x512, 3 levels")

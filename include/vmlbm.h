@@ -69,6 +69,10 @@ typedef struct {
   int adjoint_steps;          /* > 0: reserve workspace for vmlbm_forward_ckpt
                                  with this many steps */
   int ckpt_every;             /* checkpoint period of the adjoint forward pass */
+  double bulk_factor;         /* Lambda_b of the MRT collision (Sec. 2.1):
+                                 1/s_b - 1/2 = Lambda_b (1/s_nu - 1/2) on every
+                                 level; 0 or 1 selects TRT.  The adjoint
+                                 supports TRT only. */
 } vmlbm_config;
 
 typedef struct {

@@ -41,7 +41,8 @@ class Config(ctypes.Structure):
                 ("omega", ctypes.c_double), ("magic", ctypes.c_double),
                 ("body_force", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
                 ("storage", ctypes.c_int), ("check_every", ctypes.c_int), ("history", ctypes.c_int),
-                ("adjoint_steps", ctypes.c_int), ("ckpt_every", ctypes.c_int)]
+                ("adjoint_steps", ctypes.c_int), ("ckpt_every", ctypes.c_int),
+                ("bulk_factor", ctypes.c_double)]
 
 
 class Sphere(ctypes.Structure):
@@ -114,6 +115,7 @@ def make_config(cfg, storage="f64", history=4, adjoint_steps=0, ckpt_every=0, ch
     c.levels = int(cfg.get("levels", 1))
     c.omega = float(cfg["omega"])
     c.magic = float(cfg["magic"])
+    c.bulk_factor = float(cfg.get("bulk_factor", 1.0))
     c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     c.check_every = int(cfg.get("check_every", check_every))
     c.history = int(history)

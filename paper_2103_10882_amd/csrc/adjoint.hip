@@ -42,7 +42,7 @@ struct AdjState {
 namespace {
 
 // nu = J_C(d)^T lam and the parameter derivatives lam . dC/dF_z, lam . dC/domega
-// of the TRT collision on deviations d (same formulas as trt_collide).
+// of the TRT collision on deviations d (same formulas as lbm_collide with s_b = s+).
 template <typename T>
 __device__ __forceinline__ void collide_adjoint(const T (&d)[kQ], const T (&lam)[kQ], T sp, T sm, T Fx, T Fy,
                                                 T Fz, double dsm_dw, T (&nu)[kQ], double& gF, double& gW) {
@@ -322,6 +322,7 @@ int vmlbm_set_params(vmlbm_ctx* c, double body_force_z, double omega) {
   c->F[2] = body_force_z;
   c->sp = omega;
   c->sm = s_minus_of(omega, c->cfg.magic);
+  c->sb = s_bulk_of(omega, c->cfg.bulk_factor);
   return VMLBM_OK;
 }
 
@@ -332,6 +333,7 @@ int vmlbm_forward_ckpt(vmlbm_ctx* c, int sphere, int n_steps, int avg_from, int 
   AdjState& A = *c->adj;
   const vmlbm_config& g = c->cfg;
   if (g.block > 0) return fail(c, VMLBM_EINVAL, "adjoint needs the uniform grid");
+  if (c->sb != c->sp) return fail(c, VMLBM_EINVAL, "adjoint needs the TRT collision (bulk_factor 1)");
   for (int a = 0; a < 3; ++a)
     if (!g.periodic[a]) return fail(c, VMLBM_EINVAL, "adjoint needs a periodic domain");
   for (const auto& s : c->spheres)

@@ -125,6 +125,7 @@ SweepParams sweep_params(const vmlbm_ctx* c) {
     for (int a = 0; a < 3; ++a) p.wall_v[s][a] = g.wall_velocity[s][a];
   p.sp = c->sp;
   p.sm = c->sm;
+  p.sb = c->sb;
   for (int a = 0; a < 3; ++a) p.F[a] = c->F[a];
   p.N = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
   p.box = c->box;
@@ -224,6 +225,7 @@ int vmlbm_create(const vmlbm_config* cfg, vmlbm_ctx** out) {
     if (!cfg->periodic[a]) { c->wall_axis = a; break; }
   c->sp = cfg->omega;
   c->sm = s_minus_of(c->sp, cfg->magic);
+  c->sb = s_bulk_of(c->sp, cfg->bulk_factor);
   for (int a = 0; a < 3; ++a) c->F[a] = cfg->body_force[a];
   if (cfg->block > 0) {
     int rc = refine_create(c);

@@ -145,13 +145,16 @@ struct DevParticle {
 };
 
 // ---------------------------------------------------------------------------
-// TRT collision (Sec. 2.1 with Lambda_b = 1) on deviations, incompressible
-// equilibrium (rho0 = 1), forcing after Guo with the velocity shifted by F/2.
-// d[] holds pre-collision deviations on entry and post-collision on exit.
-// Returns the density deviation.
+// Collision of Sec. 2.1 on deviations, incompressible equilibrium (rho0 = 1),
+// forcing after Guo with the velocity shifted by F/2: odd non-equilibrium
+// relaxed with s-, even with s+ = s_nu (TRT), except its isotropic part
+// (the mean over each speed shell: rest, axis, diagonal), which the MRT of
+// Sec. 2.1 relaxes with s_b; the even source is weighted likewise with
+// 1 - s/2.  sb == sp gives TRT.  d[] holds pre-collision deviations on
+// entry and post-collision on exit.  Returns the density deviation.
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T trt_collide(T (&d)[kQ], T sp, T sm, T Fx, T Fy, T Fz) {
+__device__ __forceinline__ T lbm_collide(T (&d)[kQ], T sp, T sm, T sb, T Fx, T Fy, T Fz) {
   T drho = d[0];
 #pragma unroll
   for (int q = 1; q < kQ; ++q) drho += d[q];
@@ -161,13 +164,15 @@ __device__ __forceinline__ T trt_collide(T (&d)[kQ], T sp, T sm, T Fx, T Fy, T F
   const T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
   const T usq = ux * ux + uy * uy + uz * uz;
   const T uF = ux * Fx + uy * Fy + uz * Fz;
-  const T kp = T(1) - T(0.5) * sp, km = T(1) - T(0.5) * sm;
-  // rest population: purely even
+  const T kp = T(1) - T(0.5) * sp, km = T(1) - T(0.5) * sm, kb = T(1) - T(0.5) * sb;
+  // rest population: a shell of its own, so purely isotropic
   {
     const T w = T(w_of(0));
     const T eq = w * (drho - T(1.5) * usq);
-    d[0] = d[0] - sp * (d[0] - eq) + kp * (w * (T(-3) * uF));
+    d[0] = d[0] - sb * (d[0] - eq) + kb * (w * (T(-3) * uF));
   }
+  T fp[kPairs], ne[kPairs], se[kPairs];
+  T nax = T(0), ndg = T(0), sax = T(0), sdg = T(0);
 #pragma unroll
   for (int k = 0; k < kPairs; ++k) {
     const int q = pair_q(k), qb = opp_of(q);
@@ -178,14 +183,36 @@ __device__ __forceinline__ T trt_collide(T (&d)[kQ], T sp, T sm, T Fx, T Fy, T F
     const T em = T(3) * w * cu;
     const T Sp = w * (T(9) * cu * cF - T(3) * uF);
     const T Sm = T(3) * w * cF;
-    const T fp = T(0.5) * (d[q] + d[qb]);
+    fp[k] = T(0.5) * (d[q] + d[qb]);
     const T fm = T(0.5) * (d[q] - d[qb]);
-    const T np = fp - sp * (fp - ep) + kp * Sp;
+    ne[k] = fp[k] - ep;
+    se[k] = Sp;
+    if (k < 3) { nax += ne[k]; sax += Sp; } else { ndg += ne[k]; sdg += Sp; }
+    // odd part now; the even part below, once the shell means are known
     const T nm = fm - sm * (fm - em) + km * Sm;
-    d[q] = np + nm;
-    d[qb] = np - nm;
+    d[q] = nm;
+    d[qb] = -nm;
+  }
+  // shell means of the even non-equilibrium and source (axis shell: 3 pairs,
+  // diagonal shell: 6 pairs), relaxed at s_b instead of s_nu
+  const T dsb = sb - sp, dkb = kb - kp;
+  const T mn_ax = nax * T(1.0 / 3.0), mn_dg = ndg * T(1.0 / 6.0);
+  const T ms_ax = sax * T(1.0 / 3.0), ms_dg = sdg * T(1.0 / 6.0);
+#pragma unroll
+  for (int k = 0; k < kPairs; ++k) {
+    const int q = pair_q(k), qb = opp_of(q);
+    const T mn = k < 3 ? mn_ax : mn_dg, ms = k < 3 ? ms_ax : ms_dg;
+    const T np = fp[k] - sp * ne[k] - dsb * mn + kp * se[k] + dkb * ms;
+    d[q] = np + d[q];
+    d[qb] = np + d[qb];
   }
   return drho;
+}
+
+// s_b from s_nu and the bulk factor Lambda_b (Sec. 2.1); 0 or 1 gives s_nu
+__host__ __device__ inline double s_bulk_of(double snu, double bulk_factor) {
+  if (!(bulk_factor > 0.0) || bulk_factor == 1.0) return snu;
+  return 1.0 / (0.5 + bulk_factor * (1.0 / snu - 0.5));
 }
 
 // s- from s+ and the magic parameter Lambda = (1/s+ - 1/2)(1/s- - 1/2)

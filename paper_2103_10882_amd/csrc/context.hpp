@@ -30,7 +30,7 @@ struct vmlbm_ctx {
   bool initialized = false;
   bool use_flags = false;
   int wall_axis = -1;
-  double sp = 0.0, sm = 0.0, F[3] = {0.0, 0.0, 0.0};
+  double sp = 0.0, sm = 0.0, sb = 0.0, F[3] = {0.0, 0.0, 0.0};
   std::string err;
 
   // uniform-grid workspace carving

@@ -254,7 +254,7 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
     T d[kQ];
     boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status);
     if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
-    const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+    const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
     SrBits rb(c, p.seed);
 #pragma unroll
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
     const double w = w_of(q);
     d[q] = T(w * (rho - 1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq) - 3.0 * w / p.sp * QS);
   }
-  trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   SrBits sr(c, ~p.seed);
   for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store_sr(d[q], sr.next());
 }

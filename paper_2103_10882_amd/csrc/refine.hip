@@ -49,7 +49,7 @@ struct IfaceEntry {
 };
 
 struct LevelParams {
-  double sp, sm, F[3];
+  double sp, sm, sb, F[3];
 };
 
 }  // namespace
@@ -565,7 +565,7 @@ struct LevelArgs {
   const int* slot_of;
   const int* pos;      // per slot: block position x, y, z
   uint32_t N;          // population stride (cap * 4096)
-  double sp, sm, F[3];
+  double sp, sm, sb, F[3];
   uint32_t seed;       // stochastic-rounding stream of this sweep
 };
 
@@ -634,7 +634,7 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
       status[kStatusRange] = 6;
       continue;
     }
-    const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+    const T drho = lbm_collide<T>(d, T(a.sp), T(a.sm), T(a.sb), T(a.F[0]), T(a.F[1]), T(a.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
     SrBits rb(c, a.seed);
 #pragma unroll
@@ -724,7 +724,7 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
   T d[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) d[q] = T(pre[threadIdx.x][q]);
-  const T drho = trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+  const T drho = lbm_collide<T>(d, T(a.sp), T(a.sm), T(a.sb), T(a.F[0]), T(a.F[1]), T(a.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   const uint32_t c = (uint32_t)e.slot * kBlockCells + (uint32_t)e.local;
   SrBits rb(c, a.seed);
@@ -761,7 +761,7 @@ __global__ __launch_bounds__(256) void k_init_level(S* __restrict__ dst, const d
       const double cu = cx_of(q) * u[0] + cy_of(q) * u[1] + cz_of(q) * u[2];
       d[q] = T(w_of(q) * (drho + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
     }
-    trt_collide<T>(d, T(a.sp), T(a.sm), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+    lbm_collide<T>(d, T(a.sp), T(a.sm), T(a.sb), T(a.F[0]), T(a.F[1]), T(a.F[2]));
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
     SrBits rb(c, a.seed);
 #pragma unroll
@@ -861,6 +861,7 @@ LevelArgs level_args(vmlbm_ctx* c, int l, int tab) {
   a.N = (uint32_t)V.cap * kBlockCells;
   a.sp = V.lp.sp;
   a.sm = V.lp.sm;
+  a.sb = V.lp.sb;
   for (int i = 0; i < 3; ++i) a.F[i] = V.lp.F[i];
   a.seed = level_seed(c->fine_steps_done, l);
   return a;
@@ -885,6 +886,7 @@ SweepParams finest_params(vmlbm_ctx* c) {
   p.wall_axis = -1;
   p.sp = V.lp.sp;
   p.sm = V.lp.sm;
+  p.sb = V.lp.sb;
   for (int i = 0; i < 3; ++i) p.F[i] = V.lp.F[i];
   p.N = (uint32_t)V.cap * kBlockCells;
   p.box = c->box;
@@ -1153,6 +1155,7 @@ int refine_create(vmlbm_ctx* c) {
     V.npos = (long)V.nb[0] * V.nb[1] * V.nb[2];
     V.lp.sp = 1.0 / tau;
     V.lp.sm = s_minus_of(V.lp.sp, g.magic);
+    V.lp.sb = s_bulk_of(V.lp.sp, g.bulk_factor);
     for (int a = 0; a < 3; ++a) V.lp.F[a] = g.body_force[a] * (double)(1 << (f->L - l));
     tau = 0.5 + 0.5 * (tau - 0.5);
   }

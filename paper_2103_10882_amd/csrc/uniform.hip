@@ -47,7 +47,7 @@ __global__ __launch_bounds__(512) void k_sweep(const S* __restrict__ src, S* __r
   T d[kQ];
   const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz);
   load_all<S>(src, N, I, x, d, std::make_integer_sequence<int, kQ>{});
-  const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   // streaming stores: the new state is not read again within this sweep
   SrBits rb(c, p.seed);
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ sr
   T d[kQ];
   const UAddr ad = uaddr(p);
   boundary_cell<S, UAddr>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, status);
-  const T drho = trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   SrBits rb(c, p.seed);
 #pragma unroll
@@ -109,7 +109,7 @@ __global__ __launch_bounds__(256) void k_init(S* __restrict__ dst, const uint8_t
     const double cu = cx_of(q) * u[0] + cy_of(q) * u[1] + cz_of(q) * u[2];
     d[q] = T(w_of(q) * (drho + 3.0 * cu + 4.5 * cu * cu - 1.5 * usq));
   }
-  trt_collide<T>(d, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   SrBits rb(c, p.seed);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store_sr(d[q], rb.next());

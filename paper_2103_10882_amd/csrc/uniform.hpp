@@ -14,6 +14,7 @@ struct SweepParams {
   int wall_axis;          // first non-periodic axis or -1
   double wall_v[2][3];    // velocity of its low / high wall
   double sp, sm;          // s+ = omega, s- from the magic parameter
+  double sb;              // s_b of the MRT bulk moments (= sp for TRT)
   double F[3];            // fluid body force
   uint32_t N;             // cells
   int box;                // edge of a sphere's box (cells); holds all its link cells

@@ -69,13 +69,14 @@ def compare_levels(sim, ref, levels):
 REGIONS = [((8, 4, 6), (20, 14, 22), 1), ((12, 16, 16), (18, 22, 22), 2), ((0, 24, 0), (4, 28, 6), 1)]
 
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
-def test_static_three_levels(env, storage, tol):
+@pytest.mark.parametrize("storage,tol,lb", [("f64", 1e-12, 1.0), ("f32", 2e-6, 1.0), ("f64", 1e-12, 100.0)])
+def test_static_three_levels(env, storage, tol, lb):
     pkg, oracle = env
     n0 = (32, 32, 32)
     c = cfg_of(n0, 3, omega=1.7, F=(1e-5, -2e-5, 3e-5))
+    c["bulk_factor"] = lb
     u0 = synth.velocity_perturbation(n0, seed=7)
-    say(f"case refined32 L3 static {storage}")
+    say(f"case refined32 L3 static {storage} bulk factor {lb}")
     sim = pkg.Sim(c, [], storage=storage, regions=REGIONS, check_every=0)
     sim.init(1.0, u0)
     ref = oracle.Refined(c, regions=REGIONS)

@@ -44,12 +44,15 @@ def check_ft(sim, ref, nsph, radius, tol=1e-10, where=""):
         assert np.abs(Tg - To).max() <= tol * ts, (where, i, Tg, To)
 
 
-def test_tiny_fixed_sphere_parity(env):
+@pytest.mark.parametrize("lb", [1.0, 100.0])
+def test_tiny_fixed_sphere_parity(env, lb):
     """32^3 periodic, fixed sphere r=6, body force, perturbed start: F/T every
-    step for 200 steps, populations at 100 and 200."""
+    step for 200 steps, populations at 100 and 200; TRT and the MRT
+    collision with bulk factor 100."""
     pkg, oracle = env
     w = synth.tiny()
-    say("case tiny32 f64")
+    w["config"]["bulk_factor"] = lb
+    say(f"case tiny32 f64 bulk factor {lb}")
     sim = pkg.Sim(w["config"], w["spheres"], storage="f64")
     sim.init(1.0, w["u0"])
     ref = oracle.Uniform(w["config"], w["spheres"])
@@ -110,13 +113,16 @@ def test_walls(env, kind):
     assert rel <= 1e-12
 
 
-def test_moving_sphere_walls_parity(env):
+@pytest.mark.parametrize("lb", [1.0, 100.0])
+def test_moving_sphere_walls_parity(env, lb):
     """Reduced rising-sphere case: moving, rotating light sphere between
     no-slip walls with virtual mass; re-mapping and refill every step.
-    Owner maps must agree every step; F/T per step; state at the end."""
+    Owner maps must agree every step; F/T per step; state at the end.  TRT
+    and MRT (bulk factor 100)."""
     pkg, oracle = env
     n = (40, 36, 48)
     cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.7, gravity=(1e-5, 0.0, -4e-4))
+    cfg["bulk_factor"] = lb
     s = synth.sphere((20.3, 17.8, 16.2), 5.2, density_ratio=0.5, cv=0.5, fixed=False,
                      u=(0.004, -0.003, 0.0), w=(0.0, 0.002, -0.001))
     say("case moving40x36x48 f64")
@@ -199,8 +205,8 @@ def pulled(f, c):
     return np.stack([np.roll(f[q], shift=(c[q, 2], c[q, 1], c[q, 0]), axis=(0, 1, 2)) for q in range(19)])
 
 
-@pytest.mark.parametrize("case", ["box130", "sphere32"])
-def test_reduced_storage_one_step(env, case):
+@pytest.mark.parametrize("case,lb", [("box130", 1.0), ("sphere32", 1.0), ("box130", 100.0)])
+def test_reduced_storage_one_step(env, case, lb):
     """One FP16 / FP32 sweep from a rough state (per-cell random velocities
     of amplitude 0.02, so neighbouring cells differ by far more than a
     storage ulp): every cell without links equals the oracle's collision of
@@ -216,6 +222,7 @@ def test_reduced_storage_one_step(env, case):
         wk = synth.tiny()
         cfg, sph = wk["config"], wk["spheres"]
         n = tuple(cfg["n"])
+    cfg["bulk_factor"] = lb
     u0 = synth.velocity_perturbation(n, seed=11, amplitude=0.02)
     F = np.array(cfg["body_force"])
     for storage, ulp in (("f16", 2.0 ** -10), ("f32", 2.0 ** -23)):
@@ -237,7 +244,7 @@ def test_reduced_storage_one_step(env, case):
             keep &= np.sqrt((d ** 2).sum(axis=0)) > s_["radius"] + 2.5
         worst = 0.0
         for k, j, i in zip(*np.nonzero(keep)):
-            out = ora.collide_cell(pre[:, k, j, i], cfg["omega"], cfg["magic"], F)
+            out = ora.collide_cell_mrt(pre[:, k, j, i], cfg["omega"], cfg["magic"], lb, F)
             dev = out - w
             err = np.abs(f1[:, k, j, i] - out)
             worst = max(worst, float((err / (ulp * np.abs(dev) + 2e-7)).max()))
