@@ -99,7 +99,7 @@ def run_mrt(pkg, w, storages, warmup, steps, bulk_factor=100.0):
     w2 = dict(w, config=dict(w["config"], bulk_factor=bulk_factor))
     out = {"bulk_factor": bulk_factor}
     for st in storages:
-        r = run_precision(pkg, w2, st, warmup, steps, warmup + steps, 10)
+        r = run_precision(pkg, w2, st, warmup, steps, warmup + steps, 1)
         out[st] = {"mlups": round(r["mlups"], 1), "sweep_gbs": round(r["sweep_gbs"], 1),
                    "hbm_frac": round(r["sweep_gbs"] / PEAK_GBS, 4)}
     return out
