@@ -139,7 +139,7 @@ def run_refined(pkg, coarse_steps=500):
     import synth
     w = synth.refined()
     out = {}
-    for st in ("f64", "f32"):
+    for st in ("f64", "f32", "f16"):
         sim = pkg.Sim(w["config"], w["spheres"], storage=st, history=4 * coarse_steps)
         sim.init()
         blocks = [int(sim.level_blocks(l).shape[0]) for l in range(3)]
@@ -157,6 +157,9 @@ def run_refined(pkg, coarse_steps=500):
         del sim
         torch.cuda.empty_cache()
     out["coarse_steps"] = coarse_steps
+    # rise of the reduced formats against FP64 over the run
+    for st in ("f32", "f16"):
+        out[st]["z_rise_rel_err"] = abs(out[st]["z_rise"] - out["f64"]["z_rise"]) / abs(out["f64"]["z_rise"])
     return out
 
 
