@@ -166,3 +166,52 @@ def test_refined_layout_across_periodic_boundary(env):
     rel = compare_levels(sim, ref, 2)
     say(f"  refinements {sim.refinements()}; population rel err {rel:.2e}")
     assert rel <= 1e-11
+
+
+def test_single_level_block_grid_equals_uniform(env):
+    """levels = 1: every block is a level-0 leaf, no ghosts and no
+    coalescence; 16^3 blocks must reproduce the uniform grid (FP64)."""
+    pkg, oracle = env
+    n0 = (48, 32, 16)
+    c = cfg_of(n0, 1, omega=1.3, F=(1e-5, 0.0, 2e-5))
+    u0 = synth.velocity_perturbation(n0, seed=13, amplitude=0.01)
+    say("case block grid 48x32x16 L1 f64")
+    sim = pkg.Sim(c, [], storage="f64", check_every=0)
+    sim.init(1.0, u0)
+    ref = oracle.Uniform(synth.base_config(n0, omega=1.3, body_force=(1e-5, 0.0, 2e-5)))
+    ref.init(1.0, u0)
+    sim.step(20)
+    ref.step(20)
+    sim.sync()
+    org = sim.level_blocks(0)
+    assert len(org) == 3 * 2 * 1
+    fg = sim.populations(0).reshape(19, len(org), 16, 16, 16)
+    fo = ref.post_collision()
+    worst = 0.0
+    for b, (x, y, z) in enumerate(org):
+        worst = max(worst, np.abs(fg[:, b] - fo[:, z:z + 16, y:y + 16, x:x + 16]).max())
+    say(f"  max abs diff {worst:.2e}")
+    assert worst <= 1e-15
+
+
+def test_static_four_levels(env):
+    """Four levels (the most the library takes), nested static regions."""
+    pkg, oracle = env
+    n0 = (64, 16, 16)
+    c = cfg_of(n0, 4, omega=1.9, F=(0.0, 0.0, 1e-6))
+    regions = [((0, 6, 6), (2, 9, 9), 3)]
+    u0 = synth.velocity_perturbation(n0, seed=14, amplitude=0.01)
+    say("case refined64x16x16 L4 static f64")
+    sim = pkg.Sim(c, [], storage="f64", regions=regions, check_every=0)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, regions=regions)
+    ref.init(1.0, u0)
+    leaf = ref.leaf()
+    assert leaf.max() == 3 and leaf.min() == 0
+    for k in range(2):
+        sim.step(1)
+        ref.step(1)
+    sim.sync()
+    rel = compare_levels(sim, ref, 4)
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-12
