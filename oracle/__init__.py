@@ -312,7 +312,8 @@ class RConfig(ctypes.Structure):
     _fields_ = [("n0", ctypes.c_int * 3), ("block", ctypes.c_int), ("levels", ctypes.c_int),
                 ("omega", ctypes.c_double), ("magic", ctypes.c_double), ("body_force", ctypes.c_double * 3),
                 ("gravity", ctypes.c_double * 3), ("check_every", ctypes.c_int),
-                ("bulk_factor", ctypes.c_double)]
+                ("bulk_factor", ctypes.c_double), ("curl_threshold", ctypes.c_double),
+                ("curl_coarsen", ctypes.c_double)]
 
 
 def _bind_refine(L):
@@ -336,6 +337,7 @@ def _bind_refine(L):
         ("orf_particle", [vp, ctypes.c_int, vp, vp, vp]),
         ("orf_owner", [vp, vp]),
         ("orf_counters", [vp, vp, vp, vp]),
+        ("orf_block_sensor", [vp, ctypes.c_int, vp]),
     ]:
         fn = getattr(L, name)
         fn.restype = ctypes.c_int
@@ -361,6 +363,8 @@ class Refined:
         c.magic = float(cfg["magic"])
         c.check_every = int(check_every)
         c.bulk_factor = float(cfg.get("bulk_factor", 1.0))
+        c.curl_threshold = float(cfg.get("curl_threshold", 0.0))
+        c.curl_coarsen = float(cfg.get("curl_coarsen", 0.2))
         self._c = c
         self.h = lib().orf_create(ctypes.byref(c))
         if not self.h:
@@ -436,6 +440,15 @@ class Refined:
         nx, ny, nz = self.dims(self.levels - 1)
         out = np.zeros((nz, ny, nx), dtype=np.int32)
         _check(lib().orf_owner(self.h, out.ctypes.data), "owner")
+        return out
+
+    def block_sensor(self, level):
+        """Curl sensor (Eq. 23) per block of the level: [bnz][bny][bnx], -1
+        where the block is not a leaf of that level."""
+        nx, ny, nz = self.dims(level)
+        b = self._c.block
+        out = np.zeros((nz // b, ny // b, nx // b))
+        _check(lib().orf_block_sensor(self.h, int(level), out.ctypes.data), "block_sensor")
         return out
 
     def counters(self):

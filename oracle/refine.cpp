@@ -45,6 +45,8 @@ typedef struct {
   double gravity[3];
   int check_every;
   double bulk_factor;   /* Lambda_b of the MRT collision; 0 or 1 = TRT */
+  double curl_threshold; /* sigma_c of the curl sensor (Eq. 23); 0 = off */
+  double curl_coarsen;   /* c: coarsen below c sigma_c */
 } orf_config;
 
 typedef struct {
@@ -172,7 +174,9 @@ struct RForest {
     }
   }
 
-  std::vector<int> targets() const {
+  // with_flow: add the curl-sensor targets (at the layout checks; the
+  // initial layout comes from the static regions and the spheres)
+  std::vector<int> targets(bool with_flow = false) const {
     std::vector<int> t = base;
     // Sec. 4.2.1: blocks intersecting the sphere's bounding box grown by one
     // finest block edge are on the finest level (reading: the open box, so a
@@ -186,6 +190,93 @@ struct RForest {
       for (int k = lo[2]; k <= hi[2]; ++k)
         for (int j = lo[1]; j <= hi[1]; ++j)
           for (int i = lo[0]; i <= hi[0]; ++i) t[bpos(wrap(i, nb[0]), wrap(j, nb[1]), wrap(k, nb[2]))] = L;
+    }
+    if (with_flow && cfg.curl_threshold > 0.0) {
+      // Sec. 4.2.2: a leaf whose sensor exceeds sigma_c wants one level more,
+      // one below c sigma_c one level less
+      const std::vector<int> ft = flow_targets();
+      for (size_t p = 0; p < t.size(); ++p) t[p] = std::max(t[p], ft[p]);
+    }
+    return t;
+  }
+
+  // fluid velocity of level-l cell c from the stored post-collision state:
+  // u = sum_q c_q f~_q - F_l / 2 (level lattice units, equal to finest units
+  // under acoustic scaling)
+  void velocity(int l, long c, double u[3]) const {
+    const RLevel& V = lv[l];
+    double j[3] = {0.0, 0.0, 0.0};
+    for (int q = 0; q < 19; ++q) {
+      const double f = V.cur[q * V.N + c];
+      j[0] += CX[q] * f;
+      j[1] += CY[q] * f;
+      j[2] += CZ[q] * f;
+    }
+    for (int a = 0; a < 3; ++a) u[a] = j[a] - 0.5 * V.F[a];
+  }
+
+  // Curl sensor of Eq. 23 per level-l block, max over its cells:
+  // phi = |curl u| s^((r+1)/r), r = 2, s = cell edge in finest cells
+  // (reading: lengths in finest-level lattice units, central differences
+  // over the six axis neighbours of the level, evaluated where all six are
+  // interior cells of the level and, on the finest level, fluid).  Blocks
+  // without such a cell read 0; non-leaf blocks read -1.
+  std::vector<double> block_sensor(int l) const {
+    const RLevel& V = lv[l];
+    const int bn[3] = {V.n[0] / b, V.n[1] / b, V.n[2] / b};
+    std::vector<double> out((long)bn[0] * bn[1] * bn[2], -1.0);
+    const double s = (double)(1 << (L - l));
+    const double scale = s * std::sqrt(s) / (2.0 * s);   // s^(3/2) and 1/(2 s) of the differences
+    for (int k = 0; k < V.n[2]; ++k)
+      for (int j = 0; j < V.n[1]; ++j)
+        for (int i = 0; i < V.n[0]; ++i) {
+          const long bidx = ((long)(k / b) * bn[1] + j / b) * bn[0] + i / b;
+          if (kind_at(l, i, j, k) != INTERIOR) continue;
+          if (out[bidx] < 0.0) out[bidx] = 0.0;
+          const long c = idx(l, i, j, k);
+          if (l == L && !own.empty() && own[c] >= 0) continue;
+          double du[3][2][3];   // axis, side, component
+          bool ok = true;
+          for (int a = 0; a < 3 && ok; ++a)
+            for (int sd = 0; sd < 2 && ok; ++sd) {
+              int p[3] = {i, j, k};
+              p[a] += sd ? 1 : -1;
+              if (kind_at(l, p[0], p[1], p[2]) != INTERIOR) { ok = false; break; }
+              const long cn = idx(l, p[0], p[1], p[2]);
+              if (l == L && !own.empty() && own[cn] >= 0) { ok = false; break; }
+              velocity(l, cn, du[a][sd]);
+            }
+          if (!ok) continue;
+          // d u_comp / d x_axis ~ (u(+) - u(-)) (scaled below)
+          auto d = [&](int comp, int axis) { return du[axis][1][comp] - du[axis][0][comp]; };
+          const double cx = d(2, 1) - d(1, 2), cy = d(0, 2) - d(2, 0), cz = d(1, 0) - d(0, 1);
+          const double phi = std::sqrt(cx * cx + cy * cy + cz * cz) * scale;
+          out[bidx] = std::max(out[bidx], phi);
+        }
+    return out;
+  }
+
+  std::vector<int> flow_targets() const {
+    std::vector<int> t(leaf.size(), 0);
+    const double sig = cfg.curl_threshold, csig = cfg.curl_coarsen * cfg.curl_threshold;
+    for (int l = 0; l <= L; ++l) {
+      const RLevel& V = lv[l];
+      const int bn[3] = {V.n[0] / b, V.n[1] / b, V.n[2] / b};
+      const std::vector<double> sens = block_sensor(l);
+      const int sh = L - l;
+      for (int k = 0; k < bn[2]; ++k)
+        for (int j = 0; j < bn[1]; ++j)
+          for (int i = 0; i < bn[0]; ++i) {
+            const double v = sens[((long)k * bn[1] + j) * bn[0] + i];
+            if (v < 0.0) continue;   // not a leaf of this level
+            const int want = v > sig ? std::min(l + 1, L) : (v < csig ? std::max(l - 1, 0) : l);
+            for (int c = 0; c < (1 << sh); ++c)
+              for (int bb = 0; bb < (1 << sh); ++bb)
+                for (int a = 0; a < (1 << sh); ++a) {
+                  int& tv = t[bpos((i << sh) + a, (j << sh) + bb, (k << sh) + c)];
+                  tv = std::max(tv, want);
+                }
+          }
     }
     return t;
   }
@@ -483,7 +574,7 @@ struct RForest {
     step_level(0);
     coarse_steps += 1;
     if (cfg.check_every > 0 && coarse_steps % cfg.check_every == 0) {
-      std::vector<int> nl = balance(targets());
+      std::vector<int> nl = balance(targets(true));
       if (nl != leaf) {
         migrate(nl);
         refinements += 1;
@@ -703,5 +794,16 @@ int orf_counters(void* h, long long* coarse, long long* fine, int* refinements) 
 }
 
 void orf_destroy(void* h) { delete static_cast<RForest*>(h); }
+
+/* curl sensor of Eq. 23 per level-l block (level block grid order, x
+ * fastest): max over the block's evaluated cells, 0 if none, -1 for blocks
+ * that are not leaves of this level */
+int orf_block_sensor(void* h, int level, double* out) {
+  auto* R = static_cast<RForest*>(h);
+  if (!R || !out || level < 0 || level > R->L) return -1;
+  const std::vector<double> s = R->block_sensor(level);
+  for (size_t i = 0; i < s.size(); ++i) out[i] = s[i];
+  return 0;
+}
 
 }  // extern "C"

@@ -214,3 +214,77 @@ def test_migration_conserves_mass_and_momentum(ora):
     assert not np.array_equal(R.leaf(), leaf0)
     x, _, _ = R.particle(0)
     assert abs(x[2] - (40.0 + 40 * 4 * 0.06)) < 1e-9
+
+
+def shear_x_field(R, level, U, wavelength, phase=0.0):
+    """u_z = U sin(2 pi x / wavelength + phase) at the level's cell centres,
+    x in finest-level cells."""
+    nx, ny, nz = R.dims(level)
+    s = 2 ** (R.levels - 1 - level)
+    xf = (np.arange(nx) + 0.5) * s
+    u = np.zeros((3, nz, ny, nx))
+    u[2] = U * np.sin(2 * np.pi * xf / wavelength + phase)[None, None, :]
+    return u
+
+
+def test_curl_sensor_closed_form(ora):
+    """Eq. 23 with r = 2: phi = |curl u| s^(3/2), s the cell edge in finest
+    cells.  For u_z = U sin(k x) the curl is U k cos(k x); each leaf block's
+    sensor is the max over its cells, up to the central-difference factor
+    sin(k s)/(k s) (within 2e-3 here).  Checked on both levels of a
+    two-level layout, including blocks next to the level interface (the
+    field does not vary along z, where the interface lies)."""
+    n0 = (64, 16, 32)
+    c = cfg_of(n0, 2, 16, omega=1.6)
+    c["curl_threshold"] = 1.0
+    R = ora.Refined(c, regions=[((0, 0, 16), (64, 16, 32), 1)])
+    R.init(1.0)
+    U, lam = 1e-3, 128.0
+    k = 2 * np.pi / lam
+    for l in range(2):
+        R.set_level_velocity(l, 1.0, shear_x_field(R, l, U, lam))
+    for l in range(2):
+        sens = R.block_sensor(l)
+        s = 2 ** (1 - l)
+        nbx = sens.shape[2]
+        for bz in range(sens.shape[0]):
+            for by in range(sens.shape[1]):
+                for bx in range(nbx):
+                    v = sens[bz, by, bx]
+                    if v < 0:
+                        continue
+                    xf = (np.arange(16 * bx, 16 * bx + 16) + 0.5) * s
+                    exact = U * k * np.abs(np.cos(k * xf)).max() * s ** 1.5
+                    assert abs(v / exact - 1.0) < 2e-3, (l, bz, by, bx, v, exact)
+        assert (sens >= 0).sum() > 0
+
+
+def test_curl_refinement_rule(ora):
+    """Blocks whose sensor exceeds sigma_c are refined at the next check,
+    refined blocks whose sensor falls below c sigma_c coarsen again."""
+    n0 = (64, 16, 16)
+    c = cfg_of(n0, 2, 16, omega=1.6)
+    U, lam = 1e-3, 128.0
+    k = 2 * np.pi / lam
+    # level-0 sensors: U k max|cos| 2^1.5 per block; refine blocks above 0.8 of the peak
+    peak = U * k * 2 ** 1.5
+    c["curl_threshold"] = 0.8 * peak
+    c["curl_coarsen"] = 0.2
+    R = ora.Refined(c, check_every=1)
+    R.init(1.0)
+    # curl peaks at x = 48 and 112 (inside blocks 1 and 3); blocks 0 and 2 reach 0.68
+    R.set_level_velocity(0, 1.0, shear_x_field(R, 0, U, lam, np.pi / 4))
+    sens0 = R.block_sensor(0)
+    want = sens0[0, 0, :] > c["curl_threshold"]
+    margin = np.abs(sens0 / c["curl_threshold"] - 1.0).min()
+    assert margin > 0.02 and 0 < want.sum() < len(want)
+    R.step(1)
+    leaf = R.leaf()                         # finest block positions [z][y][x]; 2 per coarse block in x
+    lvl_x = leaf[0, 0, ::2]
+    assert np.array_equal(lvl_x == 1, want)
+    assert (leaf == leaf[:1, :1, :]).all()  # uniform across y and z
+    # a weak field everywhere: the refined blocks coarsen at the next check
+    for l in range(2):
+        R.set_level_velocity(l, 1.0, shear_x_field(R, l, 0.05 * U, lam, np.pi / 4))
+    R.step(1)
+    assert R.leaf().max() == 0
