@@ -73,6 +73,18 @@ typedef struct {
                                  1/s_b - 1/2 = Lambda_b (1/s_nu - 1/2) on every
                                  level; 0 or 1 selects TRT.  The adjoint
                                  supports TRT only. */
+  double curl_threshold;      /* refined grid: sigma_c of the curl sensor
+                                 phi = |curl u| s^(3/2) (Sec. 4.2.2, Eq. 23;
+                                 s the cell edge in finest cells); at every
+                                 layout check a leaf block whose max phi
+                                 exceeds sigma_c is refined, one below
+                                 curl_coarsen * sigma_c coarsened.  0 = off */
+  double curl_coarsen;        /* c of Sec. 4.2.2 (the paper advises c <= 0.35) */
+  int max_blocks;             /* refined grid with the curl sensor: block
+                                 slots per level (the flow decides how many
+                                 it needs); 0 = every block position of the
+                                 level.  A layout that needs more fails with
+                                 VMLBM_ERANGE. */
 } vmlbm_config;
 
 typedef struct {

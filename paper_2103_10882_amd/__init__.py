@@ -42,7 +42,8 @@ class Config(ctypes.Structure):
                 ("body_force", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
                 ("storage", ctypes.c_int), ("check_every", ctypes.c_int), ("history", ctypes.c_int),
                 ("adjoint_steps", ctypes.c_int), ("ckpt_every", ctypes.c_int),
-                ("bulk_factor", ctypes.c_double)]
+                ("bulk_factor", ctypes.c_double), ("curl_threshold", ctypes.c_double),
+                ("curl_coarsen", ctypes.c_double), ("max_blocks", ctypes.c_int)]
 
 
 class Sphere(ctypes.Structure):
@@ -116,6 +117,9 @@ def make_config(cfg, storage="f64", history=4, adjoint_steps=0, ckpt_every=0, ch
     c.omega = float(cfg["omega"])
     c.magic = float(cfg["magic"])
     c.bulk_factor = float(cfg.get("bulk_factor", 1.0))
+    c.curl_threshold = float(cfg.get("curl_threshold", 0.0))
+    c.curl_coarsen = float(cfg.get("curl_coarsen", 0.2))
+    c.max_blocks = int(cfg.get("max_blocks", 0))
     c.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
     c.check_every = int(cfg.get("check_every", check_every))
     c.history = int(history)

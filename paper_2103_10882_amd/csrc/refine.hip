@@ -60,6 +60,7 @@ struct Forest {
   int nbL[3] = {0, 0, 0};     // finest block positions
   std::vector<int8_t> leaf, base;
   std::vector<int> boxes;     // sphere block ranges the current layout was built for
+  bool flow = false;          // curl-sensor criterion on
   int refinements = 0;
   long long coarse_steps = 0;
   struct Lev {
@@ -76,7 +77,7 @@ struct Forest {
     LevelParams lp{};
     // device
     size_t off_pdf[2] = {0, 0}, off_flags = 0, off_slot_of[2] = {0, 0}, off_pos = 0, off_int = 0, off_ghost = 0,
-           off_explode = 0, off_iface = 0, off_band = 0, off_band_off = 0;
+           off_explode = 0, off_iface = 0, off_band = 0, off_band_off = 0, off_vel = 0, off_sens = 0;
     int cur = 0, tab = 0;
     int n_int = 0, n_ghost = 0, n_iface = 0;
   };
@@ -447,6 +448,14 @@ void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<
   for (int l = 0; l <= L; ++l) {
     cap[l] = std::min<long>(f.lv[l].npos, cap[l] + 64);
     icap[l] = std::min<long>((long)cap[l] * kBlockCells, icap[l] + 4096);
+    if (f.flow) {
+      // the flow decides the layout: every block position, or the caller's cap.
+      // Coalescence cells lie within two cells of a leaf block's surface:
+      // at most 16^3 - 12^3 per block.
+      const int mb = c->cfg.max_blocks;
+      cap[l] = mb > 0 ? std::min<long>(f.lv[l].npos, mb) : f.lv[l].npos;
+      icap[l] = (long)cap[l] * (kBlockCells - 12 * 12 * 12);
+    }
   }
 }
 
@@ -730,6 +739,78 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
   SrBits rb(c, a.seed);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store_sr(d[q], rb.next());
+}
+
+// stored post-collision velocity of every interior cell of a level:
+// u = sum_q c_q d_q - F_l / 2, as vel[a * N + c]
+template <typename S>
+__global__ __launch_bounds__(256) void k_level_velocity(const S* __restrict__ src, const int* __restrict__ list,
+                                                        LevelArgs a, double* __restrict__ vel) {
+  const int slot = list[blockIdx.x];
+  for (int t = threadIdx.x; t < kBlockCells; t += blockDim.x) {
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)t;
+    double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+      const double d = (double)Store<S>::load(src[(size_t)q * a.N + c]);
+      j[0] += cx_of(q) * d;
+      j[1] += cy_of(q) * d;
+      j[2] += cz_of(q) * d;
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b) vel[(size_t)b * a.N + c] = j[b] - 0.5 * a.F[b];
+  }
+}
+
+// Curl sensor of Sec. 4.2.2 per interior block: max over its cells of
+// |curl u| s^(3/2) (scale = s^(3/2) / (2 s) applied to the central
+// differences), evaluated where all six axis neighbours are interior cells
+// of the level and, with flags given (finest level), no cell involved is
+// solid; 0 if no cell qualifies.
+__global__ __launch_bounds__(256) void k_block_curl(const double* __restrict__ vel,
+                                                    const uint8_t* __restrict__ flags,
+                                                    const int* __restrict__ list, int n_int, LevelArgs a,
+                                                    double scale, double* __restrict__ out) {
+  __shared__ int nbs[27];
+  __shared__ double red[4];
+  const int slot = list[blockIdx.x];
+  load_neighbours(a, slot, nbs);
+  double m = 0.0;
+  for (int t = threadIdx.x; t < kBlockCells; t += blockDim.x) {
+    const int x = t & 15, y = (t >> 4) & 15, z = t >> 8;
+    const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)t;
+    if (flags && (flags[c] & kSolid)) continue;
+    double du[3][3];   // axis, component: u(+) - u(-)
+    bool ok = true;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      double up[2][3];
+#pragma unroll
+      for (int sd = 0; sd < 2; ++sd) {
+        int p[3] = {x, y, z};
+        p[ax] += sd ? 1 : -1;
+        const int bx = p[0] < 0 ? -1 : (p[0] > 15 ? 1 : 0), by = p[1] < 0 ? -1 : (p[1] > 15 ? 1 : 0),
+                  bz = p[2] < 0 ? -1 : (p[2] > 15 ? 1 : 0);
+        const int s = (bx | by | bz) ? nbs[(bz + 1) * 9 + (by + 1) * 3 + (bx + 1)] : slot;
+        uint32_t cn = c;
+        if (s < 0 || s >= n_int) ok = false;
+        else cn = (uint32_t)s * kBlockCells + (uint32_t)((((p[2] & 15) * 16) + (p[1] & 15)) * 16 + (p[0] & 15));
+        if (flags && (flags[cn] & kSolid)) ok = false;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) up[sd][b] = vel[(size_t)b * a.N + cn];
+      }
+#pragma unroll
+      for (int b = 0; b < 3; ++b) du[ax][b] = up[1][b] - up[0][b];
+    }
+    if (!ok) continue;
+    const double cx = du[1][2] - du[2][1], cy = du[2][0] - du[0][2], cz = du[0][1] - du[1][0];
+    m = fmax(m, sqrt(cx * cx + cy * cy + cz * cz) * scale);
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) out[slot] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 __global__ void k_mark_iface(uint8_t* __restrict__ flags, const IfaceEntry* __restrict__ tab, int count) {
@@ -1064,6 +1145,51 @@ int step_level(vmlbm_ctx* c, int l) {
 }
 
 // re-check the layout around the particles; move data if it changed
+// Curl-sensor targets (Sec. 4.2.2): each leaf block's sensor, one level up
+// above sigma_c, one down below c sigma_c, raised into t (finest block
+// positions)
+int flow_targets(vmlbm_ctx* c, std::vector<int8_t>& t) {
+  Forest& f = *c->forest;
+  const double sig = c->cfg.curl_threshold, csig = c->cfg.curl_coarsen * sig;
+  for (int l = 0; l <= f.L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    if (!V.n_int) continue;
+    const LevelArgs a = level_args(c, l, V.tab);
+    double* vel = (double*)(c->ws + V.off_vel);
+    double* sens = (double*)(c->ws + V.off_sens);
+    int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+      using S = std::remove_pointer_t<decltype(tag)>;
+      k_level_velocity<S><<<V.n_int, 256, 0, c->stream>>>((const S*)(c->ws + V.off_pdf[V.cur]),
+                                                          (const int*)(c->ws + V.off_int), a, vel);
+      HIP_TRY(c, hipGetLastError());
+      return VMLBM_OK;
+    });
+    if (rc) return rc;
+    const double s = (double)(1 << (f.L - l));
+    const uint8_t* fl = (l == f.L && !c->spheres.empty()) ? (const uint8_t*)(c->ws + V.off_flags) : nullptr;
+    k_block_curl<<<V.n_int, 256, 0, c->stream>>>(vel, fl, (const int*)(c->ws + V.off_int), V.n_int, a,
+                                                 s * std::sqrt(s) / (2.0 * s), sens);
+    HIP_TRY(c, hipGetLastError());
+    std::vector<double> hs(V.n_int);
+    HIP_TRY(c, hipMemcpyAsync(hs.data(), sens, V.n_int * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    const int sh = f.L - l, e = 1 << sh;
+    for (int i = 0; i < V.n_int; ++i) {
+      const int slot = V.interior[i];
+      const double v = hs[slot];
+      const int want = v > sig ? std::min(l + 1, f.L) : (v < csig ? std::max(l - 1, 0) : l);
+      const int bi = V.pos[3 * slot], bj = V.pos[3 * slot + 1], bk = V.pos[3 * slot + 2];
+      for (int z = 0; z < e; ++z)
+        for (int y = 0; y < e; ++y)
+          for (int x = 0; x < e; ++x) {
+            int8_t& tv = t[f.lpos((bi << sh) + x, (bj << sh) + y, (bk << sh) + z)];
+            tv = std::max<int8_t>(tv, (int8_t)want);
+          }
+    }
+  }
+  return VMLBM_OK;
+}
+
 int check_layout(vmlbm_ctx* c) {
   Forest& f = *c->forest;
   const int np = (int)c->spheres.size();
@@ -1076,8 +1202,13 @@ int check_layout(vmlbm_ctx* c) {
       for (int a = 0; a < 3; ++a) sph[i].x[a] = hp[i].x[a];
   }
   std::vector<int> box = sphere_boxes(sph);
-  if (box == f.boxes) return VMLBM_OK;
-  std::vector<int8_t> nl = balance_layout(f, layout_targets(f, box));
+  if (box == f.boxes && !f.flow) return VMLBM_OK;
+  std::vector<int8_t> t = layout_targets(f, box);
+  if (f.flow) {
+    int rc = flow_targets(c, t);
+    if (rc) return rc;
+  }
+  std::vector<int8_t> nl = balance_layout(f, t);
   if (nl == f.leaf) {
     f.boxes = box;
     return VMLBM_OK;
@@ -1144,6 +1275,7 @@ int refine_create(vmlbm_ctx* c) {
   const long NB = (long)f->nbL[0] * f->nbL[1] * f->nbL[2];
   if (NB > (1L << 26)) { delete f; return fail(c, VMLBM_ERANGE, "too many finest block positions"); }
   f->base.assign(NB, 0);
+  f->flow = g.curl_threshold > 0.0;
   f->lv.resize(f->L + 1);
   double tau = 1.0 / g.omega;
   for (int l = f->L; l >= 0; --l) {
@@ -1203,6 +1335,10 @@ int refine_plan(vmlbm_ctx* c) {
     V.off_iface = take((size_t)V.iface_cap * sizeof(IfaceEntry));
     V.off_band = take((size_t)V.cap * kBlockCells * sizeof(uint16_t));
     V.off_band_off = take((size_t)(V.cap + 1) * sizeof(int));
+    if (f.flow) {
+      V.off_vel = take((size_t)3 * V.cap * kBlockCells * sizeof(double));
+      V.off_sens = take((size_t)V.cap * sizeof(double));
+    }
   }
   f.off_owner = take((size_t)f.lv[f.L].cap * kBlockCells * sizeof(uint16_t));
   for (int b = 0; b < 2; ++b) f.off_leaf[b] = take(f.leaf.size());

@@ -72,6 +72,23 @@ def velocity_perturbation(n, seed=0, amplitude=1e-3):
     return rng.uniform(-amplitude, amplitude, size=(3, nz, ny, nx))
 
 
+def vortex_tube(n, centre, core, amplitude):
+    """Gaussian vortex tube along y through (x0, z0) = centre (cell-centre
+    coordinates): u_x = -A dz g, u_z = A dx g with g = exp(-(dx^2 + dz^2) /
+    core^2), minimum-image offsets in the periodic box; [3][nz][ny][nx]."""
+    nx, ny, nz = n
+    x = np.arange(nx) + 0.5 - centre[0]
+    z = np.arange(nz) + 0.5 - centre[1]
+    x -= nx * np.round(x / nx)
+    z -= nz * np.round(z / nz)
+    dz, dx = np.meshgrid(z, x, indexing="ij")
+    g = np.exp(-(dx * dx + dz * dz) / (core * core))
+    u = np.zeros((3, nz, ny, nx))
+    u[0] = (-amplitude * dz * g)[:, None, :]
+    u[2] = (amplitude * dx * g)[:, None, :]
+    return u
+
+
 def place_spheres(n, count, radius, gap, seed=0):
     """Centres uniform in the periodic box, rejected when the minimum-image
     centre distance to an accepted one is below 2r + gap; accepted in draw

@@ -215,3 +215,97 @@ def test_static_four_levels(env):
     rel = compare_levels(sim, ref, 4)
     say(f"  population rel err {rel:.2e}")
     assert rel <= 1e-12
+
+
+def write_from_oracle(sim, ref, levels):
+    """Copy the oracle's interior populations of every level into the GPU
+    grid, block by block in the GPU's slot order (same layout on both)."""
+    for l in range(levels):
+        org = sim.level_blocks(l)
+        if len(org) == 0:
+            continue
+        fo, _ = ref.level(l)
+        f = np.empty((19, len(org), 16, 16, 16))
+        for b, (x, y, z) in enumerate(org):
+            f[:, b] = fo[:, z:z + 16, y:y + 16, x:x + 16]
+        sim.write_populations(f.reshape(19, -1), l)
+
+
+def shear_x_field(ref, level, levels, U, wavelength, phase):
+    nx, ny, nz = ref.dims(level)
+    s = 2 ** (levels - 1 - level)
+    xf = (np.arange(nx) + 0.5) * s
+    u = np.zeros((3, nz, ny, nx))
+    u[2] = U * np.sin(2 * np.pi * xf / wavelength + phase)[None, None, :]
+    return u
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_curl_refine_then_coarsen(env, storage, tol):
+    """Curl-sensor criterion of Sec. 4.2.2 with check_every = 1: a shear
+    field u_z = U sin(k x + pi/4) refines the level-0 blocks whose sensor
+    exceeds sigma_c (two of four along x, margin > 2 %); the same field at
+    5 % strength on both levels coarsens them again.  Layouts and
+    populations follow the oracle after each check."""
+    pkg, oracle = env
+    n0 = (64, 16, 16)
+    c = cfg_of(n0, 2, omega=1.6)
+    U, lam = 1e-3, 128.0
+    k = 2 * np.pi / lam
+    c["curl_threshold"] = 0.8 * U * k * 2 ** 1.5
+    c["curl_coarsen"] = 0.2
+    say(f"case curl shear 64x16x16 L2 {storage}")
+    sim = pkg.Sim(c, [], storage=storage, check_every=1)
+    sim.init(1.0)
+    ref = oracle.Refined(c, check_every=1)
+    ref.init(1.0)
+    ref.set_level_velocity(0, 1.0, shear_x_field(ref, 0, 2, U, lam, np.pi / 4))
+    write_from_oracle(sim, ref, 2)
+    sim.step(1)
+    ref.step(1)
+    sim.sync()
+    leaf = ref.leaf()
+    assert leaf.max() == 1 and leaf.min() == 0
+    rel = compare_levels(sim, ref, 2)
+    say(f"  refined: {len(sim.level_blocks(1))} level-1 blocks, population rel err {rel:.2e}")
+    assert rel <= tol
+    for l in range(2):
+        ref.set_level_velocity(l, 1.0, shear_x_field(ref, l, 2, 0.05 * U, lam, np.pi / 4))
+    write_from_oracle(sim, ref, 2)
+    sim.step(1)
+    ref.step(1)
+    sim.sync()
+    assert ref.leaf().max() == 0
+    rel = compare_levels(sim, ref, 2)
+    say(f"  coarsened: population rel err {rel:.2e}")
+    assert rel <= tol
+    assert sim.refinements() == ref.counters()[2] == 2
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_curl_vortex_tube_three_levels(env, storage, tol):
+    """A Gaussian vortex tube (plus small noise) on an all-level-0 start:
+    the curl sensor refines the core to level 1 at the first check and to
+    level 2 at the second (sensors on all three levels, blocks next to level
+    interfaces, fluid-only differences); layouts and populations follow the
+    oracle over four coarse steps, each followed by a check."""
+    pkg, oracle = env
+    n0 = (64, 32, 32)
+    c = cfg_of(n0, 3, omega=1.7, F=(1e-5, 0.0, 0.0))
+    u0 = synth.vortex_tube(n0, (24.3, 15.2), 4.0, 1e-3) + synth.velocity_perturbation(n0, seed=21, amplitude=1e-5)
+    c["curl_threshold"] = 9.3e-4
+    c["curl_coarsen"] = 0.2
+    say(f"case curl vortex 64x32x32 L3 {storage}")
+    sim = pkg.Sim(c, [], storage=storage, check_every=1)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, check_every=1)
+    ref.init(1.0, u0)
+    for k in range(1, 5):
+        sim.step(1)
+        ref.step(1)
+        sim.sync()
+        rel = compare_levels(sim, ref, 3)
+        say(f"  step {k}: blocks per level {[len(sim.level_blocks(l)) for l in range(3)]}, rel err {rel:.2e}")
+        assert rel <= tol
+    assert ref.leaf().max() == 2
+    assert sim.refinements() == ref.counters()[2] == 2
