@@ -57,6 +57,7 @@ def lib():
         vp = ctypes.c_void_p
         for name, args in [
             ("ora_add_sphere", [vp, ctypes.POINTER(Sphere)]),
+            ("ora_set_sphere_motion", [vp, ctypes.c_int, vp, vp, ctypes.c_int]),
             ("ora_init", [vp, ctypes.c_double, ctypes.c_void_p]),
             ("ora_init_fields", [vp, ctypes.c_void_p, ctypes.c_void_p]),
             ("ora_step", [vp, ctypes.c_int]),
@@ -271,6 +272,12 @@ class Uniform:
         _check(lib().ora_particle(self.h, i, x.ctypes.data, u.ctypes.data, w.ctypes.data), "particle")
         return x, u, w
 
+    def set_sphere_motion(self, i, u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), fixed=0):
+        """New velocities and hold mode (0 free, 1 held, 2 rotation only)."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(lib().ora_set_sphere_motion(self.h, i, u.ctypes.data, w.ctypes.data, int(fixed)), "set_sphere_motion")
+
     def fields(self):
         nx, ny, nz = self.n
         rho = np.zeros((nz, ny, nx))
@@ -325,6 +332,7 @@ def _bind_refine(L):
     for name, args in [
         ("orf_add_region", [vp, vp, vp, ctypes.c_int]),
         ("orf_add_sphere", [vp, ctypes.POINTER(Sphere)]),
+        ("orf_set_sphere_motion", [vp, ctypes.c_int, vp, vp, ctypes.c_int]),
         ("orf_init", [vp, ctypes.c_double, vp]),
         ("orf_set_level_velocity", [vp, ctypes.c_int, ctypes.c_double, vp]),
         ("orf_step", [vp, ctypes.c_int]),
@@ -435,6 +443,11 @@ class Refined:
         x, u, w = np.zeros(3), np.zeros(3), np.zeros(3)
         _check(lib().orf_particle(self.h, i, x.ctypes.data, u.ctypes.data, w.ctypes.data), "particle")
         return x, u, w
+
+    def set_sphere_motion(self, i, u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), fixed=0):
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        _check(lib().orf_set_sphere_motion(self.h, i, u.ctypes.data, w.ctypes.data, int(fixed)), "set_sphere_motion")
 
     def owner(self):
         nx, ny, nz = self.dims(self.levels - 1)

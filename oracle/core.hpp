@@ -213,7 +213,7 @@ inline void collide_mrt(const double f[19], double snu, double sm, double sb, co
 struct Sph {
   double x[3], u[3], w[3];
   double r, rho, cv, cvw;
-  int fixed;
+  int fixed;                    // 0 free, 1 held (u = w = 0), 2 position held, rotation free
   double a[3], b[3];            // accelerations of the previous step
   double Fprev[3], Tprev[3];    // raw hydrodynamic F/T of the previous step
   int have_prev;
@@ -243,6 +243,8 @@ inline double link_delta(const double d[3], const int c[3], double r) {
 // reading: hydrodynamic F/T "averaged over two time steps" is the mean of the
 // raw sums of this and the previous step (the first step uses its own);
 // a_{t-1} and beta_{t-1} start at zero; rho_f = 1; V_p = 4/3 pi r^3.
+// A sphere with fixed == 2 (the rotation test of Sec. 3.4.2: position held,
+// rotation free) integrates only the angular part.
 // ---------------------------------------------------------------------------
 inline void update_particle(Sph& s, const double g[3], const int n[3], const int periodic[3]) {
   double Fav[3], Tav[3];
@@ -263,15 +265,16 @@ inline void update_particle(Sph& s, const double g[3], const int n[3], const int
     bn[a] = (Tav[a] + Tv) / I;
   }
   for (int a = 0; a < 3; ++a) {
-    s.u[a] = s.u[a] + 0.5 * (s.a[a] + an[a]);
     s.w[a] = s.w[a] + 0.5 * (s.b[a] + bn[a]);
+    s.b[a] = bn[a];
+    if (s.fixed == 2) continue;
+    s.u[a] = s.u[a] + 0.5 * (s.a[a] + an[a]);
     s.x[a] = s.x[a] + s.u[a] + 0.5 * an[a];
     if (periodic[a]) {
       if (s.x[a] < 0.0) s.x[a] += n[a];
       else if (s.x[a] >= n[a]) s.x[a] -= n[a];
     }
     s.a[a] = an[a];
-    s.b[a] = bn[a];
   }
 }
 

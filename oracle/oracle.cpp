@@ -324,9 +324,9 @@ void step_double(Grid<double>& G) {
   for (size_t p = 0; p < G.sph.size(); ++p) {
     Sph& s = G.sph[p];
     for (int a = 0; a < 3; ++a) { s.F[a] = G.last_F[3 * p + a]; s.T[a] = G.last_T[3 * p + a]; }
-    if (!s.fixed) {
+    if (s.fixed != 1) {
       update_particle(s, G.cfg.gravity, G.cfg.n, G.cfg.periodic);
-      moving = true;
+      moving = moving || s.fixed == 0;
     }
     for (int a = 0; a < 3; ++a) { s.Fprev[a] = s.F[a]; s.Tprev[a] = s.T[a]; }
     s.have_prev = 1;
@@ -440,9 +440,27 @@ int ora_add_sphere(void* h, const ora_sphere* s) {
   Sph p{};
   for (int a = 0; a < 3; ++a) { p.x[a] = s->x[a]; p.u[a] = s->u[a]; p.w[a] = s->w[a]; }
   p.r = s->radius; p.rho = s->density_ratio; p.cv = s->cv; p.cvw = s->cv_omega; p.fixed = s->fixed;
-  if (p.fixed) for (int a = 0; a < 3; ++a) { p.u[a] = 0.0; p.w[a] = 0.0; }
+  if (p.fixed < 0 || p.fixed > 2) return -1;
+  for (int a = 0; a < 3; ++a) {
+    if (p.fixed) p.u[a] = 0.0;
+    if (p.fixed == 1) p.w[a] = 0.0;
+  }
   G->sph.push_back(p);
   return (int)G->sph.size() - 1;
+}
+
+// new velocities and hold mode of sphere id (position unchanged); the
+// accelerations and the previous step's F/T are kept
+int ora_set_sphere_motion(void* h, int id, const double u[3], const double w[3], int fixed) {
+  auto* G = static_cast<Grid<double>*>(h);
+  if (!G || id < 0 || id >= (int)G->sph.size() || fixed < 0 || fixed > 2) return -1;
+  Sph& s = G->sph[id];
+  s.fixed = fixed;
+  for (int a = 0; a < 3; ++a) {
+    s.u[a] = fixed ? 0.0 : u[a];
+    s.w[a] = fixed == 1 ? 0.0 : w[a];
+  }
+  return 0;
 }
 
 int ora_init(void* h, double rho, const double* u0) {
@@ -574,7 +592,8 @@ int ora_vm_trajectory(const ora_sphere* s0, const double F[3], const double T[3]
   Sph s{};
   for (int a = 0; a < 3; ++a) { s.x[a] = s0->x[a]; s.u[a] = s0->u[a]; s.w[a] = s0->w[a]; s.a[a] = s.b[a] = 0.0; }
   s.r = s0->radius; s.rho = s0->density_ratio; s.cv = s0->cv; s.cvw = s0->cv_omega;
-  s.fixed = 0; s.have_prev = 0;
+  s.fixed = s0->fixed == 2 ? 2 : 0;
+  s.have_prev = 0;
   const int n[3] = {1, 1, 1}, periodic[3] = {0, 0, 0};
   for (int k = 0; k < nsteps; ++k) {
     for (int a = 0; a < 3; ++a) { s.F[a] = F[a]; s.T[a] = T[a]; }

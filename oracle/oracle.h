@@ -37,7 +37,7 @@ typedef struct {
 typedef struct {
   double x[3], u[3], w[3];
   double radius, density_ratio, cv, cv_omega;
-  int fixed;
+  int fixed;                /* 0 free, 1 held (u = w = 0), 2 position held, rotation free */
 } ora_sphere;
 
 /* lattice tables in the oracle's order */
@@ -72,6 +72,9 @@ int ora_pre_collision(void* h, double* out);   /* f(n), solid cells = 0 */
 int ora_owner(void* h, int* out);              /* -1 fluid, else sphere id */
 int ora_force_torque(void* h, int id, double F[3], double T[3]); /* raw F^n of last step */
 int ora_particle(void* h, int id, double x[3], double u[3], double w[3]);
+/* new velocities and hold mode of a sphere, position unchanged (u = 0 when
+ * held, w = 0 when fixed = 1); accelerations and last F/T are kept */
+int ora_set_sphere_motion(void* h, int id, const double u[3], const double w[3], int fixed);
 int ora_fields(void* h, double* rho, double* u /* [3][cells] */);
 int ora_steps_done(void* h);
 void ora_destroy(void* h);
@@ -90,7 +93,8 @@ int ora_drag_value(const ora_config* cfg, const ora_sphere* spheres, int nsphere
                    int n_steps, int avg_from, double* J);
 
 /* particle update alone (no fluid): nsteps updates with constant raw
- * hydrodynamic F, T; out[nsteps][15] = x, u, w, a, beta after each step */
+ * hydrodynamic F, T; out[nsteps][15] = x, u, w, a, beta after each step.
+ * s->fixed = 2 integrates the rotation only; other values move freely. */
 int ora_vm_trajectory(const ora_sphere* s, const double F[3], const double T[3], const double g[3],
                       int nsteps, double* out);
 

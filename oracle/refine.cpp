@@ -459,7 +459,10 @@ struct RForest {
     for (size_t p = 0; p < sph.size(); ++p) {
       Sph& s = sph[p];
       for (int a = 0; a < 3; ++a) { s.F[a] = (double)Fs[3 * p + a]; s.T[a] = (double)Ts[3 * p + a]; }
-      if (!s.fixed) { update_particle(s, cfg.gravity, V.n, periodic_all); moving = true; }
+      if (s.fixed != 1) {
+        update_particle(s, cfg.gravity, V.n, periodic_all);
+        moving = moving || s.fixed == 0;
+      }
       for (int a = 0; a < 3; ++a) { s.Fprev[a] = s.F[a]; s.Tprev[a] = s.T[a]; }
       s.have_prev = 1;
     }
@@ -640,7 +643,8 @@ int orf_add_sphere(void* h, const orf_sphere* s) {
   auto* R = static_cast<RForest*>(h);
   if (!R || !s) return -1;
   Sph p{};
-  for (int a = 0; a < 3; ++a) { p.x[a] = s->x[a]; p.u[a] = s->fixed ? 0.0 : s->u[a]; p.w[a] = s->fixed ? 0.0 : s->w[a]; }
+  if (s->fixed < 0 || s->fixed > 2) return -1;
+  for (int a = 0; a < 3; ++a) { p.x[a] = s->x[a]; p.u[a] = s->fixed ? 0.0 : s->u[a]; p.w[a] = s->fixed == 1 ? 0.0 : s->w[a]; }
   p.r = s->radius; p.rho = s->density_ratio; p.cv = s->cv; p.cvw = s->cv_omega; p.fixed = s->fixed;
   R->sph.push_back(p);
   return (int)R->sph.size() - 1;
@@ -790,6 +794,19 @@ int orf_counters(void* h, long long* coarse, long long* fine, int* refinements) 
   if (coarse) *coarse = R->coarse_steps;
   if (fine) *fine = R->fine_steps;
   if (refinements) *refinements = R->refinements;
+  return 0;
+}
+
+// as ora_set_sphere_motion
+int orf_set_sphere_motion(void* h, int id, const double u[3], const double w[3], int fixed) {
+  auto* R = static_cast<RForest*>(h);
+  if (!R || id < 0 || id >= (int)R->sph.size() || fixed < 0 || fixed > 2) return -1;
+  Sph& s = R->sph[id];
+  s.fixed = fixed;
+  for (int a = 0; a < 3; ++a) {
+    s.u[a] = fixed ? 0.0 : u[a];
+    s.w[a] = fixed == 1 ? 0.0 : w[a];
+  }
   return 0;
 }
 

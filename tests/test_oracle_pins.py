@@ -340,6 +340,72 @@ def test_vm_update_closed_form(ora, rho_p, cv):
     assert np.abs(out[:, 0:3] - x_exp).max() < 1e-12
 
 
+def test_vm_rotation_only_closed_form(ora):
+    """fixed = 2 (position held, rotation free): x, u and a stay as they
+    are, beta_n = (T/I_p)(1 - r^(n+1)) with r = C_v,w/(pi_p + C_v,w) and w
+    the velocity-Verlet sum of that sequence."""
+    r_p, rho_p, cv = 3.0, 0.3, 1.0
+    V = 4.0 / 3.0 * np.pi * r_p ** 3
+    Th = np.array([3e-4, 1e-4, -2e-4])
+    s = synth.sphere((1.5, 2.5, 3.5), r_p, density_ratio=rho_p, cv=cv, fixed=2)
+    n = 30
+    out = ora.vm_trajectory(s, np.array([1e-3, 0, 0]), Th, np.array([0, 0, -1e-4]), n)
+    assert (out[:, 0:3] == np.array([1.5, 2.5, 3.5])).all()
+    assert (out[:, 3:6] == 0.0).all() and (out[:, 9:12] == 0.0).all()
+    I = 0.4 * rho_p * V * r_p ** 2
+    rr = cv / (rho_p + cv)
+    k = np.arange(n)
+    b_exp = (Th / I)[None, :] * (1 - rr ** (k + 1))[:, None]
+    assert np.abs(out[:, 12:15] - b_exp).max() < 1e-15
+    w_exp = np.cumsum(b_exp, axis=0) - 0.5 * b_exp
+    assert np.abs(out[:, 6:9] - w_exp).max() < 1e-14
+
+
+def test_free_rotation_in_shear(ora):
+    """A sphere held in place but free to rotate, in plane Couette flow with
+    the walls moving at -U/2 and +U/2 (centre at rest), turns at half the
+    shear rate (the torque-free Stokes result) up to confinement H/d = 4 and
+    resolution r = 4; the torque decays to zero.  A wrong sign of the torque,
+    or a boundary that ignores the spin, breaks it."""
+    H, U = 32, 0.02
+    n = (32, 16, H)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.0, wall_velocity=((-U / 2, 0, 0), (U / 2, 0, 0)))
+    o = ora.Uniform(cfg, [synth.sphere((16.0, 8.0, 16.0), 4.0, density_ratio=1.0, cv=0.5, fixed=2)])
+    z = np.arange(H) + 0.5
+    u0 = np.zeros((3, H, n[1], n[0]))
+    u0[0] = (U * (z / H - 0.5))[:, None, None]
+    o.init(1.0, u0)
+    o.step(600)
+    x, u, w = o.particle(0)
+    F, T = o.force_torque(0)
+    gamma = U / H
+    assert (x == np.array([16.0, 8.0, 16.0])).all() and (u == 0.0).all()
+    assert abs(w[1] / (0.5 * gamma) - 1.0) < 0.03, w
+    assert abs(w[0]) < 1e-12 and abs(w[2]) < 1e-12
+    nu = (1.0 / 1.0 - 0.5) / 3.0
+    T_stokes = 8.0 * np.pi * nu * 4.0 ** 3 * 0.5 * gamma   # on the sphere held still
+    assert abs(T[1]) < 1e-3 * T_stokes
+
+
+def test_set_sphere_motion_hold_and_release(ora):
+    """Switching a held sphere to rotation-only keeps its position and starts
+    the rotation from rest; switching back holds it again (w = 0)."""
+    H, U = 16, 0.02
+    n = (16, 16, H)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.0, wall_velocity=((-U / 2, 0, 0), (U / 2, 0, 0)))
+    o = ora.Uniform(cfg, [synth.sphere((8.0, 8.0, 8.0), 3.0, density_ratio=1.0, cv=0.5, fixed=True)])
+    o.init(1.0)
+    o.step(20)
+    assert (o.particle(0)[2] == 0.0).all()
+    o.set_sphere_motion(0, fixed=2)
+    o.step(20)
+    x, u, w = o.particle(0)
+    assert (x == 8.0).all() and (u == 0.0).all() and w[1] > 0.0
+    o.set_sphere_motion(0, w=(0.0, 1.0, 0.0), fixed=1)
+    o.step(1)
+    assert (o.particle(0)[2] == 0.0).all()
+
+
 def test_galileo_parameterisation():
     """Eq. 13 with u_g = 0.01 for the rising-sphere workload."""
     w = synth.rising()
