@@ -92,7 +92,9 @@ typedef struct {
   double radius;              /* r_p in cells */
   double density_ratio;       /* pi_p = rho_p / rho_f */
   double cv, cv_omega;        /* virtual mass coefficients C_v, C_v,omega (Sec. 3.3) */
-  int fixed;                  /* 1: held in place, surface velocity 0 */
+  int fixed;                  /* 0: free; 1: held in place, surface velocity
+                                 0; 2: position held, rotation free (the
+                                 rotation test of Sec. 3.4.2) */
 } vmlbm_sphere;
 
 /* Create a context from a configuration (copied).  *out receives it. */
@@ -132,12 +134,21 @@ int vmlbm_sync(vmlbm_ctx* ctx);
 /* Particle state after the last step. */
 int vmlbm_get_particle(vmlbm_ctx* ctx, int id, double x[3], double u[3], double w[3]);
 
+/* Change how sphere id moves from the next step on, its position unchanged
+ * (Sec. 3.4.2 holds a sphere until the flow has developed, then lets it
+ * rotate).  fixed as in vmlbm_sphere; u is read when fixed = 0, w when fixed
+ * != 1 (else velocities are set to 0).  The previous accelerations and F/T
+ * are kept, so a released sphere starts from its held state.  fixed = 0 is
+ * refused (VMLBM_EINVAL) unless a sphere was added free, since only then are
+ * the re-mapping paths active.  Synchronises the stream. */
+int vmlbm_set_sphere_motion(vmlbm_ctx* ctx, int id, const double u[3], const double w[3], int fixed);
+
 /* Raw hydrodynamic force and torque F^n, T^n (Eq. 12) of the last (finest)
  * step, before the two-step average of Algorithm 1. */
 int vmlbm_get_force_torque(vmlbm_ctx* ctx, int id, double F[3], double T[3]);
 
-/* Last n history records of sphere id, oldest first: out[n][12] =
- * F^n, T^n, x, u after each step.  n <= history and <= steps done. */
+/* Last n history records of sphere id, oldest first: out[n][15] =
+ * F^n, T^n, x, u, w after each step.  n <= history and <= steps done. */
 int vmlbm_get_history(vmlbm_ctx* ctx, int id, int n, double* out);
 
 /* Post-collision populations f~(n) of a level (uniform grid: level 0),

@@ -22,6 +22,7 @@ ERRORS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: 
 EXPORTS = [
     "vmlbm_create", "vmlbm_add_sphere", "vmlbm_add_refine_region", "vmlbm_required_bytes", "vmlbm_bind_workspace",
     "vmlbm_set_stream", "vmlbm_init_equilibrium", "vmlbm_step", "vmlbm_sync", "vmlbm_get_particle",
+    "vmlbm_set_sphere_motion",
     "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
     "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
@@ -74,6 +75,7 @@ def lib():
             "vmlbm_step": [vp, ctypes.c_int],
             "vmlbm_sync": [vp],
             "vmlbm_get_particle": [vp, ctypes.c_int, vp, vp, vp],
+            "vmlbm_set_sphere_motion": [vp, ctypes.c_int, vp, vp, ctypes.c_int],
             "vmlbm_get_force_torque": [vp, ctypes.c_int, vp, vp],
             "vmlbm_get_history": [vp, ctypes.c_int, ctypes.c_int, vp],
             "vmlbm_read_populations": [vp, ctypes.c_int, vp],
@@ -254,8 +256,16 @@ class Sim:
         self._check(self.L.vmlbm_get_particle(self.h, i, _ptr(x), _ptr(u), _ptr(w)), "particle")
         return x, u, w
 
+    def set_sphere_motion(self, i, u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), fixed=0):
+        """Hold mode of sphere i from the next step on (0 free, 1 held, 2
+        position held with free rotation) and its new velocities."""
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        self._check(self.L.vmlbm_set_sphere_motion(self.h, i, _ptr(u), _ptr(w), int(fixed)), "set_sphere_motion")
+
     def history(self, i, n):
-        out = np.zeros((n, 12))
+        """[n][15]: F, T, x, u, w after each of the last n steps."""
+        out = np.zeros((n, 15))
         self._check(self.L.vmlbm_get_history(self.h, i, n, _ptr(out)), "history")
         return out
 

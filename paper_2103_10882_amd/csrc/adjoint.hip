@@ -337,7 +337,7 @@ int vmlbm_forward_ckpt(vmlbm_ctx* c, int sphere, int n_steps, int avg_from, int 
   for (int a = 0; a < 3; ++a)
     if (!g.periodic[a]) return fail(c, VMLBM_EINVAL, "adjoint needs a periodic domain");
   for (const auto& s : c->spheres)
-    if (!s.fixed) return fail(c, VMLBM_EINVAL, "adjoint needs fixed spheres");
+    if (s.fixed != 1) return fail(c, VMLBM_EINVAL, "adjoint needs spheres held in place");
   if (sphere < 0 || sphere >= (int)c->spheres.size()) return fail(c, VMLBM_EINVAL, "bad sphere id");
   if (n_steps <= 0 || n_steps > g.adjoint_steps || ckpt_every != g.ckpt_every || n_steps % ckpt_every)
     return fail(c, VMLBM_EINVAL, "n_steps must be a multiple of ckpt_every (%d) and <= %d", g.ckpt_every,
@@ -357,11 +357,11 @@ int vmlbm_forward_ckpt(vmlbm_ctx* c, int sphere, int n_steps, int avg_from, int 
   }
   rc = vmlbm_sync(c);
   if (rc) return rc;
-  std::vector<double> h((size_t)W * 12);
+  std::vector<double> h((size_t)W * kHistWords);
   rc = vmlbm_get_history(c, sphere, W, h.data());
   if (rc) return rc;
   long double acc = 0.0L;
-  for (int i = 0; i < W; ++i) acc += h[(size_t)i * 12 + 2];
+  for (int i = 0; i < W; ++i) acc += h[(size_t)i * kHistWords + 2];
   *J = (double)(acc / W);
   A.n_steps = n_steps;
   A.avg_from = avg_from;

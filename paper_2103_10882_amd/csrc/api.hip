@@ -54,7 +54,7 @@ void plan_uniform(vmlbm_ctx* c) {
   c->off_owner = take(2 * N);
   c->off_parts = take(std::max(np, 1) * sizeof(DevParticle));
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
-  c->off_hist = take((size_t)std::max(g.history, 1) * std::max(np, 1) * 12 * sizeof(double));
+  c->off_hist = take((size_t)std::max(g.history, 1) * std::max(np, 1) * kHistWords * sizeof(double));
   c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
   c->off_lcount = take((size_t)std::max(np, 1) * link_chunks(box) * sizeof(int));
   c->off_links = take((size_t)std::max(np, 1) * box * box * box * sizeof(uint32_t));
@@ -238,7 +238,8 @@ int vmlbm_create(const vmlbm_config* cfg, vmlbm_ctx** out) {
 int vmlbm_add_sphere(vmlbm_ctx* c, const vmlbm_sphere* s, int* id) {
   if (!c || !s) return VMLBM_EINVAL;
   if (c->ws) return fail(c, VMLBM_ESTATE, "spheres must be added before the workspace is bound");
-  if (!(s->radius > 0.0) || !(s->density_ratio > 0.0) || s->cv < 0.0 || s->cv_omega < 0.0)
+  if (!(s->radius > 0.0) || !(s->density_ratio > 0.0) || s->cv < 0.0 || s->cv_omega < 0.0 || s->fixed < 0 ||
+      s->fixed > 2)
     return fail(c, VMLBM_EINVAL, "bad sphere parameters");
   if (c->spheres.size() >= 65535) return fail(c, VMLBM_ERANGE, "too many spheres");
   const int box = (int)std::ceil(2.0 * s->radius) + 8;
@@ -258,7 +259,7 @@ int vmlbm_add_sphere(vmlbm_ctx* c, const vmlbm_sphere* s, int* id) {
       return fail(c, VMLBM_ERANGE, "spheres closer than 3 cells");
   }
   c->spheres.push_back(*s);
-  if (!s->fixed) c->moving = true;
+  if (s->fixed == 0) c->moving = true;
   if (id) *id = (int)c->spheres.size() - 1;
   return VMLBM_OK;
 }
@@ -317,7 +318,7 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
     for (int a = 0; a < 3; ++a) {
       P.x[a] = s.x[a];
       P.u[a] = s.fixed ? 0.0 : s.u[a];
-      P.w[a] = s.fixed ? 0.0 : s.w[a];
+      P.w[a] = s.fixed == 1 ? 0.0 : s.w[a];
     }
     P.r = s.radius; P.rho = s.density_ratio; P.cv = s.cv; P.cvw = s.cv_omega;
     P.fixed = s.fixed; P.have_prev = 0;
@@ -329,7 +330,7 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
     }
   }
   if (np) HIP_TRY(c, hipMemcpyAsync(c->parts(), hp.data(), np * sizeof(DevParticle), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * 12 * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * kHistWords * sizeof(double), c->stream));
   if (c->use_flags)
     HIP_TRY(c, launch_map_all(c->flags(), c->owner(), c->parts(), np, c->links(), p0, c->status(), c->stream));
   double* u0d = nullptr;
@@ -390,6 +391,27 @@ int vmlbm_get_particle(vmlbm_ctx* c, int id, double x[3], double u[3], double w[
   return VMLBM_OK;
 }
 
+int vmlbm_set_sphere_motion(vmlbm_ctx* c, int id, const double u[3], const double w[3], int fixed) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (id < 0 || id >= (int)c->spheres.size() || fixed < 0 || fixed > 2)
+    return fail(c, VMLBM_EINVAL, "bad sphere id or mode");
+  if (fixed == 0 && !c->moving)
+    return fail(c, VMLBM_EINVAL, "a sphere can move freely only if one was added free");
+  if ((fixed == 0 && !u) || (fixed != 1 && !w)) return fail(c, VMLBM_EINVAL, "velocity missing");
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  DevParticle P;
+  HIP_TRY(c, hipMemcpy(&P, c->parts() + id, sizeof(P), hipMemcpyDeviceToHost));
+  P.fixed = fixed;
+  for (int a = 0; a < 3; ++a) {
+    P.u[a] = fixed ? 0.0 : u[a];
+    P.w[a] = fixed == 1 ? 0.0 : w[a];
+  }
+  HIP_TRY(c, hipMemcpy(c->parts() + id, &P, sizeof(P), hipMemcpyHostToDevice));
+  c->spheres[id].fixed = fixed;
+  return VMLBM_OK;
+}
+
 int vmlbm_get_force_torque(vmlbm_ctx* c, int id, double F[3], double T[3]) {
   int rc = check_ready(c);
   if (rc) return rc;
@@ -413,12 +435,12 @@ int vmlbm_get_history(vmlbm_ctx* c, int id, int n, double* out) {
   const long long done = c->particle_steps();
   if (n < 0 || n > H || n > done) return fail(c, VMLBM_EINVAL, "history holds %d of %lld steps", H, done);
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<double> h((size_t)H * np * 12);
+  std::vector<double> h((size_t)H * np * kHistWords);
   HIP_TRY(c, hipMemcpy(h.data(), c->hist(), h.size() * sizeof(double), hipMemcpyDeviceToHost));
   for (int i = 0; i < n; ++i) {
     const long long step = done - n + i;
-    const double* src = h.data() + ((size_t)(step % H) * np + id) * 12;
-    memcpy(out + 12 * i, src, 12 * sizeof(double));
+    const double* src = h.data() + ((size_t)(step % H) * np + id) * kHistWords;
+    memcpy(out + kHistWords * i, src, kHistWords * sizeof(double));
   }
   return VMLBM_OK;
 }

@@ -52,6 +52,7 @@ constexpr uint8_t kNearW = 0x20;   // fluid cell with a wall link
 constexpr int kStatusUnstable = 0;  // non-finite density / force / torque
 constexpr int kStatusRange = 1;     // particle moved too fast / links to two particles from one cell
 constexpr int kStatusWords = 16;
+constexpr int kHistWords = 15;     // per sphere and step: F, T, x, u, w
 
 // ---------------------------------------------------------------------------
 // storage precision: load/store of deviations
@@ -139,7 +140,7 @@ struct DevParticle {
   double F[3], T[3];           // raw hydrodynamic F^n, T^n of the last step
   double Fprev[3], Tprev[3];   // of the step before
   double r, rho, cv, cvw;
-  int fixed, have_prev;
+  int fixed, have_prev;        // fixed: 0 free, 1 held (u = w = 0), 2 position held, rotation free
   int box_lo[3];               // box of the coming sweep (holds every link cell)
   int remap_lo[3];             // re-mapping region origin (old and new position)
 };

@@ -1316,7 +1316,7 @@ int refine_plan(vmlbm_ctx* c) {
   c->off_status = take(kStatusWords * sizeof(int));
   c->off_parts = take(std::max(np, 1) * sizeof(DevParticle));
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
-  c->off_hist = take((size_t)std::max(c->cfg.history, 1) * std::max(np, 1) * 12 * sizeof(double));
+  c->off_hist = take((size_t)std::max(c->cfg.history, 1) * std::max(np, 1) * kHistWords * sizeof(double));
   c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
   c->off_lcount = take((size_t)std::max(np, 1) * link_chunks(box) * sizeof(int));
   c->off_links = take((size_t)std::max(np, 1) * box * box * box * sizeof(uint32_t));
@@ -1366,7 +1366,7 @@ int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
     for (int a = 0; a < 3; ++a) {
       P.x[a] = s.x[a];
       P.u[a] = s.fixed ? 0.0 : s.u[a];
-      P.w[a] = s.fixed ? 0.0 : s.w[a];
+      P.w[a] = s.fixed == 1 ? 0.0 : s.w[a];
     }
     P.r = s.radius; P.rho = s.density_ratio; P.cv = s.cv; P.cvw = s.cv_omega;
     P.fixed = s.fixed;
@@ -1379,7 +1379,7 @@ int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
     }
   }
   if (np) HIP_TRY(c, hipMemcpyAsync(c->parts(), hp.data(), np * sizeof(DevParticle), hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * 12 * sizeof(double), c->stream));
+  HIP_TRY(c, hipMemsetAsync(c->hist(), 0, (size_t)c->cfg.history * std::max(np, 1) * kHistWords * sizeof(double), c->stream));
   // velocity staging in the second buffer of level 0
   Forest::Lev& V0 = f.lv[0];
   const uint32_t N0 = (uint32_t)((size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2]);

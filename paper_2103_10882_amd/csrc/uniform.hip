@@ -137,7 +137,18 @@ __device__ void particle_update(DevParticle& P, const double (&F)[3], const doub
   if (!finite) status[kStatusUnstable] = 2;
   for (int a = 0; a < 3; ++a) { P.F[a] = F[a]; P.T[a] = T[a]; }
   double xold[3] = {P.x[0], P.x[1], P.x[2]};
-  if (!P.fixed) {
+  if (P.fixed == 2) {
+    // position held, rotation free (the rotation test of Sec. 3.4.2)
+    const double PI = 3.14159265358979323846;
+    const double V = 4.0 / 3.0 * PI * P.r * P.r * P.r;
+    const double I = 0.4 * (P.rho + P.cvw) * V * P.r * P.r;
+    for (int a = 0; a < 3; ++a) {
+      const double Tav = P.have_prev ? 0.5 * (T[a] + P.Tprev[a]) : T[a];
+      const double bn = (Tav + 0.4 * P.cvw * V * P.r * P.r * P.b[a]) / I;
+      P.w[a] = P.w[a] + 0.5 * (P.b[a] + bn);
+      P.b[a] = bn;
+    }
+  } else if (!P.fixed) {
     const double PI = 3.14159265358979323846;
     const double V = 4.0 / 3.0 * PI * P.r * P.r * P.r;
     const double m = (P.rho + P.cv) * V;
@@ -209,8 +220,14 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
   particle_update(P, F, T, status, p, u);
   for (int a = 0; a < 3; ++a) { P.Fprev[a] = F[a]; P.Tprev[a] = T[a]; }
   P.have_prev = 1;
-  double* h = hist + ((size_t)(u.step % u.hist_len) * u.np + pi) * 12;
-  for (int a = 0; a < 3; ++a) { h[a] = F[a]; h[3 + a] = T[a]; h[6 + a] = P.x[a]; h[9 + a] = P.u[a]; }
+  double* h = hist + ((size_t)(u.step % u.hist_len) * u.np + pi) * kHistWords;
+  for (int a = 0; a < 3; ++a) {
+    h[a] = F[a];
+    h[3 + a] = T[a];
+    h[6 + a] = P.x[a];
+    h[9 + a] = P.u[a];
+    h[12 + a] = P.w[a];
+  }
 }
 
 // fixed-order partial sums over fluid cells: count, sum of deviations and

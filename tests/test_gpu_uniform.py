@@ -354,3 +354,47 @@ def test_sphere_next_to_wall(env):
                             wall_velocity=((0.002, 0.0, 0.0), (0.0, 0.0, 0.0)))
     s = synth.sphere((11.6, 10.9, 5.5), 4.0, density_ratio=2.0, cv=0.5, fixed=False, u=(0.0, 0.0, -0.004))
     run_parity(pkg, oracle, cfg, [s], 80, 4.0, "wall-sphere24x22x26 f64")
+
+
+def test_hold_then_rotate(env):
+    """The rotation test's protocol (Sec. 3.4.2) on a small box: a sphere
+    held in plane Couette flow (walls at -U/2 and +U/2), then switched to
+    rotation-only, then a second sphere switched back to held.  F/T every
+    step, angular velocity, history and populations follow the oracle;
+    positions and translational velocities stay exactly fixed."""
+    pkg, oracle = env
+    H, U = 32, 0.02
+    n = (40, 24, H)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.3, wall_velocity=((-U / 2, 0, 0), (U / 2, 0, 0)))
+    sph = [synth.sphere((11.6, 12.3, 15.4), 4.6, density_ratio=0.7, cv=1.0, fixed=True),
+           synth.sphere((30.2, 7.7, 18.9), 3.8, density_ratio=1.1, cv=1.0, fixed=2, w=(0.0, 1e-4, 0.0))]
+    z = np.arange(H) + 0.5
+    u0 = np.zeros((3, H, n[1], n[0]))
+    u0[0] = (U * (z / H - 0.5))[:, None, None]
+    say("case hold-then-rotate 40x24x32 Couette f64")
+    sim = pkg.Sim(cfg, sph, storage="f64", history=64)
+    sim.init(1.0, u0)
+    ref = oracle.Uniform(cfg, sph)
+    ref.init(1.0, u0)
+    for k in range(1, 61):
+        if k == 21:
+            for o in (sim, ref):
+                o.set_sphere_motion(0, fixed=2)
+                o.set_sphere_motion(1, fixed=1)
+        sim.step(1)
+        ref.step(1)
+        check_ft(sim, ref, 2, 4.6, where=f"step {k}")
+    sim.sync()
+    for i in range(2):
+        xg, ug, wg = sim.particle(i)
+        xo, uo, wo = ref.particle(i)
+        assert (xg == np.array(sph[i]["x"])).all() and (ug == 0.0).all()
+        assert np.abs(wg - wo).max() <= 1e-12 * max(np.abs(wo).max(), 1e-6), (i, wg, wo)
+    wg0 = sim.particle(0)[2]
+    assert wg0[1] > 0.0 and (sim.particle(1)[2] == 0.0).all()
+    h = sim.history(0, 40)
+    assert (h[-1, 12:15] == wg0).all() and (h[:, 6:12] == np.concatenate([sph[0]["x"], [0.0] * 3])).all()
+    rel = pop_rel(sim.populations(), ref.post_collision())
+    say(f"  w_y {wg0[1]:.3e}, population rel err {rel:.2e}")
+    assert rel <= 1e-12
+    sim.close()
