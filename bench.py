@@ -185,6 +185,181 @@ def run_adjoint(pkg, storage="f32"):
             "forward_s": t1 - t0, "reverse_s": t2 - t1, "cost_ratio": (t2 - t1) / (t1 - t0)}
 
 
+# ---------------------------------------------------------------------------
+# validation workloads of Sec. 3 (run with --validate; not part of the
+# headline line).  The paper's printed figures are kept here as context.
+# ---------------------------------------------------------------------------
+PAPER_TABLE1_PI_MIN = {10: 0.13, 15: 0.09, 20: 0.066, 30: 0.045, 40: 0.034, 50: 0.03, 80: 0.02}   # Table 1, Ga 100
+PAPER_TABLE2 = {   # Sec. 3.4.1, Table 2: VM-MEM (C_v = 1) against MEM, d_p = 40
+    0.1: {"ga": 100.0, "re_p": 113.08, "eps_sq": 15.48e-9, "eps_rel": 0.28e-3, "eps_term_rel": 0.04e-3},
+    1.1: {"ga": 100.0, "re_p": 111.77, "eps_sq": 1.85e-9, "eps_rel": 0.15e-3, "eps_term_rel": 0.06e-3},
+    0.001: {"ga": 170.0, "re_p": 225.64},
+}
+PAPER_ROTATION = {0.1: {"eps_rel": 0.46e-3, "eps_term_rel": 0.01e-3},   # Sec. 3.4.2, VM-MEM vs MEM
+                  1.1: {"eps_rel": 0.15e-3, "eps_term_rel": 0.0}}
+
+
+def _run_chunks(pkg, sim, steps, chunk, speed_limit, tag):
+    """Step in chunks; a run is unstable once the library flags a non-finite
+    or runaway state, or the sphere's speed passes speed_limit.  Returns
+    (status, steps done)."""
+    import numpy as np
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        sim.step(k)
+        try:
+            sim.sync()
+        except pkg.VmlbmError as e:
+            log(f"  {tag}: unstable at step <= {done + k} ({e})")
+            return "unstable", done
+        done += k
+        _, u, w = sim.particle(0)
+        if not (np.all(np.isfinite(u)) and np.all(np.isfinite(w))) or max(np.abs(u).max(), 0.0) > speed_limit:
+            log(f"  {tag}: unstable at step {done} (u = {u})")
+            return "unstable", done
+        log(f"  {tag}: step {done}/{steps}, u = {u[2]:.5f}, w = {w[1]:.3e}")
+    return "stable", done
+
+
+def run_light_sphere(pkg, d_p, pi_p, ga=100.0, cv=0.0, t_n=10.0, storage="f64", compensate=False):
+    """One rising/settling sphere run of Sec. 3.1 / 3.4.1 up to t_n = t u_g / d_p."""
+    import numpy as np
+    import torch
+    import synth
+    w = synth.light_box(d_p, pi_p, ga=ga, cv=cv, compensate=compensate)
+    steps = int(round(t_n * w["t_g"]))
+    tag = w["name"]
+    sim = pkg.Sim(w["config"], w["spheres"], storage=storage, history=steps)
+    sim.init()
+    t0 = time.time()
+    status, done = _run_chunks(pkg, sim, steps, max(500, steps // 20), 10.0 * synth.U_G, tag)
+    h = sim.history(0, done) if done > 0 else np.zeros((0, 15))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"status": status, "steps": done, "of": steps, "seconds": time.time() - t0,
+            "uz_n": h[:, 11] / synth.U_G, "nu": w["nu"], "t_g": w["t_g"]}
+
+
+def _errors(u, ref, every):
+    """Mean squared and mean relative error and the terminal relative error
+    of a series against a reference (Sec. 3.4.1), sampled every `every`
+    steps from the first sample on."""
+    import numpy as np
+    a = np.abs(u[every - 1::every])
+    b = np.abs(ref[every - 1::every])
+    return {"m": int(len(a)), "eps_sq": float(np.mean((a - b) ** 2)), "eps_rel": float(np.mean((a - b) / b)),
+            "eps_term_rel": float((a[-1] - b[-1]) / b[-1])}
+
+
+def validate_stability(pkg, diameters=(10, 15, 20, 30), storage="f64", bisections=4):
+    """Table 1: lowest density ratio at Ga 100 for which plain MEM stays
+    stable up to t_n = 10, bracketed by bisection in log(pi_p) from the
+    paper's value x {1/2, 2}; VM-MEM (C_v = 1) run at the unstable end."""
+    import math
+    out = {}
+    for d in diameters:
+        ref = PAPER_TABLE1_PI_MIN[d]
+        runs = {}
+
+        def stable(pi_p, cv=0.0):
+            r = run_light_sphere(pkg, d, pi_p, cv=cv, storage=storage)
+            runs["%.5g cv%g" % (pi_p, cv)] = {"status": r["status"], "steps": r["steps"], "of": r["of"]}
+            return r["status"] == "stable"
+
+        lo, hi = 0.5 * ref, 2.0 * ref
+        if not stable(hi):
+            hi *= 2.0
+            stable(hi)
+        if stable(lo):
+            out[d] = {"paper": ref, "pi_min_at_most": lo, "runs": runs}
+            continue
+        for _ in range(bisections):
+            mid = math.exp(0.5 * (math.log(lo) + math.log(hi)))
+            if stable(mid):
+                hi = mid
+            else:
+                lo = mid
+        vm_ok = stable(lo, cv=1.0)
+        out[d] = {"paper": ref, "pi_min_bracket": [round(lo, 5), round(hi, 5)], "vm_mem_stable_at_lo": vm_ok,
+                  "runs": runs}
+    return out
+
+
+def validate_translation(pkg, d_p=40, storage="f64", compensated=False):
+    """Table 2: VM-MEM (C_v = 1) against MEM for pi_p = 0.1 and 1.1 at Ga 100,
+    and VM-MEM alone at pi_p = 0.001, Ga 170 (MEM is expected to fail).
+    compensated: also MEM with a fluid force cancelling the net weight
+    (Re_p only), the other reading of the setup."""
+    out = {}
+    for pi_p in (0.1, 1.1):
+        ga = PAPER_TABLE2[pi_p]["ga"]
+        mem = run_light_sphere(pkg, d_p, pi_p, ga=ga, cv=0.0, storage=storage)
+        vm = run_light_sphere(pkg, d_p, pi_p, ga=ga, cv=1.0, storage=storage)
+        r = {"status_mem": mem["status"], "status_vm": vm["status"], "paper": PAPER_TABLE2[pi_p]}
+        if mem["status"] == vm["status"] == "stable":
+            r.update(_errors(vm["uz_n"], mem["uz_n"], 100))
+            for k, run in (("mem", mem), ("vm", vm)):
+                r["re_p_" + k] = float(abs(run["uz_n"][-1]) * 0.01 * d_p / run["nu"])
+        if compensated:
+            cm = run_light_sphere(pkg, d_p, pi_p, ga=ga, cv=0.0, storage=storage, compensate=True)
+            if cm["status"] == "stable":
+                r["re_p_mem_compensated"] = float(abs(cm["uz_n"][-1]) * 0.01 * d_p / cm["nu"])
+        out[pi_p] = r
+    vm = run_light_sphere(pkg, d_p, 0.001, ga=170.0, cv=1.0, storage=storage)
+    mem = run_light_sphere(pkg, d_p, 0.001, ga=170.0, cv=0.0, storage=storage)
+    r = {"status_vm": vm["status"], "status_mem": mem["status"], "steps_mem": mem["steps"],
+         "paper": PAPER_TABLE2[0.001]}
+    if vm["status"] == "stable":
+        r["re_p_vm"] = float(abs(vm["uz_n"][-1]) * 0.01 * d_p / vm["nu"])
+    out[0.001] = r
+    return out
+
+
+def run_rotation(pkg, d_p, pi_p, cv, hold_tc=20.0, free_tc=20.0, storage="f64"):
+    """Sec. 3.4.2: Couette-driven sphere held for hold_tc t_c, then free to
+    rotate (position held) for free_tc t_c; omega_n = omega_y / omega_c."""
+    import numpy as np
+    import torch
+    import synth
+    w = synth.rotation_box(d_p, pi_p, cv=cv)
+    hold = int(round(hold_tc * w["t_c"]))
+    free = int(round(free_tc * w["t_c"]))
+    tag = w["name"]
+    sim = pkg.Sim(w["config"], w["spheres"], storage=storage, history=free)
+    sim.init(1.0, w["u0"])
+    t0 = time.time()
+    status, done = _run_chunks(pkg, sim, hold, 2000, 1.0, tag + " held")
+    fdone = 0
+    if status == "stable":
+        sim.set_sphere_motion(0, fixed=2)
+        status, fdone = _run_chunks(pkg, sim, free, 2000, 1.0, tag + " rotating")
+    h = sim.history(0, fdone) if fdone > 0 else np.zeros((0, 15))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"status": status, "steps_free": fdone, "of": free, "seconds": time.time() - t0,
+            "omega_n": h[:, 13] / w["omega_c"], "t_c": w["t_c"]}
+
+
+def validate_rotation(pkg, d_p=40, storage="f64"):
+    """Sec. 3.4.2 table: VM-MEM (C_v = C_v,omega = 1) against MEM for pi_p =
+    0.1 and 1.1, and both at pi_p = 0.001."""
+    out = {}
+    for pi_p in (0.1, 1.1, 0.001):
+        mem = run_rotation(pkg, d_p, pi_p, 0.0, storage=storage)
+        vm = run_rotation(pkg, d_p, pi_p, 1.0, storage=storage)
+        r = {"status_mem": mem["status"], "status_vm": vm["status"], "paper": PAPER_ROTATION.get(pi_p)}
+        if mem["status"] == vm["status"] == "stable":
+            r.update(_errors(vm["omega_n"], mem["omega_n"], 80))
+        for k, run in (("mem", mem), ("vm", vm)):
+            if run["status"] == "stable":
+                r["omega_n_term_" + k] = float(run["omega_n"][-1])
+        out[pi_p] = r
+    return out
+
+
 def sweep_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -286,6 +461,12 @@ def main():
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run the plain copy used to scale HBM byte counters")
+    ap.add_argument("--validate", default="",
+                    help="only run validation workloads of Sec. 3: any of stability,translation,rotation")
+    ap.add_argument("--validate-diameters", default="10,15,20,30",
+                    help="sphere diameters of the stability bracket (Table 1)")
+    ap.add_argument("--validate-compensated", action="store_true",
+                    help="translation: also run MEM with a fluid force that cancels the net weight")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -296,6 +477,17 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_ref:
         copy_reference()
+        return
+    if args.validate:
+        import paper_2103_10882_amd as pkg
+        pkg.lib()
+        runs = {"stability": lambda: validate_stability(
+                    pkg, tuple(int(v) for v in args.validate_diameters.split(","))),
+                "translation": lambda: validate_translation(pkg, compensated=args.validate_compensated),
+                "rotation": lambda: validate_rotation(pkg)}
+        for name in args.validate.split(","):
+            log(f"validation: {name}")
+            print(json.dumps({"validation": name, "result": runs[name]()}, default=str), flush=True)
         return
     import synth
     import paper_2103_10882_amd as pkg

@@ -172,7 +172,12 @@ __device__ void particle_update(DevParticle& P, const double (&F)[3], const doub
       P.b[a] = bn;
     }
     double speed = P.u[0] * P.u[0] + P.u[1] * P.u[1] + P.u[2] * P.u[2];
-    if (!(speed < 0.25)) status[kStatusUnstable] = 3;
+    if (!(speed < 0.25)) {
+      // blown up (the host reports it at the next sync): the sphere keeps
+      // its last position, so boxes and mapping stay finite and in range
+      status[kStatusUnstable] = 3;
+      for (int a = 0; a < 3; ++a) P.x[a] = xold[a];
+    }
     // new boxes: force slots around the new position, re-mapping region
     // covering old and new position
     for (int a = 0; a < 3; ++a) {

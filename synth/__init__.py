@@ -20,6 +20,17 @@ Workloads (lattice units of the finest level, cell (i,j,k) has its centre at
 * ``adjoint``   128^3 periodic, fixed sphere r=10 in the centre, body force
                 1e-5 along z, omega=1.6; drag averaged over steps 1500..1999.
 
+Validation workloads of Sec. 3 (MRT with bulk factor 100, the paper's default):
+
+* ``light_box`` periodic (6.4, 6.4, 12.8) d_p box, sphere of diameter d_p at
+                (3.2, 3.2, 0.6) d_p released at rest, gravity along -z at a
+                Galileo number (Sec. 3.1 and 3.4.1).  Gravity and buoyancy
+                act on the sphere only; the fluid is unforced.
+* ``rotation_box`` (12.8, 6.4, 4.8) d_p, walls at z = 0 (rest) and z = 4.8 d_p
+                (moving at u_w = 0.1 along x), periodic in x and y, Couette
+                start, sphere of diameter d_p held at the centre (Sec. 3.4.2);
+                Re_p = (u_w / 2) d_p / nu.
+
 Galileo-number parameterisation (Eq. 13): u_g = sqrt(|pi_p-1| g d_p) = 0.01,
 Ga = u_g d_p / nu, and nu = (1/omega - 1/2)/3 in lattice units.  The derived
 numbers are written out below next to the inputs they come from.
@@ -189,4 +200,54 @@ def refined(coarse=(128, 128, 512), levels=3, block=16, radius=16.0, ga=250.0,
                            density_ratio=density_ratio, cv=cv, fixed=False)],
         "u0": None,
         "steps": 500,
+    }
+
+
+def light_box(d_p, density_ratio, ga=100.0, cv=0.0, bulk_factor=100.0, compensate=False):
+    """Rising (or settling) sphere in a periodic box (Sec. 3.1, Table 1 and
+    Sec. 3.4.1, Table 2).  d_p a multiple of 5 keeps the box whole.  The
+    fluid is unforced, so the box gains the sphere's net weight as momentum
+    (the reading whose Re_p matches Table 2); compensate=True adds a uniform
+    fluid force that cancels it instead."""
+    n = (int(round(6.4 * d_p)), int(round(6.4 * d_p)), int(round(12.8 * d_p)))
+    nu, omega, g = _ga_params(ga, density_ratio, float(d_p))
+    r = 0.5 * d_p
+    vol = 4.0 / 3.0 * np.pi * r ** 3
+    f_ext = (density_ratio - 1.0) * vol * (-g)        # net weight on the sphere, along z
+    fz = -f_ext / (n[0] * n[1] * n[2] - vol) if compensate else 0.0   # per fluid cell, opposite
+    cfg = base_config(n, omega=omega, body_force=(0.0, 0.0, fz), gravity=(0.0, 0.0, -g))
+    cfg["bulk_factor"] = float(bulk_factor)
+    return {
+        "name": "lightbox_d%d_pi%g_ga%g_cv%g" % (d_p, density_ratio, ga, cv),
+        "config": cfg,
+        "spheres": [sphere((3.2 * d_p, 3.2 * d_p, 0.6 * d_p), r, density_ratio=density_ratio, cv=cv,
+                           fixed=False)],
+        "u0": None,
+        "nu": nu,
+        "t_g": d_p / U_G,
+    }
+
+
+def rotation_box(d_p, density_ratio, cv=0.0, re_p=110.0, u_w=0.1, bulk_factor=100.0):
+    """Couette-driven sphere held at the centre, later free to rotate
+    (Sec. 3.4.2).  d_p a multiple of 5 keeps the box whole."""
+    n = (int(round(12.8 * d_p)), int(round(6.4 * d_p)), int(round(4.8 * d_p)))
+    u_p = 0.5 * u_w
+    nu = u_p * d_p / re_p
+    omega = 1.0 / (3.0 * nu + 0.5)
+    cfg = base_config(n, periodic=(1, 1, 0), omega=omega, wall_velocity=((0.0, 0.0, 0.0), (u_w, 0.0, 0.0)))
+    cfg["bulk_factor"] = float(bulk_factor)
+    H = n[2]
+    z = np.arange(H) + 0.5
+    u0 = np.zeros((3, H, n[1], n[0]))
+    u0[0] = (u_w * z / H)[:, None, None]
+    return {
+        "name": "rotation_d%d_pi%g_cv%g" % (d_p, density_ratio, cv),
+        "config": cfg,
+        "spheres": [sphere((6.4 * d_p, 3.2 * d_p, 2.4 * d_p), 0.5 * d_p, density_ratio=density_ratio, cv=cv,
+                           fixed=True)],
+        "u0": u0,
+        "nu": nu,
+        "t_c": d_p / u_p,
+        "omega_c": u_p / d_p,
     }
