@@ -39,7 +39,8 @@ class Config(ctypes.Structure):
 class Sphere(ctypes.Structure):
     _fields_ = [("x", ctypes.c_double * 3), ("u", ctypes.c_double * 3), ("w", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("density_ratio", ctypes.c_double),
-                ("cv", ctypes.c_double), ("cv_omega", ctypes.c_double), ("fixed", ctypes.c_int)]
+                ("cv", ctypes.c_double), ("cv_omega", ctypes.c_double), ("fixed", ctypes.c_int),
+                ("vm_scheme", ctypes.c_int)]
 
 
 def _dp(a):
@@ -73,7 +74,7 @@ def lib():
                                    ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
             ("ora_drag_value", [ctypes.POINTER(Config), ctypes.POINTER(Sphere), ctypes.c_int,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
-            ("ora_vm_trajectory", [ctypes.POINTER(Sphere), ctypes.c_void_p, ctypes.c_void_p,
+            ("ora_vm_trajectory", [ctypes.POINTER(Sphere), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
             ("ora_num_threads", []),
         ]:
@@ -136,6 +137,7 @@ def make_sphere(s):
     o.cv = s["cv"]
     o.cv_omega = s["cv_omega"]
     o.fixed = int(s["fixed"])
+    o.vm_scheme = int(s.get("vm_scheme", 0))
     return o
 
 
@@ -192,13 +194,16 @@ def link_delta(d, c, radius):
     return lib().ora_link_delta(d.ctypes.data, c.ctypes.data, float(radius))
 
 
-def vm_trajectory(sph, F, T, g, nsteps):
+def vm_trajectory(sph, F, T, g, nsteps, dF=(0.0, 0.0, 0.0)):
+    """Particle update alone: raw force F + k dF at update k, torque T;
+    [nsteps][15] = x, u, w, a, beta after each update."""
     s = make_sphere(sph)
     F = np.ascontiguousarray(F, dtype=np.float64)
+    dF = np.ascontiguousarray(dF, dtype=np.float64)
     T = np.ascontiguousarray(T, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     out = np.zeros((nsteps, 15))
-    _check(lib().ora_vm_trajectory(ctypes.byref(s), F.ctypes.data, T.ctypes.data, g.ctypes.data,
+    _check(lib().ora_vm_trajectory(ctypes.byref(s), F.ctypes.data, dF.ctypes.data, T.ctypes.data, g.ctypes.data,
                                    nsteps, out.ctypes.data), "vm_trajectory")
     return out
 

@@ -440,7 +440,9 @@ int ora_add_sphere(void* h, const ora_sphere* s) {
   Sph p{};
   for (int a = 0; a < 3; ++a) { p.x[a] = s->x[a]; p.u[a] = s->u[a]; p.w[a] = s->w[a]; }
   p.r = s->radius; p.rho = s->density_ratio; p.cv = s->cv; p.cvw = s->cv_omega; p.fixed = s->fixed;
-  if (p.fixed < 0 || p.fixed > 2) return -1;
+  p.scheme = s->vm_scheme;
+  p.nvel = 1;
+  if (p.fixed < 0 || p.fixed > 2 || p.scheme < 0 || p.scheme > 1) return -1;
   for (int a = 0; a < 3; ++a) {
     if (p.fixed) p.u[a] = 0.0;
     if (p.fixed == 1) p.w[a] = 0.0;
@@ -586,17 +588,19 @@ int ora_drag_value(const ora_config* cfg, const ora_sphere* spheres, int nsphere
   return 0;
 }
 
-int ora_vm_trajectory(const ora_sphere* s0, const double F[3], const double T[3], const double g[3],
-                      int nsteps, double* out) {
+int ora_vm_trajectory(const ora_sphere* s0, const double F[3], const double dF[3], const double T[3],
+                      const double g[3], int nsteps, double* out) {
   if (!s0 || nsteps < 0 || !out) return -1;
   Sph s{};
   for (int a = 0; a < 3; ++a) { s.x[a] = s0->x[a]; s.u[a] = s0->u[a]; s.w[a] = s0->w[a]; s.a[a] = s.b[a] = 0.0; }
   s.r = s0->radius; s.rho = s0->density_ratio; s.cv = s0->cv; s.cvw = s0->cv_omega;
   s.fixed = s0->fixed == 2 ? 2 : 0;
+  s.scheme = s0->vm_scheme;
+  s.nvel = 1;
   s.have_prev = 0;
   const int n[3] = {1, 1, 1}, periodic[3] = {0, 0, 0};
   for (int k = 0; k < nsteps; ++k) {
-    for (int a = 0; a < 3; ++a) { s.F[a] = F[a]; s.T[a] = T[a]; }
+    for (int a = 0; a < 3; ++a) { s.F[a] = F[a] + k * dF[a]; s.T[a] = T[a]; }
     update_particle(s, g, n, periodic);
     for (int a = 0; a < 3; ++a) { s.Fprev[a] = s.F[a]; s.Tprev[a] = s.T[a]; }
     s.have_prev = 1;

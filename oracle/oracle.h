@@ -38,6 +38,8 @@ typedef struct {
   double x[3], u[3], w[3];
   double radius, density_ratio, cv, cv_omega;
   int fixed;                /* 0 free, 1 held (u = w = 0), 2 position held, rotation free */
+  int vm_scheme;            /* acceleration in the virtual force: 0 previous step's (Sec. 3.3),
+                               1 Lagrange extrapolation from three velocities */
 } ora_sphere;
 
 /* lattice tables in the oracle's order */
@@ -92,11 +94,12 @@ int ora_drag_gradient(const ora_config* cfg, const ora_sphere* spheres, int nsph
 int ora_drag_value(const ora_config* cfg, const ora_sphere* spheres, int nspheres,
                    int n_steps, int avg_from, double* J);
 
-/* particle update alone (no fluid): nsteps updates with constant raw
- * hydrodynamic F, T; out[nsteps][15] = x, u, w, a, beta after each step.
- * s->fixed = 2 integrates the rotation only; other values move freely. */
-int ora_vm_trajectory(const ora_sphere* s, const double F[3], const double T[3], const double g[3],
-                      int nsteps, double* out);
+/* particle update alone (no fluid): nsteps updates with raw hydrodynamic
+ * force F + k dF at update k and constant T; out[nsteps][15] = x, u, w, a,
+ * beta after each step.  s->fixed = 2 integrates the rotation only; other
+ * values move freely. */
+int ora_vm_trajectory(const ora_sphere* s, const double F[3], const double dF[3], const double T[3],
+                      const double g[3], int nsteps, double* out);
 
 int ora_num_threads(void);
 

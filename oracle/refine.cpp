@@ -53,6 +53,7 @@ typedef struct {
   double x[3], u[3], w[3];
   double radius, density_ratio, cv, cv_omega;
   int fixed;
+  int vm_scheme;
 } orf_sphere;
 }
 
@@ -646,6 +647,9 @@ int orf_add_sphere(void* h, const orf_sphere* s) {
   if (s->fixed < 0 || s->fixed > 2) return -1;
   for (int a = 0; a < 3; ++a) { p.x[a] = s->x[a]; p.u[a] = s->fixed ? 0.0 : s->u[a]; p.w[a] = s->fixed == 1 ? 0.0 : s->w[a]; }
   p.r = s->radius; p.rho = s->density_ratio; p.cv = s->cv; p.cvw = s->cv_omega; p.fixed = s->fixed;
+  p.scheme = s->vm_scheme;
+  p.nvel = 1;
+  if (p.scheme < 0 || p.scheme > 1) return -1;
   R->sph.push_back(p);
   return (int)R->sph.size() - 1;
 }

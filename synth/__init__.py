@@ -63,9 +63,10 @@ def base_config(n, periodic=(1, 1, 1), omega=1.6, body_force=(0.0, 0.0, 0.0),
 
 
 def sphere(x, radius, density_ratio=1.0, cv=0.0, cv_omega=None, fixed=True,
-           u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0)):
+           u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), vm_scheme=0):
     """fixed: True held in place, False free, 2 position held with free
-    rotation."""
+    rotation.  vm_scheme: acceleration inside the virtual force, 0 the
+    previous step's, 1 Lagrange extrapolation from three velocities."""
     return {
         "x": tuple(float(v) for v in x),
         "u": tuple(float(v) for v in u),
@@ -75,6 +76,7 @@ def sphere(x, radius, density_ratio=1.0, cv=0.0, cv_omega=None, fixed=True,
         "cv": float(cv),
         "cv_omega": float(cv if cv_omega is None else cv_omega),
         "fixed": 2 if (fixed == 2 and fixed is not True) else int(bool(fixed)),
+        "vm_scheme": int(vm_scheme),
     }
 
 

@@ -340,6 +340,40 @@ def test_vm_update_closed_form(ora, rho_p, cv):
     assert np.abs(out[:, 0:3] - x_exp).max() < 1e-12
 
 
+@pytest.mark.parametrize("rho_p,cv", [(0.1, 1.0), (0.5, 0.5), (2.0, 0.5)])
+def test_vm_acceleration_schemes_linear_force(ora, rho_p, cv):
+    """Force growing linearly in time, no fluid.  The physical acceleration
+    is A_n = (F_n-bar + F_g) / (pi_p V), with F_n-bar the two-step mean.  With
+    the previous step's acceleration inside the virtual force (Sec. 3.3),
+    a_n settles at a constant lag A_n - r s / (1 - r), where s is the slope
+    of A and r = C_v / (pi_p + C_v).  The quadratic extrapolation from three
+    velocities is exact for velocities quadratic in time, so a_n settles on
+    A_n itself.  Both schemes coincide until three velocities are known."""
+    r_p = 3.0
+    V = 4.0 / 3.0 * np.pi * r_p ** 3
+    F = np.array([1e-4, -2e-4, 5e-5])
+    dF = np.array([1e-7, 2e-7, -3e-7])
+    T = np.array([2e-4, 0.0, -1e-4])
+    g = np.array([0.0, 0.0, -1e-5])
+    n = 3000
+    k = np.arange(n)
+    A = (F[None, :] + (k[:, None] - 0.5) * dF[None, :] + (rho_p - 1.0) * g * V) / (rho_p * V)
+    rr = cv / (rho_p + cv)
+    slope = dF / (rho_p * V)
+    out = {}
+    for scheme in (0, 1):
+        s = synth.sphere((0.0, 0.0, 0.0), r_p, density_ratio=rho_p, cv=cv, fixed=False, vm_scheme=scheme)
+        out[scheme] = ora.vm_trajectory(s, F, T, g, n, dF=dF)
+    scale = np.abs(A[-1]).max()
+    assert np.abs(out[0][-1, 9:12] - (A[-1] - rr * slope / (1 - rr))).max() < 1e-9 * scale
+    assert np.abs(out[1][-1, 9:12] - A[-1]).max() < 1e-9 * scale
+    assert np.abs(out[0][-1, 9:12] - A[-1]).max() > 1e-6 * scale          # the lag is there
+    assert (out[0][:2] == out[1][:2]).all() and (out[0][2] != out[1][2]).any()
+    I_p = 0.4 * rho_p * V * r_p ** 2
+    for scheme in (0, 1):                                                  # constant torque: beta -> T / I_p
+        assert np.abs(out[scheme][-1, 12:15] - T / I_p).max() < 1e-10 * np.abs(T / I_p).max()
+
+
 def test_vm_rotation_only_closed_form(ora):
     """fixed = 2 (position held, rotation free): x, u and a stay as they
     are, beta_n = (T/I_p)(1 - r^(n+1)) with r = C_v,w/(pi_p + C_v,w) and w
