@@ -222,12 +222,12 @@ def _run_chunks(pkg, sim, steps, chunk, speed_limit, tag):
     return "stable", done
 
 
-def run_light_sphere(pkg, d_p, pi_p, ga=100.0, cv=0.0, t_n=10.0, storage="f64", compensate=False):
+def run_light_sphere(pkg, d_p, pi_p, ga=100.0, cv=0.0, t_n=10.0, storage="f64", compensate=False, vm_scheme=0):
     """One rising/settling sphere run of Sec. 3.1 / 3.4.1 up to t_n = t u_g / d_p."""
     import numpy as np
     import torch
     import synth
-    w = synth.light_box(d_p, pi_p, ga=ga, cv=cv, compensate=compensate)
+    w = synth.light_box(d_p, pi_p, ga=ga, cv=cv, compensate=compensate, vm_scheme=vm_scheme)
     steps = int(round(t_n * w["t_g"]))
     tag = w["name"]
     sim = pkg.Sim(w["config"], w["spheres"], storage=storage, history=steps)
@@ -284,6 +284,23 @@ def validate_stability(pkg, diameters=(10, 15, 20, 30), storage="f64", bisection
         vm_ok = stable(lo, cv=1.0)
         out[d] = {"paper": ref, "pi_min_bracket": [round(lo, 5), round(hi, 5)], "vm_mem_stable_at_lo": vm_ok,
                   "runs": runs}
+    return out
+
+
+def validate_extrapolation(pkg, d_p=40, storage="f64", schemes=(1, 2), densities=(0.1, 1.1)):
+    """VM-MEM (C_v = 1) with the acceleration from three velocities
+    (schemes 1 and 2) in the Table 2 cases, against MEM."""
+    out = {}
+    for pi_p in densities:
+        ga = PAPER_TABLE2[pi_p]["ga"]
+        mem = run_light_sphere(pkg, d_p, pi_p, ga=ga, cv=0.0, storage=storage)
+        for sc in schemes:
+            lag = run_light_sphere(pkg, d_p, pi_p, ga=ga, cv=1.0, storage=storage, vm_scheme=sc)
+            r = {"status_mem": mem["status"], "status_vm": lag["status"], "steps_vm": lag["steps"]}
+            if mem["status"] == lag["status"] == "stable":
+                r.update(_errors(lag["uz_n"], mem["uz_n"], 100))
+                r["re_p_vm"] = float(abs(lag["uz_n"][-1]) * 0.01 * d_p / lag["nu"])
+            out["%g scheme %d" % (pi_p, sc)] = r
     return out
 
 
@@ -462,9 +479,12 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run the plain copy used to scale HBM byte counters")
     ap.add_argument("--validate", default="",
-                    help="only run validation workloads of Sec. 3: any of stability,translation,rotation")
+                    help="only run validation workloads of Sec. 3: any of stability,translation,rotation,"
+                         "extrapolation")
     ap.add_argument("--validate-diameters", default="10,15,20,30",
                     help="sphere diameters of the stability bracket (Table 1)")
+    ap.add_argument("--validate-schemes", default="1,2", help="extrapolation: virtual-force schemes to run")
+    ap.add_argument("--validate-densities", default="0.1,1.1", help="extrapolation: density ratios to run")
     ap.add_argument("--validate-compensated", action="store_true",
                     help="translation: also run MEM with a fluid force that cancels the net weight")
     args = ap.parse_args()
@@ -484,7 +504,10 @@ def main():
         runs = {"stability": lambda: validate_stability(
                     pkg, tuple(int(v) for v in args.validate_diameters.split(","))),
                 "translation": lambda: validate_translation(pkg, compensated=args.validate_compensated),
-                "rotation": lambda: validate_rotation(pkg)}
+                "rotation": lambda: validate_rotation(pkg),
+                "extrapolation": lambda: validate_extrapolation(
+                    pkg, schemes=tuple(int(v) for v in args.validate_schemes.split(",")),
+                    densities=tuple(float(v) for v in args.validate_densities.split(",")))}
         for name in args.validate.split(","):
             log(f"validation: {name}")
             print(json.dumps({"validation": name, "result": runs[name]()}, default=str), flush=True)

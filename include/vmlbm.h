@@ -95,6 +95,14 @@ typedef struct {
   int fixed;                  /* 0: free; 1: held in place, surface velocity
                                  0; 2: position held, rotation free (the
                                  rotation test of Sec. 3.4.2) */
+  int vm_scheme;              /* acceleration inside the virtual force and
+                                 torque (Sec. 3.3): 0 the previous step's;
+                                 1 / 2 the derivative of the quadratic
+                                 through the three most recent velocities
+                                 (the Lagrange alternative after Schwarz et
+                                 al.) at the new time level / at the newest
+                                 velocity; the previous step's until three
+                                 velocities are known */
 } vmlbm_sphere;
 
 /* Create a context from a configuration (copied).  *out receives it. */

@@ -214,7 +214,7 @@ struct Sph {
   double x[3], u[3], w[3];
   double r, rho, cv, cvw;
   int fixed;                    // 0 free, 1 held (u = w = 0), 2 position held, rotation free
-  int scheme;                   // virtual-mass acceleration: 0 previous step's, 1 Lagrange extrapolation
+  int scheme;                   // virtual-force acceleration: 0 previous step's, 1 and 2 from three velocities
   double uh[2][3], wh[2][3];    // the two velocities before u, w (newest first)
   int nvel;                     // how many of u, uh[0], uh[1] are known (1..3)
   double a[3], b[3];            // accelerations of the previous step
@@ -249,11 +249,13 @@ inline double link_delta(const double d[3], const int c[3], double r) {
 // A sphere with fixed == 2 (the rotation test of Sec. 3.4.2: position held,
 // rotation free) integrates only the angular part.
 // The acceleration inside the virtual force is the previous step's (Sec. 3.3)
-// or, with scheme 1, the alternative the paper attributes to Schwarz et al.:
-// reading, the derivative at the new time level of the quadratic through the
-// three most recent velocities u_{n-1}, u_{n-2}, u_{n-3} (unit steps),
-// 5/2 u_{n-1} - 4 u_{n-2} + 3/2 u_{n-3}; the previous step's acceleration
-// stands in until three velocities are known.
+// or the alternative the paper attributes to Schwarz et al., the derivative
+// of the quadratic through the three most recent velocities u_{n-1},
+// u_{n-2}, u_{n-3} (unit steps).  The paper leaves open where it is taken:
+// scheme 1 reads it at the new time level, 5/2 u_{n-1} - 4 u_{n-2}
+// + 3/2 u_{n-3}; scheme 2 at the newest velocity, 3/2 u_{n-1} - 2 u_{n-2}
+// + 1/2 u_{n-3}.  The previous step's acceleration stands in until three
+// velocities are known.
 // ---------------------------------------------------------------------------
 inline void update_particle(Sph& s, const double g[3], const int n[3], const int periodic[3]) {
   double Fav[3], Tav[3];
@@ -266,12 +268,14 @@ inline void update_particle(Sph& s, const double g[3], const int n[3], const int
   double m = (s.rho + s.cv) * V;                           // virtually increased mass
   double I = 0.4 * (s.rho + s.cvw) * V * s.r * s.r;        // and moment of inertia
   double an[3], bn[3];
-  const bool lagrange = s.scheme == 1 && s.nvel >= 3;
+  const bool lagrange = s.scheme != 0 && s.nvel >= 3;
+  // weights of u_{n-1}, u_{n-2}, u_{n-3}
+  const double c0 = s.scheme == 1 ? 2.5 : 1.5, c1 = s.scheme == 1 ? -4.0 : -2.0, c2 = s.scheme == 1 ? 1.5 : 0.5;
   for (int a = 0; a < 3; ++a) {
     double a_est = s.a[a], b_est = s.b[a];
     if (lagrange) {
-      a_est = 2.5 * s.u[a] - 4.0 * s.uh[0][a] + 1.5 * s.uh[1][a];
-      b_est = 2.5 * s.w[a] - 4.0 * s.wh[0][a] + 1.5 * s.wh[1][a];
+      a_est = c0 * s.u[a] + c1 * s.uh[0][a] + c2 * s.uh[1][a];
+      b_est = c0 * s.w[a] + c1 * s.wh[0][a] + c2 * s.wh[1][a];
     }
     double Fg = (s.rho - 1.0) * g[a] * V;                  // gravity + buoyancy
     double Fv = s.cv * V * a_est;                          // virtual force, m_v a_{t-1}

@@ -442,7 +442,7 @@ int ora_add_sphere(void* h, const ora_sphere* s) {
   p.r = s->radius; p.rho = s->density_ratio; p.cv = s->cv; p.cvw = s->cv_omega; p.fixed = s->fixed;
   p.scheme = s->vm_scheme;
   p.nvel = 1;
-  if (p.fixed < 0 || p.fixed > 2 || p.scheme < 0 || p.scheme > 1) return -1;
+  if (p.fixed < 0 || p.fixed > 2 || p.scheme < 0 || p.scheme > 2) return -1;
   for (int a = 0; a < 3; ++a) {
     if (p.fixed) p.u[a] = 0.0;
     if (p.fixed == 1) p.w[a] = 0.0;

@@ -38,8 +38,9 @@ typedef struct {
   double x[3], u[3], w[3];
   double radius, density_ratio, cv, cv_omega;
   int fixed;                /* 0 free, 1 held (u = w = 0), 2 position held, rotation free */
-  int vm_scheme;            /* acceleration in the virtual force: 0 previous step's (Sec. 3.3),
-                               1 Lagrange extrapolation from three velocities */
+  int vm_scheme;            /* acceleration in the virtual force: 0 previous step's (Sec. 3.3);
+                               derivative of the quadratic through three velocities at the new
+                               time level (1) or at the newest velocity (2) */
 } ora_sphere;
 
 /* lattice tables in the oracle's order */

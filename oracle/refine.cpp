@@ -649,7 +649,7 @@ int orf_add_sphere(void* h, const orf_sphere* s) {
   p.r = s->radius; p.rho = s->density_ratio; p.cv = s->cv; p.cvw = s->cv_omega; p.fixed = s->fixed;
   p.scheme = s->vm_scheme;
   p.nvel = 1;
-  if (p.scheme < 0 || p.scheme > 1) return -1;
+  if (p.scheme < 0 || p.scheme > 2) return -1;
   R->sph.push_back(p);
   return (int)R->sph.size() - 1;
 }

@@ -50,7 +50,8 @@ class Config(ctypes.Structure):
 class Sphere(ctypes.Structure):
     _fields_ = [("x", ctypes.c_double * 3), ("u", ctypes.c_double * 3), ("w", ctypes.c_double * 3),
                 ("radius", ctypes.c_double), ("density_ratio", ctypes.c_double),
-                ("cv", ctypes.c_double), ("cv_omega", ctypes.c_double), ("fixed", ctypes.c_int)]
+                ("cv", ctypes.c_double), ("cv_omega", ctypes.c_double), ("fixed", ctypes.c_int),
+                ("vm_scheme", ctypes.c_int)]
 
 
 _lib = None
@@ -141,6 +142,7 @@ def make_sphere(s):
     o.cv = s["cv"]
     o.cv_omega = s["cv_omega"]
     o.fixed = int(s["fixed"])
+    o.vm_scheme = int(s.get("vm_scheme", 0))
     return o
 
 

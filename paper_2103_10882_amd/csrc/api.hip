@@ -239,7 +239,7 @@ int vmlbm_add_sphere(vmlbm_ctx* c, const vmlbm_sphere* s, int* id) {
   if (!c || !s) return VMLBM_EINVAL;
   if (c->ws) return fail(c, VMLBM_ESTATE, "spheres must be added before the workspace is bound");
   if (!(s->radius > 0.0) || !(s->density_ratio > 0.0) || s->cv < 0.0 || s->cv_omega < 0.0 || s->fixed < 0 ||
-      s->fixed > 2)
+      s->fixed > 2 || s->vm_scheme < 0 || s->vm_scheme > 2)
     return fail(c, VMLBM_EINVAL, "bad sphere parameters");
   if (c->spheres.size() >= 65535) return fail(c, VMLBM_ERANGE, "too many spheres");
   const int box = (int)std::ceil(2.0 * s->radius) + 8;
@@ -322,6 +322,7 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
     }
     P.r = s.radius; P.rho = s.density_ratio; P.cv = s.cv; P.cvw = s.cv_omega;
     P.fixed = s.fixed; P.have_prev = 0;
+    P.scheme = s.vm_scheme; P.nvel = 1;
     for (int a = 0; a < 3; ++a) {
       int lo = (int)std::floor(s.x[a] - s.radius) - 3;
       if (c->cfg.periodic[a]) lo = ((lo % c->cfg.n[a]) + c->cfg.n[a]) % c->cfg.n[a];

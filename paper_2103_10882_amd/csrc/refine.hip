@@ -1370,6 +1370,7 @@ int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
     }
     P.r = s.radius; P.rho = s.density_ratio; P.cv = s.cv; P.cvw = s.cv_omega;
     P.fixed = s.fixed;
+    P.scheme = s.vm_scheme; P.nvel = 1;
     for (int a = 0; a < 3; ++a) {
       const int n = f.lv[f.L].n[a];
       int lo = (int)std::floor(s.x[a] - s.radius) - 3;

@@ -1,7 +1,7 @@
 // Uniform-grid kernels: fused pull stream-collide sweep with the moving-wall
-// CLI boundary and momentum-exchange link forces on particle links, the
-// per-particle force/torque reduction fused with the virtual-mass particle
-// update, refill of uncovered cells, and re-mapping.
+// CLI boundary and momentum-exchange link forces on particle links, refill
+// of uncovered cells, and re-mapping.  The per-particle reduction and update
+// are in motion.hip.
 //
 // Layout: populations SoA [q][z][y][x] as deviations in storage type S, two
 // buffers (pull from src, write dst); flags uint8 [z][y][x]; owner uint16
@@ -122,117 +122,6 @@ __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, ui
   if (c >= p.N) return;
   const int x = c % p.nx, y = (c / p.nx) % p.ny, z = c / ((uint32_t)p.nx * p.ny);
   map_cell<UAddr>(x, y, z, c, flags, owner, parts, np, p, uaddr(p), status);
-}
-
-// ---------------------------------------------------------------------------
-// per-particle force/torque reduction (fixed order, FP64) fused with the
-// two-step average and the virtual-mass velocity-Verlet update (Sec. 2.2,
-// Sec. 3.3, Algorithm 1).  One workgroup per particle.
-// ---------------------------------------------------------------------------
-__device__ void particle_update(DevParticle& P, const double (&F)[3], const double (&T)[3], int* __restrict__ status,
-                                const SweepParams& p, const UpdateParams& u) {
-#pragma clang fp contract(off)
-  bool finite = true;
-  for (int a = 0; a < 3; ++a) finite = finite && isfinite(F[a]) && isfinite(T[a]);
-  if (!finite) status[kStatusUnstable] = 2;
-  for (int a = 0; a < 3; ++a) { P.F[a] = F[a]; P.T[a] = T[a]; }
-  double xold[3] = {P.x[0], P.x[1], P.x[2]};
-  if (P.fixed == 2) {
-    // position held, rotation free (the rotation test of Sec. 3.4.2)
-    const double PI = 3.14159265358979323846;
-    const double V = 4.0 / 3.0 * PI * P.r * P.r * P.r;
-    const double I = 0.4 * (P.rho + P.cvw) * V * P.r * P.r;
-    for (int a = 0; a < 3; ++a) {
-      const double Tav = P.have_prev ? 0.5 * (T[a] + P.Tprev[a]) : T[a];
-      const double bn = (Tav + 0.4 * P.cvw * V * P.r * P.r * P.b[a]) / I;
-      P.w[a] = P.w[a] + 0.5 * (P.b[a] + bn);
-      P.b[a] = bn;
-    }
-  } else if (!P.fixed) {
-    const double PI = 3.14159265358979323846;
-    const double V = 4.0 / 3.0 * PI * P.r * P.r * P.r;
-    const double m = (P.rho + P.cv) * V;
-    const double I = 0.4 * (P.rho + P.cvw) * V * P.r * P.r;
-    for (int a = 0; a < 3; ++a) {
-      const double Fav = P.have_prev ? 0.5 * (F[a] + P.Fprev[a]) : F[a];
-      const double Tav = P.have_prev ? 0.5 * (T[a] + P.Tprev[a]) : T[a];
-      const double Fg = (P.rho - 1.0) * u.g[a] * V;
-      const double an = (Fav + Fg + P.cv * V * P.a[a]) / m;
-      const double bn = (Tav + 0.4 * P.cvw * V * P.r * P.r * P.b[a]) / I;
-      P.u[a] = P.u[a] + 0.5 * (P.a[a] + an);
-      P.w[a] = P.w[a] + 0.5 * (P.b[a] + bn);
-      double xn = P.x[a] + P.u[a] + 0.5 * an;
-      if (p.per[a]) {
-        const double na = a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
-        if (xn < 0.0) xn += na;
-        else if (xn >= na) xn -= na;
-      }
-      P.x[a] = xn;
-      P.a[a] = an;
-      P.b[a] = bn;
-    }
-    double speed = P.u[0] * P.u[0] + P.u[1] * P.u[1] + P.u[2] * P.u[2];
-    if (!(speed < 0.25)) {
-      // blown up (the host reports it at the next sync): the sphere keeps
-      // its last position, so boxes and mapping stay finite and in range
-      status[kStatusUnstable] = 3;
-      for (int a = 0; a < 3; ++a) P.x[a] = xold[a];
-    }
-    // new boxes: force slots around the new position, re-mapping region
-    // covering old and new position
-    for (int a = 0; a < 3; ++a) {
-      const int na = a == 0 ? p.nx : (a == 1 ? p.ny : p.nz);
-      int lo_new = (int)floor(P.x[a] - P.r) - 3;
-      int lo_old = (int)floor(xold[a] - P.r) - 3;
-      double dx = P.x[a] - xold[a];
-      if (p.per[a]) {
-        if (dx > 0.5 * na) dx -= na;
-        else if (dx < -0.5 * na) dx += na;
-      }
-      if (!(fabs(dx) < 0.5)) status[kStatusRange] = 3;
-      int lo = dx >= 0.0 ? lo_old : lo_new;
-      if (p.per[a]) { lo = ((lo % na) + na) % na; lo_new = ((lo_new % na) + na) % na; }
-      P.remap_lo[a] = lo;
-      P.box_lo[a] = lo_new;
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__ parts, double* __restrict__ slots,
-                                                       double* __restrict__ hist, int* __restrict__ status,
-                                                       SweepParams p, UpdateParams u) {
-  const int pi = blockIdx.x;
-  __shared__ double red[6][256];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  double* s = slots + (size_t)pi * p.slot_stride;
-  const int nslots = (int)(p.slot_stride / 6);
-  for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) acc[j] += s[(size_t)k * 6 + j];
-  }
-#pragma unroll
-  for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
-#pragma unroll
-      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
-    __syncthreads();
-  }
-  if (threadIdx.x != 0) return;
-  DevParticle& P = parts[pi];
-  double F[3] = {red[0][0], red[1][0], red[2][0]}, T[3] = {red[3][0], red[4][0], red[5][0]};
-  particle_update(P, F, T, status, p, u);
-  for (int a = 0; a < 3; ++a) { P.Fprev[a] = F[a]; P.Tprev[a] = T[a]; }
-  P.have_prev = 1;
-  double* h = hist + ((size_t)(u.step % u.hist_len) * u.np + pi) * kHistWords;
-  for (int a = 0; a < 3; ++a) {
-    h[a] = F[a];
-    h[3 + a] = T[a];
-    h[6 + a] = P.x[a];
-    h[9 + a] = P.u[a];
-    h[12 + a] = P.w[a];
-  }
 }
 
 // fixed-order partial sums over fluid cells: count, sum of deviations and
@@ -359,12 +248,6 @@ hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, con
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_link_lists<UAddr>(flags, owner, parts, np, p, uaddr(p), ll.count, ll.links, ll.len, st);
-}
-
-hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
-                                const SweepParams& p, const UpdateParams& u, hipStream_t st) {
-  k_reduce_update<<<dim3(np), dim3(256), 0, st>>>(parts, slots, hist, status, p, u);
-  return hipGetLastError();
 }
 
 template hipError_t launch_interior<double>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,

@@ -66,7 +66,8 @@ def sphere(x, radius, density_ratio=1.0, cv=0.0, cv_omega=None, fixed=True,
            u=(0.0, 0.0, 0.0), w=(0.0, 0.0, 0.0), vm_scheme=0):
     """fixed: True held in place, False free, 2 position held with free
     rotation.  vm_scheme: acceleration inside the virtual force, 0 the
-    previous step's, 1 Lagrange extrapolation from three velocities."""
+    previous step's, 1 / 2 the derivative of the quadratic through the three
+    most recent velocities at the new time level / at the newest velocity."""
     return {
         "x": tuple(float(v) for v in x),
         "u": tuple(float(v) for v in u),
@@ -205,7 +206,7 @@ def refined(coarse=(128, 128, 512), levels=3, block=16, radius=16.0, ga=250.0,
     }
 
 
-def light_box(d_p, density_ratio, ga=100.0, cv=0.0, bulk_factor=100.0, compensate=False):
+def light_box(d_p, density_ratio, ga=100.0, cv=0.0, bulk_factor=100.0, compensate=False, vm_scheme=0):
     """Rising (or settling) sphere in a periodic box (Sec. 3.1, Table 1 and
     Sec. 3.4.1, Table 2).  d_p a multiple of 5 keeps the box whole.  The
     fluid is unforced, so the box gains the sphere's net weight as momentum
@@ -220,10 +221,10 @@ def light_box(d_p, density_ratio, ga=100.0, cv=0.0, bulk_factor=100.0, compensat
     cfg = base_config(n, omega=omega, body_force=(0.0, 0.0, fz), gravity=(0.0, 0.0, -g))
     cfg["bulk_factor"] = float(bulk_factor)
     return {
-        "name": "lightbox_d%d_pi%g_ga%g_cv%g" % (d_p, density_ratio, ga, cv),
+        "name": "lightbox_d%d_pi%g_ga%g_cv%g_s%d" % (d_p, density_ratio, ga, cv, vm_scheme),
         "config": cfg,
         "spheres": [sphere((3.2 * d_p, 3.2 * d_p, 0.6 * d_p), r, density_ratio=density_ratio, cv=cv,
-                           fixed=False)],
+                           fixed=False, vm_scheme=vm_scheme)],
         "u0": None,
         "nu": nu,
         "t_g": d_p / U_G,

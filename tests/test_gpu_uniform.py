@@ -398,3 +398,21 @@ def test_hold_then_rotate(env):
     say(f"  w_y {wg0[1]:.3e}, population rel err {rel:.2e}")
     assert rel <= 1e-12
     sim.close()
+
+
+@pytest.mark.parametrize("scheme,rho_p", [(0, 0.2), (1, 0.5), (1, 1.5), (2, 0.2)])
+def test_sphere_vm_schemes(env, scheme, rho_p):
+    """Rising or settling sphere (C_v = 1) in a periodic box under gravity,
+    with each acceleration inside the virtual force (Sec. 3.3): the previous
+    step's, or the derivative of the quadratic through three velocities at
+    the new time level (1) or at the newest velocity (2).
+    F/T, mapping and particle state every step, populations at the end,
+    against the oracle.  (The extrapolation makes the lateral motion of the
+    density-0.5 sphere grow, and a density-0.2 sphere blows up within 65
+    steps, so its parity case uses 0.5 and 1.5.)"""
+    pkg, oracle = env
+    n = (24, 26, 40)
+    cfg = synth.base_config(n, omega=1.7, gravity=(0.0, 0.0, -4e-5))
+    s = synth.sphere((11.7, 13.2, 9.6), 4.4, density_ratio=rho_p, cv=1.0, fixed=False, vm_scheme=scheme,
+                     u=(0.002, -0.001, 0.0))
+    run_parity(pkg, oracle, cfg, [s], 80, 4.4, f"sphere24x26x40 scheme {scheme} density {rho_p} f64")

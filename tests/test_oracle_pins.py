@@ -346,9 +346,11 @@ def test_vm_acceleration_schemes_linear_force(ora, rho_p, cv):
     is A_n = (F_n-bar + F_g) / (pi_p V), with F_n-bar the two-step mean.  With
     the previous step's acceleration inside the virtual force (Sec. 3.3),
     a_n settles at a constant lag A_n - r s / (1 - r), where s is the slope
-    of A and r = C_v / (pi_p + C_v).  The quadratic extrapolation from three
-    velocities is exact for velocities quadratic in time, so a_n settles on
-    A_n itself.  Both schemes coincide until three velocities are known."""
+    of A and r = C_v / (pi_p + C_v).  The derivative of the quadratic through
+    three velocities is exact for velocities quadratic in time: taken at the
+    new time level (scheme 1) a_n settles on A_n itself, taken at the newest
+    velocity (scheme 2) it estimates a_{n-1} and keeps scheme 0's lag.  All
+    schemes coincide until three velocities are known."""
     r_p = 3.0
     V = 4.0 / 3.0 * np.pi * r_p ** 3
     F = np.array([1e-4, -2e-4, 5e-5])
@@ -361,16 +363,19 @@ def test_vm_acceleration_schemes_linear_force(ora, rho_p, cv):
     rr = cv / (rho_p + cv)
     slope = dF / (rho_p * V)
     out = {}
-    for scheme in (0, 1):
+    for scheme in (0, 1, 2):
         s = synth.sphere((0.0, 0.0, 0.0), r_p, density_ratio=rho_p, cv=cv, fixed=False, vm_scheme=scheme)
         out[scheme] = ora.vm_trajectory(s, F, T, g, n, dF=dF)
     scale = np.abs(A[-1]).max()
-    assert np.abs(out[0][-1, 9:12] - (A[-1] - rr * slope / (1 - rr))).max() < 1e-9 * scale
+    lagged = A[-1] - rr * slope / (1 - rr)
+    assert np.abs(out[0][-1, 9:12] - lagged).max() < 1e-9 * scale
     assert np.abs(out[1][-1, 9:12] - A[-1]).max() < 1e-9 * scale
+    assert np.abs(out[2][-1, 9:12] - lagged).max() < 1e-9 * scale
     assert np.abs(out[0][-1, 9:12] - A[-1]).max() > 1e-6 * scale          # the lag is there
-    assert (out[0][:2] == out[1][:2]).all() and (out[0][2] != out[1][2]).any()
+    for scheme in (1, 2):
+        assert (out[0][:2] == out[scheme][:2]).all() and (out[0][2] != out[scheme][2]).any()
     I_p = 0.4 * rho_p * V * r_p ** 2
-    for scheme in (0, 1):                                                  # constant torque: beta -> T / I_p
+    for scheme in (0, 1, 2):                                               # constant torque: beta -> T / I_p
         assert np.abs(out[scheme][-1, 12:15] - T / I_p).max() < 1e-10 * np.abs(T / I_p).max()
 
 
