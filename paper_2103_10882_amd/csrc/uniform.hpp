@@ -5,6 +5,7 @@
 #include <cstdint>
 
 #include "common.hpp"
+#include "particle_state.hpp"
 
 namespace vm {
 
