@@ -28,6 +28,26 @@ int fail(vmlbm_ctx* c, int code, const char* fmt, ...) {
 
 size_t storage_bytes(int storage) { return storage == VMLBM_F64 ? 8 : storage == VMLBM_F32 ? 4 : 2; }
 
+// IEEE binary16 bits of v, rounded once to nearest with ties to even
+// (subnormals kept, overflow to infinity); the scalings by powers of two are
+// exact, so std::nearbyint in the default rounding mode does the rounding
+uint16_t half_bits_rne(double v) {
+  const uint16_t sgn = std::signbit(v) ? 0x8000u : 0u;
+  const double a = std::fabs(v);
+  if (std::isnan(v)) return 0x7e00u;
+  if (a < std::ldexp(1.0, -14)) {                       // subnormal or zero: multiples of 2^-24
+    const double k = std::nearbyint(std::ldexp(a, 24));  // 1024 rounds up to the smallest normal
+    return (uint16_t)(sgn | (uint16_t)k);
+  }
+  int e = 0;
+  std::frexp(a, &e);                                    // a = m 2^e, m in [0.5, 1)
+  int E = e - 1;                                        // a in [2^E, 2^(E+1))
+  double r = std::nearbyint(std::ldexp(a, 10 - E));     // in [1024, 2048]
+  if (r == 2048.0) { r = 1024.0; E += 1; }
+  if (E > 15) return (uint16_t)(sgn | 0x7c00u);
+  return (uint16_t)(sgn | (uint16_t)((E + 15) << 10) | (uint16_t)(r - 1024.0));
+}
+
 }  // namespace vm
 
 namespace {
@@ -72,7 +92,7 @@ double dev_to_double(const void* buf, int storage, size_t i) {
 void double_to_dev(void* buf, int storage, size_t i, double v) {
   if (storage == VMLBM_F64) ((double*)buf)[i] = v;
   else if (storage == VMLBM_F32) ((float*)buf)[i] = (float)v;
-  else ((__half*)buf)[i] = __float2half_rn((float)v);
+  else ((uint16_t*)buf)[i] = half_bits_rne(v);
 }
 
 int check_ready(vmlbm_ctx* c) {

@@ -97,6 +97,8 @@ struct SweepParams;
 SweepParams sweep_params(const vmlbm_ctx* c);
 int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1);
 size_t storage_bytes(int storage);
+// host conversion to IEEE binary16 bits, round to nearest even (api.hip)
+uint16_t half_bits_rne(double v);
 
 int uniform_step(vmlbm_ctx* c, int nsteps);
 

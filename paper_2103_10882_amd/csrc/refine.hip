@@ -1492,7 +1492,7 @@ int refine_write_populations(vmlbm_ctx* c, int level, const double* in) {
       const double d = in[q * cells + i] - w_of(q);
       if (c->cfg.storage == VMLBM_F64) ((double*)raw.data())[i] = d;
       else if (c->cfg.storage == VMLBM_F32) ((float*)raw.data())[i] = (float)d;
-      else ((__half*)raw.data())[i] = __float2half_rn((float)d);
+      else ((uint16_t*)raw.data())[i] = half_bits_rne(d);
     }
     HIP_TRY(c, hipMemcpy(c->ws + V.off_pdf[V.cur] + ((size_t)q * V.cap * kBlockCells) * S, raw.data(), cells * S,
                          hipMemcpyHostToDevice));

@@ -69,8 +69,14 @@ def compare_levels(sim, ref, levels):
 REGIONS = [((8, 4, 6), (20, 14, 22), 1), ((12, 16, 16), (18, 22, 22), 2), ((0, 24, 0), (4, 28, 6), 1)]
 
 
-@pytest.mark.parametrize("storage,tol,lb", [("f64", 1e-12, 1.0), ("f32", 2e-6, 1.0), ("f64", 1e-12, 100.0)])
+@pytest.mark.parametrize("storage,tol,lb", [("f64", 1e-12, 1.0), ("f32", 2e-6, 1.0), ("f16", 2e-4, 1.0),
+                                            ("f64", 1e-12, 100.0)])
 def test_static_three_levels(env, storage, tol, lb):
+    """Three static levels from a perturbed equilibrium: every level's
+    interior populations against the FP64 oracle after each coarse step.
+    FP16 stores deviations of about 1e-3 with a 2^-11 relative rounding, a
+    few 1e-7 of the largest population per store; 2e-4 leaves room for the
+    stores of three coarse steps (12 on the finest level)."""
     pkg, oracle = env
     n0 = (32, 32, 32)
     c = cfg_of(n0, 3, omega=1.7, F=(1e-5, -2e-5, 3e-5))

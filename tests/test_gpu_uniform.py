@@ -211,7 +211,10 @@ def test_reduced_storage_one_step(env, case, lb):
     of amplitude 0.02, so neighbouring cells differ by far more than a
     storage ulp): every cell without links equals the oracle's collision of
     its pulled populations to within one storage ulp of the deviation plus
-    FP32 round-off, at the periodic row ends and next to flagged cells."""
+    FP32 round-off, at the periodic row ends and next to flagged cells.  The
+    state is the oracle's after two steps with its deviations rounded here
+    to the storage format (FP32, then FP16); the rounded state is what both
+    sides start from, and the library stores it exactly."""
     pkg, ora = env
     c, w, _ = ora.lattice()
     if case == "box130":
@@ -225,13 +228,18 @@ def test_reduced_storage_one_step(env, case, lb):
     cfg["bulk_factor"] = lb
     u0 = synth.velocity_perturbation(n, seed=11, amplitude=0.02)
     F = np.array(cfg["body_force"])
+    ref = ora.Uniform(cfg, sph)
+    ref.init(1.0, u0)
+    ref.step(2)
+    f_ref = ref.post_collision()
     for storage, ulp in (("f16", 2.0 ** -10), ("f32", 2.0 ** -23)):
         say(f"case {case} one step {storage}")
+        dev32 = (f_ref - w[:, None, None, None]).astype(np.float32)
+        dev = dev32.astype(np.float16) if storage == "f16" else dev32
+        f0 = w[:, None, None, None] + dev.astype(np.float64)
         sim = pkg.Sim(cfg, sph, storage=storage)
         sim.init(1.0, u0)
-        sim.step(2)
-        sim.sync()
-        f0 = sim.populations()
+        sim.write_populations(f0)
         sim.step(1)
         sim.sync()
         f1 = sim.populations()
@@ -416,3 +424,31 @@ def test_sphere_vm_schemes(env, scheme, rho_p):
     s = synth.sphere((11.7, 13.2, 9.6), 4.4, density_ratio=rho_p, cv=1.0, fixed=False, vm_scheme=scheme,
                      u=(0.002, -0.001, 0.0))
     run_parity(pkg, oracle, cfg, [s], 80, 4.4, f"sphere24x26x40 scheme {scheme} density {rho_p} f64")
+
+
+def test_fp16_write_rounds_to_nearest_even(env):
+    """Host conversion of the write call for FP16 storage: one rounding of
+    the double deviation to nearest, ties to even, subnormals kept; checked
+    against numpy's binary16 conversion on random values over 12 decades
+    and on exact midpoints between neighbouring FP16 values."""
+    pkg, ora = env
+    _, w, _ = ora.lattice()
+    n = (16, 16, 16)
+    cfg = synth.base_config(n, omega=1.6)
+    rng = np.random.default_rng(21)
+    N = n[0] * n[1] * n[2]
+    d = rng.choice([-1.0, 1.0], size=(19, N)) * 10.0 ** rng.uniform(-12, -0.5, size=(19, N))
+    lo = np.float16(d[:, : N // 2]).astype(np.float64)        # midpoints of FP16 neighbours
+    hi = np.nextafter(np.float16(d[:, : N // 2]), np.float16(np.inf)).astype(np.float64)
+    d[:, : N // 2] = 0.5 * (lo + hi)
+    f = w[:, None] + d
+    seen = f - w[:, None]                                       # what the library converts
+    ties = (seen[:, : N // 2] == d[:, : N // 2]).sum()          # midpoints that survive w + d - w
+    assert ties > 20000
+    sim = pkg.Sim(cfg, [], storage="f16")
+    sim.init()
+    sim.write_populations(f.reshape(19, n[2], n[1], n[0]))
+    back = sim.populations().reshape(19, N)
+    sim.close()
+    want = w[:, None] + seen.astype(np.float16).astype(np.float64)
+    assert np.array_equal(back, want)
