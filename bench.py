@@ -377,6 +377,84 @@ def validate_rotation(pkg, d_p=40, storage="f64"):
     return out
 
 
+def run_amr(pkg, refined, t_n, storage="f64", curl_threshold=0.0, check_every=4, ga=300.0):
+    """The rising sphere of Sec. 4.3 (d_p = 25, density ratio 0.5, MEM) on
+    the uniform finest grid or on 3 refined levels, up to t_n."""
+    import numpy as np
+    import torch
+    import synth
+    w = synth.amr_box(refined=refined, curl_threshold=curl_threshold, ga=ga)
+    steps = int(round(t_n * w["t_g"]))                      # finest-level steps
+    per = 4 if refined else 1                               # finest steps per call unit
+    tag = w["name"] + (" curl" if curl_threshold > 0 else "")
+    sim = pkg.Sim(w["config"], w["spheres"], storage=storage, history=steps, check_every=check_every)
+    sim.init()
+    sim.sync()
+    cu0, _ = sim.stats()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    done, status = 0, "stable"
+    chunk = 2000
+    while done < steps:
+        k = min(chunk, steps - done)
+        sim.step(k // per)
+        try:
+            sim.sync()
+        except pkg.VmlbmError as e:
+            status = "failed: %s" % e
+            log(f"  {tag}: {status}")
+            break
+        done += k
+        x, u, _ = sim.particle(0)
+        extra = (" blocks " + str([int(sim.level_blocks(l).shape[0]) for l in range(3)])) if refined else ""
+        log(f"  {tag}: step {done}/{steps}, z = {x[2]:.2f}, u = {u}{extra}")
+    wall = time.time() - t0
+    cu1, _ = sim.stats()
+    h = sim.history(0, done) if done else np.zeros((0, 15))
+    out = {"status": status, "steps": done, "seconds": wall, "cell_updates": cu1 - cu0,
+           "refinements": sim.refinements() if refined else 0, "hist": h, "d_p": 25.0,
+           "x0": np.array(w["spheres"][0]["x"])}
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def validate_amr(pkg, t_n=12.0, storage="f64", curl_threshold=0.0, ga=300.0):
+    """Sec. 4.3: trajectory on 3 refined levels against the uniform finest
+    grid; u_z,n compared every 100 finest steps from t_n = 0.5 on."""
+    import numpy as np
+    import synth
+    uni = run_amr(pkg, False, t_n, storage, ga=ga)
+    ref = run_amr(pkg, True, t_n, storage, curl_threshold=curl_threshold, ga=ga)
+    out = {"t_n": t_n, "ga": ga, "storage": storage, "curl_threshold": curl_threshold,
+           "status": [uni["status"], ref["status"]]}
+    m = min(len(uni["hist"]), len(ref["hist"]))
+    out["steps"] = [uni["steps"], ref["steps"]]
+    if m < 400:
+        return out
+    d = uni["d_p"]
+    ug = synth.U_G
+    s = slice(int(0.5 * d / ug) - 1, m, 100)
+    uu, ur = uni["hist"][s, 11] / ug, ref["hist"][s, 11] / ug
+    lat = {}
+    for k, r in (("uniform", uni), ("refined", ref)):
+        dx = r["hist"][:m, 6:8] - r["x0"][None, :2]
+        lat[k] = float(np.sqrt((dx ** 2).sum(axis=1)).max() / d)
+    out.update({
+        "samples": int(len(uu)),
+        "uz_n_mean_rel_err": float(np.mean(np.abs(ur - uu) / np.abs(uu))),
+        "uz_n_max_abs_diff": float(np.abs(ur - uu).max()),
+        "uz_n_end": [float(uu[-1]), float(ur[-1])],
+        "z_n_end": [float(uni["hist"][m - 1, 8] / d), float(ref["hist"][m - 1, 8] / d)],
+        "max_lateral_displacement_n": [lat["uniform"], lat["refined"]],
+        "cell_updates": [uni["cell_updates"], ref["cell_updates"]],
+        "seconds": [round(uni["seconds"], 1), round(ref["seconds"], 1)],
+        "refinements": ref["refinements"],
+    })
+    return out
+
+
 def sweep_source_hash():
     import hashlib
     h = hashlib.sha256()
@@ -479,11 +557,15 @@ def main():
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run the plain copy used to scale HBM byte counters")
     ap.add_argument("--validate", default="",
-                    help="only run validation workloads of Sec. 3: any of stability,translation,rotation,"
-                         "extrapolation")
+                    help="only run validation workloads of Sec. 3 and 4.3: any of stability,translation,"
+                         "rotation,extrapolation,amr")
     ap.add_argument("--validate-diameters", default="10,15,20,30",
                     help="sphere diameters of the stability bracket (Table 1)")
     ap.add_argument("--validate-schemes", default="1,2", help="extrapolation: virtual-force schemes to run")
+    ap.add_argument("--validate-tn", type=float, default=12.0, help="amr: run length in t_n = t u_g / d_p")
+    ap.add_argument("--validate-curl", type=float, default=0.0, help="amr: curl-sensor threshold (0 = particle only)")
+    ap.add_argument("--validate-ga", type=float, default=150.0, help="amr: Galileo number (the paper's 300 needs "
+                    "more than 25 cells per diameter)")
     ap.add_argument("--validate-densities", default="0.1,1.1", help="extrapolation: density ratios to run")
     ap.add_argument("--validate-compensated", action="store_true",
                     help="translation: also run MEM with a fluid force that cancels the net weight")
@@ -505,6 +587,8 @@ def main():
                     pkg, tuple(int(v) for v in args.validate_diameters.split(","))),
                 "translation": lambda: validate_translation(pkg, compensated=args.validate_compensated),
                 "rotation": lambda: validate_rotation(pkg),
+                "amr": lambda: validate_amr(pkg, t_n=args.validate_tn, curl_threshold=args.validate_curl,
+                                            ga=args.validate_ga),
                 "extrapolation": lambda: validate_extrapolation(
                     pkg, schemes=tuple(int(v) for v in args.validate_schemes.split(",")),
                     densities=tuple(float(v) for v in args.validate_densities.split(",")))}

@@ -26,6 +26,10 @@ Validation workloads of Sec. 3 (MRT with bulk factor 100, the paper's default):
                 (3.2, 3.2, 0.6) d_p released at rest, gravity along -z at a
                 Galileo number (Sec. 3.1 and 3.4.1).  Gravity and buoyancy
                 act on the sphere only; the fluid is unforced.
+* ``amr_box``   refinement validation of Sec. 4.3 at a smaller sphere: periodic
+                (7.68, 7.68, 53.76) d_p box, sphere of diameter d_p released at
+                (3.84, 3.84, 0.6) d_p, Ga 300, density ratio 0.5, plain MEM;
+                either the uniform finest grid or 3 levels of 16^3 blocks.
 * ``rotation_box`` (12.8, 6.4, 4.8) d_p, walls at z = 0 (rest) and z = 4.8 d_p
                 (moving at u_w = 0.1 along x), periodic in x and y, Couette
                 start, sphere of diameter d_p held at the centre (Sec. 3.4.2);
@@ -253,4 +257,35 @@ def rotation_box(d_p, density_ratio, cv=0.0, re_p=110.0, u_w=0.1, bulk_factor=10
         "nu": nu,
         "t_c": d_p / u_p,
         "omega_c": u_p / d_p,
+    }
+
+
+def amr_box(d_p=25, refined=False, ga=300.0, density_ratio=0.5, levels=3, bulk_factor=100.0,
+            curl_threshold=0.0, curl_coarsen=0.2):
+    """Rising sphere of Sec. 4.3 (uniform against adaptively refined grid).
+    The finest grid has (7.68, 7.68, 53.76) d_p cells; d_p = 25 makes that
+    (192, 192, 1344), whole 16^3 blocks of the coarsest of 3 levels.  The
+    refined grid holds the finest level around the sphere (and, with a curl
+    threshold, wherever the flow asks for it)."""
+    scale = 2 ** (levels - 1)
+    n = (int(round(7.68 * d_p)), int(round(7.68 * d_p)), int(round(53.76 * d_p)))
+    _, omega, g = _ga_params(ga, density_ratio, float(d_p))
+    centre = (3.84 * d_p, 3.84 * d_p, 0.6 * d_p)
+    if refined:
+        if any(v % (16 * scale) for v in n):
+            raise ValueError("the finest grid must hold whole coarsest blocks")
+        cfg = base_config(tuple(v // scale for v in n), omega=omega, gravity=(0.0, 0.0, -g))
+        cfg["levels"] = levels
+        cfg["block"] = 16
+        cfg["curl_threshold"] = float(curl_threshold)
+        cfg["curl_coarsen"] = float(curl_coarsen)
+    else:
+        cfg = base_config(n, omega=omega, gravity=(0.0, 0.0, -g))
+    cfg["bulk_factor"] = float(bulk_factor)
+    return {
+        "name": "amr_d%d_%s" % (d_p, "refined" if refined else "uniform"),
+        "config": cfg,
+        "spheres": [sphere(centre, 0.5 * d_p, density_ratio=density_ratio, cv=0.0, fixed=False)],
+        "finest": n,
+        "t_g": d_p / U_G,
     }
