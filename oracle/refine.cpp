@@ -594,7 +594,7 @@ struct RForest {
 extern "C" {
 
 void* orf_create(const orf_config* cfg) {
-  if (!cfg || cfg->levels < 1 || cfg->levels > 4 || cfg->block < 2) return nullptr;
+  if (!cfg || cfg->levels < 1 || cfg->levels > 8 || cfg->block < 2) return nullptr;
   auto* R = new RForest();
   R->cfg = *cfg;
   R->L = cfg->levels - 1;

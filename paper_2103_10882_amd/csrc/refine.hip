@@ -37,6 +37,9 @@ namespace vm {
 namespace {
 
 constexpr uint8_t kIface = 0x10;   // interior cell with a coalescence pull
+// deepest hierarchy: the per-level seeds step by 8 per finest step, and the
+// migration kernel takes per-level tables by value
+constexpr int kMaxLevels = 8;
 
 struct IfaceEntry {
   int slot, local;      // the coarse cell
@@ -870,10 +873,10 @@ struct MigrateArgs {
   int L;
   int nbL[3];
   const int8_t* old_leaf;
-  const void* old_pdf[4];
-  const int* old_slot_of[4];
-  int nb[4][3];
-  uint32_t oldN[4];
+  const void* old_pdf[kMaxLevels];
+  const int* old_slot_of[kMaxLevels];
+  int nb[kMaxLevels][3];
+  uint32_t oldN[kMaxLevels];
   uint32_t seed;
 };
 
@@ -1261,7 +1264,7 @@ int check_layout(vmlbm_ctx* c) {
 int refine_create(vmlbm_ctx* c) {
   const vmlbm_config& g = c->cfg;
   if (g.block != kBlock) return fail(c, VMLBM_EINVAL, "block edge must be %d", kBlock);
-  if (g.levels < 1 || g.levels > 4) return fail(c, VMLBM_EINVAL, "levels must lie in 1..4");
+  if (g.levels < 1 || g.levels > kMaxLevels) return fail(c, VMLBM_EINVAL, "levels must lie in 1..%d", kMaxLevels);
   for (int a = 0; a < 3; ++a) {
     if (!g.periodic[a]) return fail(c, VMLBM_EINVAL, "the refined grid is periodic");
     if (g.n[a] % kBlock) return fail(c, VMLBM_EINVAL, "coarse cells must be a multiple of %d", kBlock);
