@@ -657,7 +657,11 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
 // ghost cells (the band of each ghost block listed in band[band_off[g] ..
 // band_off[g+1]) as local cell indices): stream only; sources not stored at
 // this level give 0.  Cells of a ghost block outside its band are never
-// read by an update of this level's region within the two substeps.
+// read by an update of this level's region within the two substeps.  A band
+// holds a few hundred cells: gridDim.y workgroups share one, so that each
+// thread takes about one cell and the launch is one round of short,
+// latency-bound work.
+constexpr int kBandSplit = 2;
 template <typename S>
 __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src, S* __restrict__ dst,
                                                       const int* __restrict__ list, const int* __restrict__ band_off,
@@ -667,7 +671,7 @@ __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src,
   const int slot = list[blockIdx.x];
   load_neighbours(a, slot, nbs);
   const int b1 = band_off[blockIdx.x + 1];
-  for (int i = band_off[blockIdx.x] + threadIdx.x; i < b1; i += blockDim.x) {
+  for (int i = band_off[blockIdx.x] + blockIdx.y * blockDim.x + threadIdx.x; i < b1; i += gridDim.y * blockDim.x) {
     const int local = band[i];
     const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)local;
@@ -687,7 +691,7 @@ __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S
   const int* e = ex + 5 * blockIdx.x;
   const int gs = e[0], ps = e[1], ox = e[2], oy = e[3], oz = e[4];
   const int b1 = band_off[blockIdx.x + 1];
-  for (int i = band_off[blockIdx.x] + threadIdx.x; i < b1; i += blockDim.x) {
+  for (int i = band_off[blockIdx.x] + blockIdx.y * blockDim.x + threadIdx.x; i < b1; i += gridDim.y * blockDim.x) {
     const int local = band[i];
     const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
     const uint32_t cf = (uint32_t)gs * kBlockCells + (uint32_t)local;
@@ -701,7 +705,7 @@ __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S
 // coalescence cells of level l, kIfaceCells per workgroup: first one thread
 // per (cell, q) gathers the weighted coarse pull and the 1/8-weighted fine
 // ghost children into LDS, then one thread per cell collides and stores.
-constexpr int kIfaceCells = 64;
+constexpr int kIfaceCells = 16;
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __restrict__ dst,
@@ -1044,11 +1048,10 @@ int explode(vmlbm_ctx* c, int l) {
   if (!F.n_ghost) return VMLBM_OK;
   return dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
-    k_explode<S><<<F.n_ghost, 256, 0, c->stream>>>((const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]),
-                                                   (const int*)(c->ws + F.off_explode),
-                                                   (const int*)(c->ws + F.off_band_off),
-                                                   (const uint16_t*)(c->ws + F.off_band),
-                                                   (uint32_t)C.cap * kBlockCells, (uint32_t)F.cap * kBlockCells);
+    k_explode<S><<<dim3(F.n_ghost, kBandSplit), 256, 0, c->stream>>>(
+        (const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]), (const int*)(c->ws + F.off_explode),
+        (const int*)(c->ws + F.off_band_off), (const uint16_t*)(c->ws + F.off_band), (uint32_t)C.cap * kBlockCells,
+        (uint32_t)F.cap * kBlockCells);
     HIP_TRY(c, hipGetLastError());
     return VMLBM_OK;
   });
@@ -1079,9 +1082,9 @@ int sweep_level(vmlbm_ctx* c, int l) {
       HIP_TRY(c, hipGetLastError());
     }
     if (V.n_ghost) {
-      k_ghost_stream<S><<<V.n_ghost, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const int*)(c->ws + V.off_ghost),
-                                                          (const int*)(c->ws + V.off_band_off),
-                                                          (const uint16_t*)(c->ws + V.off_band), a);
+      k_ghost_stream<S><<<dim3(V.n_ghost, kBandSplit), 256, 0, c->stream>>>(
+          (const S*)src, (S*)dst, (const int*)(c->ws + V.off_ghost), (const int*)(c->ws + V.off_band_off),
+          (const uint16_t*)(c->ws + V.off_band), a);
       HIP_TRY(c, hipGetLastError());
     }
     if (l == f.L && np) {
