@@ -297,6 +297,9 @@ __device__ void map_cell(int x, int y, int z, uint32_t c, uint8_t* __restrict__ 
     f = kSolid;
     link = o;
   } else {
+    // unrolled, so that the neighbour lookups of all directions are in
+    // flight together: the kernel is one short wave of latency-bound work
+#pragma unroll
     for (int q = 1; q < kQ; ++q) {
       uint32_t sc = 0;
       int wa = 0, ws = 0;
@@ -359,13 +362,16 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
   if (!(flags[c] & kSolid) || owner[c] != pi) return;
   if (cell_owner(x, y, z, parts, np, p) >= 0) return;   // still covered
   // density from old-fluid neighbours
+  // (loops unrolled so that the neighbours' loads are in flight together)
   double rsum = 0.0;
   int cnt = 0;
+#pragma unroll
   for (int q = 1; q < kQ; ++q) {
     uint32_t sc = 0;
     if (ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws) != 1) continue;
     if (flags[sc] & kSolid) continue;
     double r = 0.0;
+#pragma unroll
     for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + sc]);
     rsum += 1.0 + r;
     ++cnt;
