@@ -539,9 +539,15 @@ def cpu_baseline(target_s=12.0):
         if time.perf_counter() - t0 > target_s and k >= 2:
             break
     t = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": n ** 3 * k / t / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"128^3 periodic box with one fixed r=20 sphere (omega 1.6, F=1e-5 z), {k} steps, "
-                      f"{t:.1f} s"}
+                      f"{t:.1f} s", "cpu": model}
 
 
 def main():
