@@ -166,8 +166,9 @@ int vmlbm_get_history(vmlbm_ctx* ctx, int id, int n, double* out);
  * vmlbm_level_blocks.  Solid cells read 0. */
 int vmlbm_read_populations(vmlbm_ctx* ctx, int level, double* out);
 
-/* Overwrite the post-collision populations of a level (same layout), rounded
- * to the storage precision.  For tests and fault injection. */
+/* Overwrite the post-collision populations of a level (same layout).  The
+ * deviation f - w is rounded once to the storage precision, to nearest with
+ * ties to even.  For tests and fault injection. */
 int vmlbm_write_populations(vmlbm_ctx* ctx, int level, const double* in);
 
 /* Particle owner per cell of a level: -1 fluid, else sphere id. */
