@@ -1067,9 +1067,10 @@ int sweep_level(vmlbm_ctx* c, int l) {
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
     if (V.n_int) {
-      // levels with few blocks: four workgroups per block (4 planes each)
-      // so that the launch still covers every compute unit several times
-      const dim3 grid(V.n_int, V.n_int < 1024 ? 4 : 1);
+      // levels with few blocks: one workgroup per plane of a block, so that
+      // the launch still covers every compute unit many times (measured
+      // against 4 and 8 planes per workgroup on the 3-level workload)
+      const dim3 grid(V.n_int, V.n_int < 1024 ? 16 : 1);
       k_level_sweep<S><<<grid, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
                                                     (const int*)(c->ws + V.off_int), c->status(), a);
       HIP_TRY(c, hipGetLastError());
