@@ -626,18 +626,32 @@ __device__ __forceinline__ void load_neighbours(const LevelArgs& a, int slot, in
   __syncthreads();
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin in launch order.  This
+// renumbering gives each XCD a contiguous run of work items instead, so that
+// blocks next to each other in the (x-fastest) block list share one L2: the
+// x-faces of a block pull single cells out of rows of its x-neighbours.  It
+// is a bijection of [0, G) for any G.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t lin, uint32_t G) {
+  const uint32_t q8 = G / 8, r8 = G % 8, xcd = lin % 8, ord = lin / 8;
+  return xcd * q8 + min(xcd, r8) + ord;
+}
+
 // interior blocks of a level: pull + collide, cells with flags left out.
 // gridDim.y workgroups share a block, each taking kBlock / gridDim.y planes.
+// FP32 and FP16 storage number the work XCD-contiguously (3-4 % faster on the
+// 3-level workload); FP64 keeps launch order (3 % slower otherwise).
 template <typename S>
 __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
                                                      const uint8_t* __restrict__ flags, const int* __restrict__ list,
                                                      int* __restrict__ status, LevelArgs a) {
   using T = typename Store<S>::T;
   __shared__ int nbs[27];
-  const int slot = list[blockIdx.x];
+  const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const uint32_t item = sizeof(S) < 8 ? xcd_contiguous(lin, gridDim.x * gridDim.y) : lin;
+  const int slot = list[item / gridDim.y];
   load_neighbours(a, slot, nbs);
   const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  const int planes = kBlock / gridDim.y, z0 = blockIdx.y * planes;
+  const int planes = kBlock / gridDim.y, z0 = (int)(item % gridDim.y) * planes;
   for (int z = z0; z < z0 + planes; ++z) {
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
     if (flags[c]) continue;
