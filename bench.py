@@ -577,8 +577,8 @@ def main():
                     help="translation: also run MEM with a fluid force that cancels the net weight")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (no halo exchange, "
+              "all-reduce or load balancing across GPUs)", file=sys.stderr)
         sys.exit(2)
 
     import torch
