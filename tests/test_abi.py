@@ -52,7 +52,28 @@ def test_host_only_calls(pkg):
     # stepping before a workspace is bound is an ordering error
     assert L.vmlbm_step(h, 1) == -4
     assert b"workspace" in L.vmlbm_last_error(h)
+    zero = (ctypes.c_double * 3)()
+    assert L.vmlbm_set_sphere_motion(h, 0, zero, zero, 2) == -4
+    # sphere parameters outside their ranges
+    bad = pkg.make_sphere(synth.sphere((4.0, 4.0, 4.0), 2.0))
+    bad.fixed = 3
+    assert L.vmlbm_add_sphere(h, ctypes.byref(bad), ctypes.byref(i)) == -1
+    bad = pkg.make_sphere(synth.sphere((4.0, 4.0, 4.0), 2.0, vm_scheme=3))
+    assert L.vmlbm_add_sphere(h, ctypes.byref(bad), ctypes.byref(i)) == -1
     assert L.vmlbm_destroy(h) == 0
+
+
+def test_level_count_limits(pkg):
+    """1..8 levels for a block grid; 9 is refused at creation."""
+    L = pkg.lib()
+    h = ctypes.c_void_p()
+    for levels, rc in ((8, 0), (9, -1), (0, -1)):
+        cfg = synth.base_config((16, 16, 16))
+        cfg["levels"], cfg["block"] = levels, 16
+        c = pkg.make_config(cfg, "f32")
+        assert L.vmlbm_create(ctypes.byref(c), ctypes.byref(h)) == rc, levels
+        if rc == 0:
+            assert L.vmlbm_destroy(h) == 0
 
 
 def test_bad_config_rejected(pkg):

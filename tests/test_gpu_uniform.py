@@ -452,3 +452,22 @@ def test_fp16_write_rounds_to_nearest_even(env):
     sim.close()
     want = w[:, None] + seen.astype(np.float16).astype(np.float64)
     assert np.array_equal(back, want)
+
+
+def test_set_sphere_motion_errors(env):
+    """The set-motion call refuses a bad sphere id or mode, and a release to
+    free motion when no sphere was added free (the re-mapping paths are off);
+    a refused call leaves the sphere as it was."""
+    pkg, ora = env
+    cfg = synth.base_config((24, 24, 24), omega=1.5)
+    sim = pkg.Sim(cfg, [synth.sphere((12.3, 11.8, 12.1), 4.0, fixed=True)], storage="f64")
+    sim.init()
+    for args in ((1, 2), (-1, 2), (0, 3), (0, 0)):
+        with pytest.raises(pkg.VmlbmError) as e:
+            sim.set_sphere_motion(args[0], fixed=args[1])
+        assert e.value.code == -1, args
+    sim.step(2)
+    sim.sync()
+    x, u, w = sim.particle(0)
+    assert (x == np.array([12.3, 11.8, 12.1])).all() and (u == 0.0).all() and (w == 0.0).all()
+    sim.close()
