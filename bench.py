@@ -253,10 +253,13 @@ def _errors(u, ref, every):
             "eps_term_rel": float((a[-1] - b[-1]) / b[-1])}
 
 
-def validate_stability(pkg, diameters=(10, 15, 20, 30), storage="f64", bisections=4):
+def validate_stability(pkg, diameters=(10, 15, 20, 30), storage="f64", bisections=4, factors=None):
     """Table 1: lowest density ratio at Ga 100 for which plain MEM stays
     stable up to t_n = 10, bracketed by bisection in log(pi_p) from the
-    paper's value x {1/2, 2}; VM-MEM (C_v = 1) run at the unstable end."""
+    paper's value x {1/2, 2}; VM-MEM (C_v = 1) run at the unstable end.
+    With factors, MEM runs only at those multiples of the paper's value
+    (VM-MEM at the smallest), for diameters where a bisection costs too
+    much."""
     import math
     out = {}
     for d in diameters:
@@ -267,6 +270,12 @@ def validate_stability(pkg, diameters=(10, 15, 20, 30), storage="f64", bisection
             r = run_light_sphere(pkg, d, pi_p, cv=cv, storage=storage)
             runs["%.5g cv%g" % (pi_p, cv)] = {"status": r["status"], "steps": r["steps"], "of": r["of"]}
             return r["status"] == "stable"
+
+        if factors:
+            for fct in sorted(factors, reverse=True):
+                stable(fct * ref)
+            out[d] = {"paper": ref, "vm_mem_stable_at_smallest": stable(min(factors) * ref, cv=1.0), "runs": runs}
+            continue
 
         lo, hi = 0.5 * ref, 2.0 * ref
         if not stable(hi):
@@ -567,6 +576,8 @@ def main():
                          "rotation,extrapolation,amr")
     ap.add_argument("--validate-diameters", default="10,15,20,30",
                     help="sphere diameters of the stability bracket (Table 1)")
+    ap.add_argument("--validate-factors", default="",
+                    help="stability: run only these multiples of the paper's lowest density ratio")
     ap.add_argument("--validate-schemes", default="1,2", help="extrapolation: virtual-force schemes to run")
     ap.add_argument("--validate-tn", type=float, default=12.0, help="amr: run length in t_n = t u_g / d_p")
     ap.add_argument("--validate-curl", type=float, default=0.0, help="amr: curl-sensor threshold (0 = particle only)")
@@ -590,7 +601,8 @@ def main():
         import paper_2103_10882_amd as pkg
         pkg.lib()
         runs = {"stability": lambda: validate_stability(
-                    pkg, tuple(int(v) for v in args.validate_diameters.split(","))),
+                    pkg, tuple(int(v) for v in args.validate_diameters.split(",")),
+                    factors=tuple(float(v) for v in args.validate_factors.split(",")) if args.validate_factors else None),
                 "translation": lambda: validate_translation(pkg, compensated=args.validate_compensated),
                 "rotation": lambda: validate_rotation(pkg),
                 "amr": lambda: validate_amr(pkg, t_n=args.validate_tn, curl_threshold=args.validate_curl,
