@@ -201,7 +201,8 @@ def test_single_level_block_grid_equals_uniform(env):
 
 
 def test_static_four_levels(env):
-    """Four levels (the most the library takes), nested static regions."""
+    """Four levels (the deepest the dense oracle follows at this size), nested
+    static regions."""
     pkg, oracle = env
     n0 = (64, 16, 16)
     c = cfg_of(n0, 4, omega=1.9, F=(0.0, 0.0, 1e-6))
