@@ -591,7 +591,7 @@ __device__ __forceinline__ int nbr_slot(const LevelArgs& a, const int* pos3, int
 
 // population q of local cell (x,y,z) pulled from x - c_q, via the neighbour
 // slot table nb[27]; returns false if the source block is not stored
-template <typename S, int Q>
+template <typename S, int Q, bool CHECK = true>
 __device__ __forceinline__ bool pull_block(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x,
                                            int y, int z, typename Store<S>::T& out) {
   constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
@@ -599,16 +599,16 @@ __device__ __forceinline__ bool pull_block(const S* __restrict__ src, uint32_t N
   const int bx = xs < 0 ? -1 : (xs > 15 ? 1 : 0), by = ys < 0 ? -1 : (ys > 15 ? 1 : 0),
             bz = zs < 0 ? -1 : (zs > 15 ? 1 : 0);
   const int s = (bx | by | bz) ? nbs[(bz + 1) * 9 + (by + 1) * 3 + (bx + 1)] : slot;
-  if (s < 0) return false;
+  if (CHECK && s < 0) return false;
   const uint32_t c = (uint32_t)s * kBlockCells + (uint32_t)(((zs & 15) * 16 + (ys & 15)) * 16 + (xs & 15));
   out = Store<S>::load(src[(size_t)Q * N + c]);
   return true;
 }
 
-template <typename S, int... Qs>
+template <typename S, bool CHECK, int... Qs>
 __device__ __forceinline__ bool pull_cell(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x, int y,
                                           int z, typename Store<S>::T (&d)[kQ], std::integer_sequence<int, Qs...>) {
-  return (pull_block<S, Qs>(src, N, nbs, slot, x, y, z, d[Qs]) & ...);
+  return (pull_block<S, Qs, CHECK>(src, N, nbs, slot, x, y, z, d[Qs]) & ...);
 }
 
 template <typename S, int... Qs>
@@ -636,27 +636,19 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t lin, uint32_t G) {
   return xcd * q8 + min(xcd, r8) + ord;
 }
 
-// interior blocks of a level: pull + collide, cells with flags left out.
-// gridDim.y workgroups share a block, each taking kBlock / gridDim.y planes.
-// FP32 and FP16 storage number the work XCD-contiguously (3-4 % faster on the
-// 3-level workload); FP64 keeps launch order (3 % slower otherwise).
-template <typename S>
-__global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
-                                                     const uint8_t* __restrict__ flags, const int* __restrict__ list,
-                                                     int* __restrict__ status, LevelArgs a) {
+// planes z0 .. z0 + planes - 1 of one block; CHECK: test per source that
+// its block is stored (needed only when a neighbour slot is missing)
+template <typename S, bool CHECK>
+__device__ __forceinline__ void sweep_planes(const S* __restrict__ src, S* __restrict__ dst,
+                                             const uint8_t* __restrict__ flags, int* __restrict__ status,
+                                             const LevelArgs& a, const int* nbs, int slot, int z0, int planes) {
   using T = typename Store<S>::T;
-  __shared__ int nbs[27];
-  const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
-  const uint32_t item = sizeof(S) < 8 ? xcd_contiguous(lin, gridDim.x * gridDim.y) : lin;
-  const int slot = list[item / gridDim.y];
-  load_neighbours(a, slot, nbs);
   const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
-  const int planes = kBlock / gridDim.y, z0 = (int)(item % gridDim.y) * planes;
   for (int z = z0; z < z0 + planes; ++z) {
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
     if (flags[c]) continue;
     T d[kQ];
-    if (!pull_cell<S>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
+    if (!pull_cell<S, CHECK>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
       status[kStatusRange] = 6;
       continue;
     }
@@ -666,6 +658,32 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
 #pragma unroll
     for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * a.N + c], Store<S>::store_sr(d[q], rb.next()));
   }
+}
+
+// interior blocks of a level: pull + collide, cells with flags left out.
+// gridDim.y workgroups share a block, each taking kBlock / gridDim.y planes.
+// FP32 and FP16 storage number the work XCD-contiguously (3-4 % faster on the
+// 3-level workload); FP64 keeps launch order (3 % slower otherwise).
+template <typename S>
+__global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                                     const uint8_t* __restrict__ flags, const int* __restrict__ list,
+                                                     int* __restrict__ status, LevelArgs a) {
+  __shared__ int nbs[27];
+  __shared__ int all_stored;
+  const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const uint32_t item = sizeof(S) < 8 ? xcd_contiguous(lin, gridDim.x * gridDim.y) : lin;
+  const int slot = list[item / gridDim.y];
+  load_neighbours(a, slot, nbs);
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    for (int t = 0; t < 27; ++t) ok &= nbs[t] >= 0;
+    all_stored = ok;
+  }
+  __syncthreads();
+  const int planes = kBlock / gridDim.y, z0 = (int)(item % gridDim.y) * planes;
+  // one test per workgroup instead of one per direction and cell
+  if (all_stored) sweep_planes<S, false>(src, dst, flags, status, a, nbs, slot, z0, planes);
+  else sweep_planes<S, true>(src, dst, flags, status, a, nbs, slot, z0, planes);
 }
 
 // ghost cells (the band of each ghost block listed in band[band_off[g] ..
