@@ -99,20 +99,23 @@ def test_static_three_levels(env, storage, tol, lb):
         assert rel <= tol
 
 
-def test_moving_sphere_rerefinement(env):
+@pytest.mark.parametrize("lb", [1.0, 100.0])
+def test_moving_sphere_rerefinement(env, lb):
     """Sphere on the finest level moving across a finest-block boundary: the
     layout is re-checked every 4 coarse steps and changes; F/T, mapping,
-    particle state and populations follow the oracle."""
+    particle state and populations follow the oracle, with TRT and with the
+    MRT collision (bulk factor 100)."""
     pkg, oracle = env
     n0 = (32, 32, 48)
     c = cfg_of(n0, 3, omega=1.8, gravity=(0.0, 0.0, -2e-4))
+    c["bulk_factor"] = lb
     # top of the grown box (sphere box plus one finest block) just below the
     # boundary of a level-1 node (32 finest cells): the layout changes once
     # the heavy sphere has moved half a cell
     s = synth.sphere((64.2, 63.7, 63.5 - 5.5 - 16.0), 5.5, density_ratio=1e3, cv=0.5, fixed=False,
                      u=(0.0, 0.0, 0.1))
     u0 = synth.velocity_perturbation(n0, seed=9)
-    say("case refined32x32x48 L3 moving f64")
+    say(f"case refined32x32x48 L3 moving f64, bulk factor {lb}")
     sim = pkg.Sim(c, [s], storage="f64", history=8, check_every=4)
     sim.init(1.0, u0)
     ref = oracle.Refined(c, spheres=[s], check_every=4)
