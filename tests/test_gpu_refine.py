@@ -397,3 +397,41 @@ def test_deep_hierarchy_comoving_sphere(env):
     _, u, _ = sim.particle(0)
     assert np.abs(u - U).max() < 1e-14
     sim.close()
+
+
+def test_two_spheres_refined(env):
+    """Two spheres on the finest level of a 3-level grid, one held and one
+    moving through the layout: per-sphere link lists, force slots and
+    refinement boxes; F/T of both every step and populations at the end
+    follow the oracle."""
+    pkg, oracle = env
+    n0 = (64, 32, 32)
+    c = cfg_of(n0, 3, omega=1.7, F=(2e-6, 0.0, 1e-6))
+    held = synth.sphere((40.6, 62.2, 58.9), 6.5, fixed=True)
+    # the moving sphere's refinement box reaches the next finest block
+    # after about 2.5 cells of motion along x
+    moving = synth.sphere((168.2, 66.1, 70.3), 5.5, density_ratio=50.0, cv=0.5, fixed=False,
+                          u=(0.08, -0.02, 0.05))
+    u0 = synth.velocity_perturbation(n0, seed=16)
+    say("case refined64x32x32 L3 two spheres f64")
+    sim = pkg.Sim(c, [held, moving], storage="f64", history=8, check_every=4)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, spheres=[held, moving], check_every=4)
+    ref.init(1.0, u0)
+    for k in range(1, 13):
+        sim.step(1)
+        ref.step(1)
+        for i, r in ((0, 6.5), (1, 5.5)):
+            Fg, Tg = sim.force_torque(i)
+            Fo, To = ref.force_torque(i)
+            assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, i, Fg, Fo)
+            assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), r * np.abs(Fo).max()), (k, i, Tg, To)
+    sim.sync()
+    assert sim.refinements() == ref.counters()[2] >= 1
+    for i in range(2):
+        xg, ug, _ = sim.particle(i)
+        xo, uo, _ = ref.particle(i)
+        assert np.abs(xg - xo).max() < 1e-11 and np.abs(ug - uo).max() < 1e-12
+    rel = compare_levels(sim, ref, 3)
+    say(f"  refinements {sim.refinements()}; population rel err {rel:.2e}")
+    assert rel <= 1e-11
