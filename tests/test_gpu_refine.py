@@ -435,3 +435,40 @@ def test_two_spheres_refined(env):
     rel = compare_levels(sim, ref, 3)
     say(f"  refinements {sim.refinements()}; population rel err {rel:.2e}")
     assert rel <= 1e-11
+
+
+def test_rotation_only_sphere_refined(env):
+    """Hold modes on the refined grid: a sphere held in a shear wave, then
+    switched to rotation-only (Sec. 3.4.2 protocol) with the Lagrange
+    virtual-force scheme; F/T every step and the angular velocity follow
+    the oracle, the position stays put."""
+    pkg, oracle = env
+    n0 = (32, 16, 32)
+    c = cfg_of(n0, 2, omega=1.5)
+    s = synth.sphere((31.3, 15.6, 33.2), 5.0, density_ratio=0.8, cv=1.0, fixed=True, vm_scheme=2)
+    z = np.arange(n0[2]) + 0.5
+    u0 = np.zeros((3, n0[2], n0[1], n0[0]))
+    u0[0] = (0.02 * np.sin(2 * np.pi * z / n0[2]))[:, None, None]
+    say("case refined32x16x32 L2 hold then rotate f64")
+    sim = pkg.Sim(c, [s], storage="f64", history=8, check_every=4)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, spheres=[s], check_every=4)
+    ref.init(1.0, u0)
+    for k in range(1, 9):
+        if k == 3:
+            for o in (sim, ref):
+                o.set_sphere_motion(0, fixed=2)
+        sim.step(1)
+        ref.step(1)
+        Fg, Tg = sim.force_torque(0)
+        Fo, To = ref.force_torque(0)
+        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), 5.0 * np.abs(Fo).max()), (k, Tg, To)
+    sim.sync()
+    xg, ug, wg = sim.particle(0)
+    xo, uo, wo = ref.particle(0)
+    assert (xg == np.array(s["x"])).all() and (ug == 0.0).all()
+    assert np.abs(wg - wo).max() <= 1e-12 * np.abs(wo).max() and np.abs(wo).max() > 0
+    rel = compare_levels(sim, ref, 2)
+    say(f"  w {wg}, population rel err {rel:.2e}")
+    assert rel <= 1e-11
