@@ -81,18 +81,15 @@ struct SrBits {
 
 // FP32 -> FP16 rounding up or down with probability proportional to the
 // distance to the two neighbours (unbiased in expectation).  r: 32 random
-// bits.  FP16 normals keep 10 of FP32's 23 mantissa bits: add 13 random bits
-// below the kept ones and truncate; subnormals (|v| < 2^-14) are multiples
-// of 2^-24: scale, add a uniform [0,1) and take the floor.
+// bits.  gfx950's v_cvt_sr_f16_f32 does this in one instruction, taking the
+// uniform variate from the high bits of r, for normal and subnormal results
+// alike (measured: a mean over 2^16 words of each value reproduces it to the
+// 2^-16 quantisation of the variate).
 __device__ __forceinline__ __half half_sr(float v, uint32_t r) {
-  const uint32_t b = __float_as_uint(v);
-  const uint32_t sgn = b & 0x80000000u, mag = b & 0x7fffffffu;
-  if (mag >= 0x38800000u) {
-    const uint32_t m = (mag + (r >> 19)) & ~0x1fffu;
-    return __float2half_rn(__uint_as_float(sgn | m));
-  }
-  const float k = floorf(__uint_as_float(mag) * 16777216.0f + (float)(r >> 8) * (1.0f / 16777216.0f));
-  return __float2half_rn(__uint_as_float(sgn | __float_as_uint(k * (1.0f / 16777216.0f))));
+  typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+  const h2 zero = {(_Float16)0.0f, (_Float16)0.0f};
+  const h2 h = __builtin_amdgcn_cvt_sr_f16_f32(zero, v, r, false);
+  return __ushort_as_half(__builtin_bit_cast(unsigned short, h[0]));
 }
 
 // Storage formats (reduced-precision storage is not part of the paper's
