@@ -76,11 +76,13 @@ struct Forest {
     std::vector<int> explode;         // per ghost slot: ghost slot, parent slot, ox, oy, oz
     std::vector<uint16_t> band;       // ghost cells (local index) of each ghost block, in ghost order
     std::vector<int> band_off;        // per ghost block: start in band; one extra end entry
+    std::vector<uint32_t> band_dirs;  // per band cell: populations written by explosion, sub-step 1, 2
     std::vector<IfaceEntry> iface;
     LevelParams lp{};
     // device
     size_t off_pdf[2] = {0, 0}, off_flags = 0, off_slot_of[2] = {0, 0}, off_pos = 0, off_int = 0, off_ghost = 0,
-           off_explode = 0, off_iface = 0, off_band = 0, off_band_off = 0, off_vel = 0, off_sens = 0;
+           off_explode = 0, off_iface = 0, off_band = 0, off_band_off = 0, off_band_dirs = 0, off_vel = 0,
+           off_sens = 0;
     int cur = 0, tab = 0;
     int n_int = 0, n_ghost = 0, n_iface = 0;
   };
@@ -462,6 +464,76 @@ void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<
   }
 }
 
+// Populations of the ghost band of level l (l >= 1) that are read before the
+// next explosion overwrites them; only those are written.  Within one
+// level-(l-1) step, with buffers A (current) and B:
+//   explosion -> A;  sub-step 1 reads A, writes B;  sub-step 2 reads B,
+//   writes A;  the level-(l-1) coalescence reads A.
+// Sub-step 2 produces the children its coalescence table adds (bit q of the
+// entry's mask).  Sub-step 1 produces population q of band cell g where
+// g + c_q is an interior cell (its pull in sub-step 2; coalescence cells of
+// level l and the link and second-node reads of the particle coupling are
+// such pulls) and the band sources g - c_q of the sub-step-2 streaming.  The
+// explosion produces the same for sub-step 1: the interior pulls and the band
+// sources of the sub-step-1 streaming.  band_dirs[3 i + s], bit q: band cell i
+// writes population q in the explosion (s = 0) or in sub-step s.
+void band_directions(const Kinds& K, Forest& f, int l) {
+  Forest::Lev& V = f.lv[l];
+  const int n_int = (int)V.interior.size();
+  V.band_dirs.assign(3 * V.band.size(), 0u);
+  std::vector<int> at(V.ghost.size() * kBlockCells, -1);   // band index of every ghost-block cell
+  for (size_t g = 0; g < V.ghost.size(); ++g)
+    for (int i = V.band_off[g]; i < V.band_off[g + 1]; ++i) at[g * kBlockCells + V.band[i]] = i;
+  auto band_at = [&](int i, int j, int k) -> int {
+    i = Kinds::wrap1(i, V.n[0]); j = Kinds::wrap1(j, V.n[1]); k = Kinds::wrap1(k, V.n[2]);
+    const int s = V.slot_of[K.bpos(l, i >> 4, j >> 4, k >> 4)];
+    if (s < n_int) return -1;
+    return at[(size_t)(s - n_int) * kBlockCells + (((k & 15) * kBlock + (j & 15)) * kBlock + (i & 15))];
+  };
+  auto coords = [&](int b, int g, int& i, int& j, int& k) {
+    const int s = V.ghost[g], loc = V.band[b];
+    i = V.pos[3 * s] * kBlock + (loc & 15);
+    j = V.pos[3 * s + 1] * kBlock + ((loc >> 4) & 15);
+    k = V.pos[3 * s + 2] * kBlock + (loc >> 8);
+  };
+  // sub-step 2: the coalescence reads of level l - 1
+  for (const IfaceEntry& e : f.lv[l - 1].iface) {
+    if (e.fine_slot < n_int) continue;
+    for (int q = 0; q < kQ; ++q)
+      for (int m = 0; m < 8; ++m)
+        if (e.mask[q] & (1u << m)) {
+          const int loc = e.fine_local + ((m >> 2) * kBlock + ((m >> 1) & 1)) * kBlock + (m & 1);
+          const int b = at[(size_t)(e.fine_slot - n_int) * kBlockCells + loc];
+          if (b >= 0) V.band_dirs[3 * b + 2] |= 1u << q;
+        }
+  }
+  // sub-step 1 and explosion: interior pulls, then the band sources of the
+  // streaming of the following sub-step
+  for (size_t g = 0; g < V.ghost.size(); ++g)
+    for (int b = V.band_off[g]; b < V.band_off[g + 1]; ++b) {
+      int i, j, k;
+      coords(b, (int)g, i, j, k);
+      uint32_t pulled = 0;
+      for (int q = 1; q < kQ; ++q)
+        if (K.kind(l, i + cx_of(q), j + cy_of(q), k + cz_of(q)) == K_INTERIOR) pulled |= 1u << q;
+      V.band_dirs[3 * b] |= pulled;
+      V.band_dirs[3 * b + 1] |= pulled;
+    }
+  for (int s = 2; s >= 1; --s)
+    for (size_t g = 0; g < V.ghost.size(); ++g)
+      for (int b = V.band_off[g]; b < V.band_off[g + 1]; ++b) {
+        const uint32_t m = V.band_dirs[3 * b + s];
+        if (!m) continue;
+        int i, j, k;
+        coords(b, (int)g, i, j, k);
+        for (int q = 1; q < kQ; ++q)
+          if (m & (1u << q)) {
+            const int src = band_at(i - cx_of(q), j - cy_of(q), k - cz_of(q));
+            if (src >= 0) V.band_dirs[3 * src + s - 1] |= 1u << q;
+          }
+      }
+}
+
 // slot lists, ghost blocks, explosion map and coalescence table of every
 // level for the current leaf field
 int build_tables(vmlbm_ctx* c, Forest& f) {
@@ -566,6 +638,7 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
       return fail(c, VMLBM_ERANGE, "level %d coalescence table needs %zu entries, capacity %d", l, V.iface.size(),
                   V.iface_cap);
   }
+  for (int l = 1; l <= L; ++l) band_directions(K, f, l);
   return VMLBM_OK;
 }
 
@@ -611,11 +684,19 @@ __device__ __forceinline__ bool pull_cell(const S* __restrict__ src, uint32_t N,
   return (pull_block<S, Qs, CHECK>(src, N, nbs, slot, x, y, z, d[Qs]) & ...);
 }
 
+// the populations of mask `dirs` of a ghost cell; a source block that is not
+// stored gives 0.  All loads are issued before the first store.
+template <typename S, int Q>
+__device__ __forceinline__ void ghost_pull_one(const S* __restrict__ src, uint32_t N, const int* nbs, int slot,
+                                               int x, int y, int z, uint32_t dirs, typename Store<S>::T& d) {
+  if (!((dirs >> Q) & 1u) || !pull_block<S, Q>(src, N, nbs, slot, x, y, z, d)) d = typename Store<S>::T(0);
+}
+
 template <typename S, int... Qs>
 __device__ __forceinline__ void ghost_pull(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x,
-                                           int y, int z, typename Store<S>::T (&d)[kQ],
+                                           int y, int z, uint32_t dirs, typename Store<S>::T (&d)[kQ],
                                            std::integer_sequence<int, Qs...>) {
-  ((d[Qs] = pull_block<S, Qs>(src, N, nbs, slot, x, y, z, d[Qs]) ? d[Qs] : typename Store<S>::T(0)), ...);
+  (ghost_pull_one<S, Qs>(src, N, nbs, slot, x, y, z, dirs, d[Qs]), ...);
 }
 
 __device__ __forceinline__ void load_neighbours(const LevelArgs& a, int slot, int* nbs) {
@@ -689,48 +770,65 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
 // ghost cells (the band of each ghost block listed in band[band_off[g] ..
 // band_off[g+1]) as local cell indices): stream only; sources not stored at
 // this level give 0.  Cells of a ghost block outside its band are never
-// read by an update of this level's region within the two substeps.  A band
-// holds a few hundred cells: gridDim.y workgroups share one, so that each
-// thread takes about one cell and the launch is one round of short,
-// latency-bound work.
+// read by an update of this level's region within the two substeps, and a
+// band cell writes only the populations of its direction mask for this
+// sub-step (dirs, stride 3), the ones read before the next explosion.  Cells
+// on the x-faces of the region form 2-cell runs that touch a cache line per
+// population, so the masks cut the lines moved by about four.  A band holds a
+// few hundred cells: gridDim.y workgroups share one, so that each thread
+// takes about one cell and the launch is one round of short, latency-bound
+// work.
 constexpr int kBandSplit = 2;
 template <typename S>
 __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src, S* __restrict__ dst,
                                                       const int* __restrict__ list, const int* __restrict__ band_off,
-                                                      const uint16_t* __restrict__ band, LevelArgs a) {
+                                                      const uint16_t* __restrict__ band,
+                                                      const uint32_t* __restrict__ dirs, LevelArgs a) {
   using T = typename Store<S>::T;
   __shared__ int nbs[27];
   const int slot = list[blockIdx.x];
   load_neighbours(a, slot, nbs);
   const int b1 = band_off[blockIdx.x + 1];
   for (int i = band_off[blockIdx.x] + blockIdx.y * blockDim.x + threadIdx.x; i < b1; i += gridDim.y * blockDim.x) {
+    const uint32_t m = dirs[3 * i];
+    if (!m) continue;
     const int local = band[i];
     const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)local;
     T d[kQ];
-    ghost_pull<S>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
+    ghost_pull<S>(src, a.N, nbs, slot, x, y, z, m, d, std::make_integer_sequence<int, kQ>{});
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+    for (int q = 1; q < kQ; ++q)
+      if ((m >> q) & 1u) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
   }
 }
 
 // explosion: every ghost cell of level l+1 takes its parent's populations
-// (level l, current state); ghost block g is explode entry g
+// (level l, current state), those of its explosion mask (dirs, stride 3);
+// ghost block g is explode entry g
 template <typename S>
 __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S* __restrict__ fine,
                                                  const int* __restrict__ ex, const int* __restrict__ band_off,
-                                                 const uint16_t* __restrict__ band, uint32_t Nc, uint32_t Nf) {
+                                                 const uint16_t* __restrict__ band, const uint32_t* __restrict__ dirs,
+                                                 uint32_t Nc, uint32_t Nf) {
   const int* e = ex + 5 * blockIdx.x;
   const int gs = e[0], ps = e[1], ox = e[2], oy = e[3], oz = e[4];
   const int b1 = band_off[blockIdx.x + 1];
   for (int i = band_off[blockIdx.x] + blockIdx.y * blockDim.x + threadIdx.x; i < b1; i += gridDim.y * blockDim.x) {
+    const uint32_t m = dirs[3 * i];
+    if (!m) continue;
     const int local = band[i];
     const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
     const uint32_t cf = (uint32_t)gs * kBlockCells + (uint32_t)local;
     const uint32_t cc = (uint32_t)ps * kBlockCells +
                         (uint32_t)(((oz + (z >> 1)) * 16 + (oy + (y >> 1))) * 16 + (ox + (x >> 1)));
+    S v[kQ];
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) fine[(size_t)q * Nf + cf] = coarse[(size_t)q * Nc + cc];
+    for (int q = 1; q < kQ; ++q)
+      if ((m >> q) & 1u) v[q] = coarse[(size_t)q * Nc + cc];
+#pragma unroll
+    for (int q = 1; q < kQ; ++q)
+      if ((m >> q) & 1u) fine[(size_t)q * Nf + cf] = v[q];
   }
 }
 
@@ -1033,9 +1131,12 @@ int upload_tables(vmlbm_ctx* c) {
     if (!V.iface.empty())
       HIP_TRY(c, hipMemcpy(c->ws + V.off_iface, V.iface.data(), V.iface.size() * sizeof(IfaceEntry),
                            hipMemcpyHostToDevice));
-    if (!V.band.empty())
+    if (!V.band.empty()) {
       HIP_TRY(c, hipMemcpy(c->ws + V.off_band, V.band.data(), V.band.size() * sizeof(uint16_t),
                            hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_band_dirs, V.band_dirs.data(), V.band_dirs.size() * sizeof(uint32_t),
+                           hipMemcpyHostToDevice));
+    }
     HIP_TRY(c, hipMemcpy(c->ws + V.off_band_off, V.band_off.data(), V.band_off.size() * sizeof(int),
                          hipMemcpyHostToDevice));
     V.n_int = (int)V.interior.size();
@@ -1082,14 +1183,15 @@ int explode(vmlbm_ctx* c, int l) {
     using S = std::remove_pointer_t<decltype(tag)>;
     k_explode<S><<<dim3(F.n_ghost, kBandSplit), 256, 0, c->stream>>>(
         (const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]), (const int*)(c->ws + F.off_explode),
-        (const int*)(c->ws + F.off_band_off), (const uint16_t*)(c->ws + F.off_band), (uint32_t)C.cap * kBlockCells,
-        (uint32_t)F.cap * kBlockCells);
+        (const int*)(c->ws + F.off_band_off), (const uint16_t*)(c->ws + F.off_band),
+        (const uint32_t*)(c->ws + F.off_band_dirs), (uint32_t)C.cap * kBlockCells, (uint32_t)F.cap * kBlockCells);
     HIP_TRY(c, hipGetLastError());
     return VMLBM_OK;
   });
 }
 
-int sweep_level(vmlbm_ctx* c, int l) {
+// sub: 0 or 1, the first or second step of level l within a level-(l-1) step
+int sweep_level(vmlbm_ctx* c, int l, int sub) {
   Forest& f = *c->forest;
   Forest::Lev& V = f.lv[l];
   const LevelArgs a = level_args(c, l, V.tab);
@@ -1117,7 +1219,7 @@ int sweep_level(vmlbm_ctx* c, int l) {
     if (V.n_ghost) {
       k_ghost_stream<S><<<dim3(V.n_ghost, kBandSplit), 256, 0, c->stream>>>(
           (const S*)src, (S*)dst, (const int*)(c->ws + V.off_ghost), (const int*)(c->ws + V.off_band_off),
-          (const uint16_t*)(c->ws + V.off_band), a);
+          (const uint16_t*)(c->ws + V.off_band), (const uint32_t*)(c->ws + V.off_band_dirs) + 1 + sub, a);
       HIP_TRY(c, hipGetLastError());
     }
     if (l == f.L && np) {
@@ -1170,17 +1272,17 @@ int sweep_level(vmlbm_ctx* c, int l) {
   return VMLBM_OK;
 }
 
-int step_level(vmlbm_ctx* c, int l) {
+int step_level(vmlbm_ctx* c, int l, int sub) {
   Forest& f = *c->forest;
   if (l < f.L) {
     int rc = explode(c, l);
     if (rc) return rc;
-    rc = step_level(c, l + 1);
+    rc = step_level(c, l + 1, 0);
     if (rc) return rc;
-    rc = step_level(c, l + 1);
+    rc = step_level(c, l + 1, 1);
     if (rc) return rc;
   }
-  return sweep_level(c, l);
+  return sweep_level(c, l, sub);
 }
 
 // re-check the layout around the particles; move data if it changed
@@ -1374,6 +1476,7 @@ int refine_plan(vmlbm_ctx* c) {
     V.off_iface = take((size_t)V.iface_cap * sizeof(IfaceEntry));
     V.off_band = take((size_t)V.cap * kBlockCells * sizeof(uint16_t));
     V.off_band_off = take((size_t)(V.cap + 1) * sizeof(int));
+    V.off_band_dirs = take((size_t)V.cap * kBlockCells * 3 * sizeof(uint32_t));
     if (f.flow) {
       V.off_vel = take((size_t)3 * V.cap * kBlockCells * sizeof(double));
       V.off_sens = take((size_t)V.cap * sizeof(double));
@@ -1461,7 +1564,7 @@ int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
 int refine_step(vmlbm_ctx* c, int n) {
   Forest& f = *c->forest;
   for (int s = 0; s < n; ++s) {
-    int rc = step_level(c, 0);
+    int rc = step_level(c, 0, 0);
     if (rc) return rc;
     c->steps_done += 1;
     f.coarse_steps += 1;
