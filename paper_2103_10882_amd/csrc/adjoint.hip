@@ -205,7 +205,7 @@ __global__ __launch_bounds__(256) void k_adj_boundary(const S* __restrict__ s, c
     ad.n[0] = p.nx; ad.n[1] = p.ny; ad.n[2] = p.nz;
     ad.per[0] = ad.per[1] = ad.per[2] = 1;
     ad.N = p.N;
-    boundary_cell<S, UAddr>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status, &mask, kap);
+    boundary_cell<S, UAddr>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status, &mask, kap, pi);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) lam[q] = T(lin[(size_t)q * N + c]);
     collide_adjoint<T>(d, lam, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]), dsm_dw, nu, gF, gW);

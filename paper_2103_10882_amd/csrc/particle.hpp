@@ -17,27 +17,35 @@ namespace vm {
 // is left out: summed over the closed surface of a body it vanishes exactly
 // (every lattice line enters and leaves the body equally often), and so does
 // its torque (entry and exit points of a line differ by a multiple of c_q).
+// `sphere` >= 0 names the particle whose links the caller expects: its state
+// is then read once instead of per link (a link of another particle still
+// sets pid to that one, for the caller's check).  Every stage issues the
+// loads of all directions before their first use, and errors are recorded
+// after the loops, so that no store can order the loads of one direction
+// after those of the previous one.
 template <typename S, typename A>
 __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restrict__ flags,
                               const uint16_t* __restrict__ owner, const DevParticle* __restrict__ parts,
                               const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
                               typename Store<S>::T (&d)[kQ], int& pid, double (&Fl)[3], double (&Tl)[3],
                               int* __restrict__ status, uint32_t* link_mask = nullptr,
-                              typename Store<S>::T* kappa_out = nullptr) {
+                              typename Store<S>::T* kappa_out = nullptr, int sphere = -1) {
   using T = typename Store<S>::T;
   const uint32_t N = ad.N;
   const int n[3] = {p.nx, p.ny, p.nz};
-  // pass 1: pull source of every direction and its flag, loads issued together
+  // pass 1: pull source of every direction and its flag
   uint32_t sidx[kQ];
   int8_t wall[kQ];          // -1: inside the domain, else 2*axis + side of the wall crossed
   uint8_t sfl[kQ];
+  bool unstored = false;
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
     int wa = 0, ws = 0;
-    sidx[q] = c;
-    const int st = ad.locate(x - cx_of(q), y - cy_of(q), z - cz_of(q), sidx[q], wa, ws);
+    uint32_t si = c;
+    const int st = ad.locate(x - cx_of(q), y - cy_of(q), z - cz_of(q), si, wa, ws);
     wall[q] = st == 0 ? (int8_t)(2 * wa + ws) : (int8_t)-1;
-    if (st < 0) { status[kStatusRange] = 5; sidx[q] = c; }
+    unstored = unstored || st < 0;
+    sidx[q] = st < 0 ? c : si;
   }
 #pragma unroll
   for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;   // sidx = c across walls
@@ -49,9 +57,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     const T v = Store<S>::load(src[(size_t)q * N + sidx[q]]);
     if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = v;
   }
-  // pass 3: links.  Each stage issues its loads for all directions at once
-  // (non-link directions read the cell itself), so the dependent accesses
-  // of the directions overlap instead of following one another.
+  // pass 3: links (non-link directions read the cell itself)
   bool link[kQ];
   T own[kQ];
 #pragma unroll
@@ -62,22 +68,35 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     link[q] = wall[q] >= 0 || (sfl[q] & kSolid);
     pq[q] = owner[(link[q] && wall[q] < 0) ? sidx[q] : c];
   }
-  // second node x - c_qq = x + c_q of each particle link
+  // second node x - c_qq = x + c_q of each particle link, located for every
+  // direction and kept where it is a stored fluid cell
   uint32_t tidx[kQ];
   bool tok[kQ];
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
     int wa2 = 0, ws2 = 0;
-    tidx[q] = c;
-    tok[q] = link[q] && wall[q] < 0 &&
-             ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), tidx[q], wa2, ws2) == 1;
-    if (!tok[q]) tidx[q] = c;
+    uint32_t ti = c;
+    const int st2 = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), ti, wa2, ws2);
+    tok[q] = link[q] && wall[q] < 0 && st2 == 1;
+    tidx[q] = tok[q] ? ti : c;
   }
+  uint8_t tfl[kQ];
 #pragma unroll
-  for (int q = 1; q < kQ; ++q) tok[q] = tok[q] && !(flags[tidx[q]] & kSolid);
+  for (int q = 1; q < kQ; ++q) tfl[q] = flags[tidx[q]];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) tok[q] = tok[q] && !(tfl[q] & kSolid);
   T sec[kQ];
 #pragma unroll
   for (int q = 1; q < kQ; ++q) sec[q] = Store<S>::load(src[(size_t)opp_of(q) * N + (tok[q] ? tidx[q] : c)]);
+  // state of the expected particle, read once
+  double kx[3] = {0.0, 0.0, 0.0}, ku[3] = {0.0, 0.0, 0.0}, kw[3] = {0.0, 0.0, 0.0}, kr = 0.0;
+  if (sphere >= 0) {
+    const DevParticle& K = parts[sphere];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { kx[a] = K.x[a]; ku[a] = K.u[a]; kw[a] = K.w[a]; }
+    kr = K.r;
+  }
+  bool mixed = false;
   if (link_mask) *link_mask = 0;
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
@@ -99,14 +118,24 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     }
     // particle link in direction qq (c_qq = -c_q points into the solid)
     const int pi = pq[q];
-    const DevParticle& P = parts[pi];
+    double px[3], pu[3], pw[3], pr;
+    if (sphere >= 0) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { px[a] = kx[a]; pu[a] = ku[a]; pw[a] = kw[a]; }
+      pr = kr;
+    } else {
+      const DevParticle& P = parts[pi];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) { px[a] = P.x[a]; pu[a] = P.u[a]; pw[a] = P.w[a]; }
+      pr = P.r;
+    }
     double off[3];
-    sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
-    const double delta = ray_delta(off, -cq[0], -cq[1], -cq[2], P.r);
+    sphere_offset(px, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
+    const double delta = ray_delta(off, -cq[0], -cq[1], -cq[2], pr);
     double rb[3] = {off[0] - delta * cq[0], off[1] - delta * cq[1], off[2] - delta * cq[2]};
-    double v[3] = {P.u[0] + (P.w[1] * rb[2] - P.w[2] * rb[1]),
-                   P.u[1] + (P.w[2] * rb[0] - P.w[0] * rb[2]),
-                   P.u[2] + (P.w[0] * rb[1] - P.w[1] * rb[0])};
+    double v[3] = {pu[0] + (pw[1] * rb[2] - pw[2] * rb[1]),
+                   pu[1] + (pw[2] * rb[0] - pw[0] * rb[2]),
+                   pu[2] + (pw[0] * rb[1] - pw[1] * rb[0])};
     double kappa = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
     double alpha = 4.0 / (1.0 + 2.0 * delta);
     if (!tok[q]) { kappa = 0.0; alpha = 2.0; }
@@ -121,13 +150,15 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     double Fq[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) Fq[a] = (-cq[a] - v[a]) * a0 + (-cq[a] + v[a]) * a1;
-    if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
+    mixed = mixed || (pid >= 0 && pid != pi);
     pid = pi;
     Fl[0] += Fq[0]; Fl[1] += Fq[1]; Fl[2] += Fq[2];
     Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
     Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
     Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
   }
+  if (unstored) status[kStatusRange] = 5;
+  if (mixed) status[kStatusRange] = 2;
 }
 
 
@@ -252,7 +283,7 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
     }
     int pid = -1;
     T d[kQ];
-    boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status);
+    boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status, nullptr, nullptr, pi);
     if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
     const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;

@@ -90,15 +90,18 @@ struct BAddr {
   int nb[3];           // block positions of the level per axis
   const int* slot_of;  // [nb2][nb1][nb0]
   uint32_t N;          // population stride: slot capacity * 4096
-  // 1: stored cell c; -1: not stored at this level
+  // 1: stored cell c; -1: not stored at this level (c unchanged).  Written
+  // with bit masks rather than a branch on the loaded slot, so that callers
+  // can issue the lookups of several cells before waiting for any.
   __device__ __forceinline__ int locate(int x, int y, int z, uint32_t& c, int&, int&) const {
     x = x < 0 ? x + n[0] : (x >= n[0] ? x - n[0] : x);
     y = y < 0 ? y + n[1] : (y >= n[1] ? y - n[1] : y);
     z = z < 0 ? z + n[2] : (z >= n[2] ? z - n[2] : z);
     const int s = slot_of[((z >> 4) * nb[1] + (y >> 4)) * nb[0] + (x >> 4)];
-    if (s < 0) return -1;
-    c = (uint32_t)s * kBlockCells + (uint32_t)((((z & 15) << 4) | (y & 15)) << 4 | (x & 15));
-    return 1;
+    const uint32_t cs = (uint32_t)s * kBlockCells + (uint32_t)((((z & 15) << 4) | (y & 15)) << 4 | (x & 15));
+    const uint32_t miss = (uint32_t)(s >> 31);   // all ones where the block is not stored
+    c = (cs & ~miss) | (c & miss);
+    return (s >> 31) | 1;
   }
 };
 
