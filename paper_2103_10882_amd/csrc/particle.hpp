@@ -328,22 +328,28 @@ __device__ void map_cell(int x, int y, int z, uint32_t c, uint8_t* __restrict__ 
     f = kSolid;
     link = o;
   } else {
-    // unrolled, so that the neighbour lookups of all directions are in
-    // flight together: the kernel is one short wave of latency-bound work
+    // the neighbour lookups of all directions are issued before any is
+    // used: the kernel is one short wave of latency-bound work
+    int st[kQ];
 #pragma unroll
     for (int q = 1; q < kQ; ++q) {
       uint32_t sc = 0;
       int wa = 0, ws = 0;
-      const int st = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws);
-      if (st == 0) { f |= kNearW; continue; }
-      if (st < 0) continue;
+      st[q] = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws);
+    }
+    bool mixed = false;
+#pragma unroll
+    for (int q = 1; q < kQ; ++q) {
+      if (st[q] == 0) { f |= kNearW; continue; }
+      if (st[q] < 0) continue;
       const int so = cell_owner(x + cx_of(q), y + cy_of(q), z + cz_of(q), parts, np, p);
       if (so >= 0) {
-        if (link >= 0 && link != so) status[kStatusRange] = 4;
+        mixed = mixed || (link >= 0 && link != so);
         if (link < 0) link = so;
         f |= kNearP;
       }
     }
+    if (mixed) status[kStatusRange] = 4;
   }
   flags[c] = f;
   owner[c] = link < 0 ? 0 : (uint16_t)link;
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint
 // the flags are updated, so flags/owner still describe the old mapping.
 // ---------------------------------------------------------------------------
 template <typename S, typename A>
-__global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uint8_t* __restrict__ flags,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_refill(S* __restrict__ state, const uint8_t* __restrict__ flags,
                                                 const uint16_t* __restrict__ owner,
                                                 const DevParticle* __restrict__ parts, int np, SweepParams p,
                                                 A ad, int* __restrict__ status) {
@@ -392,20 +398,30 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
   const uint32_t N = ad.N;
   if (!(flags[c] & kSolid) || owner[c] != pi) return;
   if (cell_owner(x, y, z, parts, np, p) >= 0) return;   // still covered
-  // density from old-fluid neighbours
-  // (loops unrolled so that the neighbours' loads are in flight together)
+  // density from old-fluid neighbours.  Each stage issues its loads for all
+  // neighbours before the first use; a neighbour that does not count reads
+  // the cell itself and is dropped afterwards.
+  uint32_t nc[kQ];
+  bool nok[kQ];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    uint32_t sc = c;
+    nok[q] = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws) == 1;
+    nc[q] = nok[q] ? sc : c;
+  }
+  uint8_t nfl[kQ];
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) nfl[q] = flags[nc[q]];
   double rsum = 0.0;
   int cnt = 0;
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
-    uint32_t sc = 0;
-    if (ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws) != 1) continue;
-    if (flags[sc] & kSolid) continue;
+    const bool use = nok[q] && !(nfl[q] & kSolid);
     double r = 0.0;
 #pragma unroll
-    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + sc]);
-    rsum += 1.0 + r;
-    ++cnt;
+    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + nc[q]]);
+    rsum = use ? rsum + (1.0 + r) : rsum;
+    cnt += use ? 1 : 0;
   }
   const double rho = cnt ? rsum / cnt : 1.0;
   double off[3];
@@ -413,35 +429,41 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
   const double v[3] = {P.u[0] + (P.w[1] * off[2] - P.w[2] * off[1]),
                        P.u[1] + (P.w[2] * off[0] - P.w[0] * off[2]),
                        P.u[2] + (P.w[0] * off[1] - P.w[1] * off[0])};
-  // velocity at the six axis neighbours
+  // velocity at the six axis neighbours: fluid momentum, the rigid-body
+  // velocity of a solid neighbour's sphere, or the wall velocity; every
+  // source is read for every neighbour (the cell itself where it does not
+  // apply) and the applicable one is selected
   double Vn[3][2][3];
+  bool unstored = false;
+#pragma unroll
   for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int side = 0; side < 2; ++side) {
       int s[3] = {x, y, z};
       s[a] += side ? 1 : -1;
       double* V = Vn[a][side];
-      uint32_t sc = 0;
+      uint32_t sc = c;
       int wa2 = 0, ws2 = 0;
       const int st = ad.locate(s[0], s[1], s[2], sc, wa2, ws2);
+      const uint32_t src = st == 1 ? sc : c;
+      const bool solid = (flags[src] & kSolid) != 0;
+      const int ow = owner[src];
+      const DevParticle& Q = parts[ow < np ? ow : 0];   // a fluid cell's owner entry is not a sphere
+      double j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) {
+        const double dq = (double)Store<S>::load(state[(size_t)q * N + src]);
+        j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
+      }
       if (st == 0) {
         for (int b = 0; b < 3; ++b) V[b] = (wa2 == p.wall_axis) ? p.wall_v[ws2][b] : 0.0;
-        continue;
-      }
-      if (st < 0) {
-        status[kStatusRange] = 5;
+      } else if (st < 0) {
+        unstored = true;
         for (int b = 0; b < 3; ++b) V[b] = v[b];
-        continue;
-      }
-      if (!(flags[sc] & kSolid)) {
-        double j[3] = {0.0, 0.0, 0.0};
-        for (int q = 0; q < kQ; ++q) {
-          const double dq = (double)Store<S>::load(state[(size_t)q * N + sc]);
-          j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
-        }
+      } else if (!solid) {
         // post-collision momentum minus F/2 is the macroscopic velocity
         for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
       } else {
-        const DevParticle& Q = parts[owner[sc]];
         double o2[3];
         sphere_offset(Q.x, s[0] + 0.5, s[1] + 0.5, s[2] + 0.5, p.nx, p.ny, p.nz, p.per, o2);
         V[0] = Q.u[0] + (Q.w[1] * o2[2] - Q.w[2] * o2[1]);
@@ -449,6 +471,7 @@ __global__ __launch_bounds__(256) void k_refill(S* __restrict__ state, const uin
         V[2] = Q.u[2] + (Q.w[0] * o2[1] - Q.w[1] * o2[0]);
       }
     }
+  if (unstored) status[kStatusRange] = 5;
   double Sab[3][3];
   for (int a = 0; a < 3; ++a)
     for (int b = 0; b < 3; ++b)
