@@ -480,21 +480,34 @@ void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<
 void band_directions(const Kinds& K, Forest& f, int l) {
   Forest::Lev& V = f.lv[l];
   const int n_int = (int)V.interior.size();
+  const int ng = (int)V.ghost.size();
   V.band_dirs.assign(3 * V.band.size(), 0u);
-  std::vector<int> at(V.ghost.size() * kBlockCells, -1);   // band index of every ghost-block cell
-  for (size_t g = 0; g < V.ghost.size(); ++g)
-    for (int i = V.band_off[g]; i < V.band_off[g + 1]; ++i) at[g * kBlockCells + V.band[i]] = i;
+  std::vector<int> at((size_t)ng * kBlockCells, -1);   // band index of every ghost-block cell
+  for (int g = 0; g < ng; ++g)
+    for (int i = V.band_off[g]; i < V.band_off[g + 1]; ++i) at[(size_t)g * kBlockCells + V.band[i]] = i;
   auto band_at = [&](int i, int j, int k) -> int {
     i = Kinds::wrap1(i, V.n[0]); j = Kinds::wrap1(j, V.n[1]); k = Kinds::wrap1(k, V.n[2]);
     const int s = V.slot_of[K.bpos(l, i >> 4, j >> 4, k >> 4)];
     if (s < n_int) return -1;
     return at[(size_t)(s - n_int) * kBlockCells + (((k & 15) * kBlock + (j & 15)) * kBlock + (i & 15))];
   };
-  auto coords = [&](int b, int g, int& i, int& j, int& k) {
-    const int s = V.ghost[g], loc = V.band[b];
-    i = V.pos[3 * s] * kBlock + (loc & 15);
-    j = V.pos[3 * s + 1] * kBlock + ((loc >> 4) & 15);
-    k = V.pos[3 * s + 2] * kBlock + (loc >> 8);
+  // every band cell writes only its own masks, so ghost blocks are split
+  // over host threads
+  auto over_cells = [&](auto&& fn) {
+    const int nt = std::max(1, std::min({ng, 16, (int)std::max(1u, std::thread::hardware_concurrency())}));
+    std::vector<std::thread> pool;
+    for (int t = 0; t < nt; ++t)
+      pool.emplace_back([&, t]() {
+        for (int g = t; g < ng; g += nt) {
+          const int s = V.ghost[g];
+          for (int b = V.band_off[g]; b < V.band_off[g + 1]; ++b) {
+            const int loc = V.band[b];
+            fn(b, V.pos[3 * s] * kBlock + (loc & 15), V.pos[3 * s + 1] * kBlock + ((loc >> 4) & 15),
+               V.pos[3 * s + 2] * kBlock + (loc >> 8));
+          }
+        }
+      });
+    for (auto& th : pool) th.join();
   };
   // sub-step 2: the coalescence reads of level l - 1
   for (const IfaceEntry& e : f.lv[l - 1].iface) {
@@ -507,31 +520,25 @@ void band_directions(const Kinds& K, Forest& f, int l) {
           if (b >= 0) V.band_dirs[3 * b + 2] |= 1u << q;
         }
   }
-  // sub-step 1 and explosion: interior pulls, then the band sources of the
-  // streaming of the following sub-step
-  for (size_t g = 0; g < V.ghost.size(); ++g)
-    for (int b = V.band_off[g]; b < V.band_off[g + 1]; ++b) {
-      int i, j, k;
-      coords(b, (int)g, i, j, k);
-      uint32_t pulled = 0;
-      for (int q = 1; q < kQ; ++q)
-        if (K.kind(l, i + cx_of(q), j + cy_of(q), k + cz_of(q)) == K_INTERIOR) pulled |= 1u << q;
-      V.band_dirs[3 * b] |= pulled;
-      V.band_dirs[3 * b + 1] |= pulled;
-    }
-  for (int s = 2; s >= 1; --s)
-    for (size_t g = 0; g < V.ghost.size(); ++g)
-      for (int b = V.band_off[g]; b < V.band_off[g + 1]; ++b) {
-        const uint32_t m = V.band_dirs[3 * b + s];
-        if (!m) continue;
-        int i, j, k;
-        coords(b, (int)g, i, j, k);
-        for (int q = 1; q < kQ; ++q)
-          if (m & (1u << q)) {
-            const int src = band_at(i - cx_of(q), j - cy_of(q), k - cz_of(q));
-            if (src >= 0) V.band_dirs[3 * src + s - 1] |= 1u << q;
-          }
+  // sub-step 1 and explosion: the interior pulls, then the band sources of
+  // the streaming of the following stage (population q of cell b is such a
+  // source when the band cell b + c_q streams q in that stage)
+  over_cells([&](int b, int i, int j, int k) {
+    uint32_t pulled = 0;
+    for (int q = 1; q < kQ; ++q)
+      if (K.kind(l, i + cx_of(q), j + cy_of(q), k + cz_of(q)) == K_INTERIOR) pulled |= 1u << q;
+    V.band_dirs[3 * b] = pulled;
+    V.band_dirs[3 * b + 1] = pulled;
+  });
+  for (int st = 2; st >= 1; --st)
+    over_cells([&](int b, int i, int j, int k) {
+      uint32_t m = 0;
+      for (int q = 1; q < kQ; ++q) {
+        const int g = band_at(i + cx_of(q), j + cy_of(q), k + cz_of(q));
+        if (g >= 0 && (V.band_dirs[3 * g + st] & (1u << q))) m |= 1u << q;
       }
+      V.band_dirs[3 * b + st - 1] |= m;
+    });
 }
 
 // slot lists, ghost blocks, explosion map and coalescence table of every
