@@ -485,29 +485,39 @@ void band_directions(const Kinds& K, Forest& f, int l) {
   std::vector<int> at((size_t)ng * kBlockCells, -1);   // band index of every ghost-block cell
   for (int g = 0; g < ng; ++g)
     for (int i = V.band_off[g]; i < V.band_off[g + 1]; ++i) at[(size_t)g * kBlockCells + V.band[i]] = i;
-  auto band_at = [&](int i, int j, int k) -> int {
-    i = Kinds::wrap1(i, V.n[0]); j = Kinds::wrap1(j, V.n[1]); k = Kinds::wrap1(k, V.n[2]);
-    const int s = V.slot_of[K.bpos(l, i >> 4, j >> 4, k >> 4)];
-    if (s < n_int) return -1;
-    return at[(size_t)(s - n_int) * kBlockCells + (((k & 15) * kBlock + (j & 15)) * kBlock + (i & 15))];
-  };
-  // every band cell writes only its own masks, so ghost blocks are split
-  // over host threads
+  // Every band cell writes only its own masks, so ghost blocks are split
+  // over host threads.  A cell's neighbours lie in the 27 blocks around its
+  // own; whether a cell is interior is a property of its block (leaf level
+  // l), so per block only the neighbours' slots and leaf levels are looked up.
   auto over_cells = [&](auto&& fn) {
     const int nt = std::max(1, std::min({ng, 16, (int)std::max(1u, std::thread::hardware_concurrency())}));
     std::vector<std::thread> pool;
     for (int t = 0; t < nt; ++t)
       pool.emplace_back([&, t]() {
+        int nslot[27];
+        bool ninterior[27];
         for (int g = t; g < ng; g += nt) {
           const int s = V.ghost[g];
+          const int bi = V.pos[3 * s], bj = V.pos[3 * s + 1], bk = V.pos[3 * s + 2];
+          for (int d = 0; d < 27; ++d) {
+            const int dx = d % 3 - 1, dy = (d / 3) % 3 - 1, dz = d / 9 - 1;
+            nslot[d] = V.slot_of[K.bpos(l, bi + dx, bj + dy, bk + dz)];
+            ninterior[d] = K.block(l, bi + dx, bj + dy, bk + dz) == l;
+          }
           for (int b = V.band_off[g]; b < V.band_off[g + 1]; ++b) {
             const int loc = V.band[b];
-            fn(b, V.pos[3 * s] * kBlock + (loc & 15), V.pos[3 * s + 1] * kBlock + ((loc >> 4) & 15),
-               V.pos[3 * s + 2] * kBlock + (loc >> 8));
+            fn(b, loc & 15, (loc >> 4) & 15, loc >> 8, nslot, ninterior);
           }
         }
       });
     for (auto& th : pool) th.join();
+  };
+  // neighbour block (0..26) and local index of local cell (x, y, z) + c_q
+  auto step = [](int x, int y, int z, int q, int& d, int& loc) {
+    const int xs = x + cx_of(q), ys = y + cy_of(q), zs = z + cz_of(q);
+    const int bx = xs < 0 ? 0 : (xs > 15 ? 2 : 1), by = ys < 0 ? 0 : (ys > 15 ? 2 : 1), bz = zs < 0 ? 0 : (zs > 15 ? 2 : 1);
+    d = bz * 9 + by * 3 + bx;
+    loc = ((zs & 15) * kBlock + (ys & 15)) * kBlock + (xs & 15);
   };
   // sub-step 2: the coalescence reads of level l - 1
   for (const IfaceEntry& e : f.lv[l - 1].iface) {
@@ -523,18 +533,25 @@ void band_directions(const Kinds& K, Forest& f, int l) {
   // sub-step 1 and explosion: the interior pulls, then the band sources of
   // the streaming of the following stage (population q of cell b is such a
   // source when the band cell b + c_q streams q in that stage)
-  over_cells([&](int b, int i, int j, int k) {
+  over_cells([&](int b, int x, int y, int z, const int*, const bool* ninterior) {
     uint32_t pulled = 0;
-    for (int q = 1; q < kQ; ++q)
-      if (K.kind(l, i + cx_of(q), j + cy_of(q), k + cz_of(q)) == K_INTERIOR) pulled |= 1u << q;
+    for (int q = 1; q < kQ; ++q) {
+      int d, loc;
+      step(x, y, z, q, d, loc);
+      if (ninterior[d]) pulled |= 1u << q;
+    }
     V.band_dirs[3 * b] = pulled;
     V.band_dirs[3 * b + 1] = pulled;
   });
   for (int st = 2; st >= 1; --st)
-    over_cells([&](int b, int i, int j, int k) {
+    over_cells([&](int b, int x, int y, int z, const int* nslot, const bool*) {
       uint32_t m = 0;
       for (int q = 1; q < kQ; ++q) {
-        const int g = band_at(i + cx_of(q), j + cy_of(q), k + cz_of(q));
+        int d, loc;
+        step(x, y, z, q, d, loc);
+        const int s = nslot[d];
+        if (s < n_int) continue;
+        const int g = at[(size_t)(s - n_int) * kBlockCells + loc];
         if (g >= 0 && (V.band_dirs[3 * g + st] & (1u << q))) m |= 1u << q;
       }
       V.band_dirs[3 * b + st - 1] |= m;
