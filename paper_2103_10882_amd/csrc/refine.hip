@@ -1225,10 +1225,16 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
     if (V.n_int) {
-      // levels with few blocks: one workgroup per plane of a block, so that
-      // the launch still covers every compute unit many times (measured
-      // against 4 and 8 planes per workgroup on the 3-level workload)
-      const dim3 grid(V.n_int, V.n_int < 1024 ? 16 : 1);
+      // workgroups per block: each takes 16 / gridDim.y planes.  Every
+      // workgroup holds one plane of 256 cells in flight at a time, so the
+      // split sets how many loads the launch keeps outstanding.  Levels with
+      // few blocks take one plane per workgroup; large levels take one
+      // plane per workgroup in FP64, two in FP32 and four in FP16, about
+      // the same bytes per workgroup (measured on the 3-level workload
+      // against 1, 2, 4, 8 and 16 workgroups per block: whole blocks per
+      // workgroup were 6 / 4 / 7 % slower in FP64 / FP32 / FP16)
+      const int split = V.n_int < 1024 ? 16 : (sizeof(S) == 8 ? 16 : (sizeof(S) == 4 ? 8 : 4));
+      const dim3 grid(V.n_int, split);
       k_level_sweep<S><<<grid, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
                                                     (const int*)(c->ws + V.off_int), c->status(), a);
       HIP_TRY(c, hipGetLastError());
