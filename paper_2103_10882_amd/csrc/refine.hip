@@ -869,21 +869,27 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
   __shared__ double pre[kIfaceCells][kQ];
   const int e0 = blockIdx.x * kIfaceCells;
   const int n = min(kIfaceCells, count - e0);
+  // The source and the eight children are loaded in every thread, so that
+  // no branch separates the loads: an unused source index is 0 in the
+  // table, and a child outside the mask reads element 0 of the fine array.
   for (int p = threadIdx.x; p < n * kQ; p += blockDim.x) {
     const int j = p / kQ, q = p - j * kQ;
     const IfaceEntry& e = tab[e0 + j];
-    double v = 0.0;
     const float wq = e.weight[q];
-    if (wq != 0.0f) v = (double)wq * (double)Store<S>::load(src[(size_t)q * a.N + e.src[q]]);
+    const double sv = (double)Store<S>::load(src[(size_t)q * a.N + e.src[q]]);
+    double v = wq != 0.0f ? (double)wq * sv : 0.0;
     const unsigned mk = e.mask[q];
+    const uint32_t c0 = (uint32_t)e.fine_slot * kBlockCells + (uint32_t)e.fine_local;
+    typename Store<S>::T ch[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const uint32_t cf = (mk & (1u << m)) ? c0 + (uint32_t)(((m >> 2) * 16 + ((m >> 1) & 1)) * 16 + (m & 1)) : 0u;
+      ch[m] = Store<S>::load(fine[(size_t)q * Nf + cf]);
+    }
     if (mk) {
       double acc = 0.0;
-      for (int m = 0; m < 8; ++m)
-        if (mk & (1u << m)) {
-          const uint32_t cf = (uint32_t)e.fine_slot * kBlockCells + (uint32_t)e.fine_local +
-                              (uint32_t)(((m >> 2) * 16 + ((m >> 1) & 1)) * 16 + (m & 1));
-          acc += (double)Store<S>::load(fine[(size_t)q * Nf + cf]);
-        }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc = (mk & (1u << m)) ? acc + (double)ch[m] : acc;
       v += 0.125 * acc;
     }
     pre[j][q] = v;
