@@ -749,13 +749,32 @@ __device__ __forceinline__ void sweep_planes(const S* __restrict__ src, S* __res
                                              const LevelArgs& a, const int* nbs, int slot, int z0, int planes) {
   using T = typename Store<S>::T;
   const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  // CHECK: the pulls of a cell reach the face and edge neighbour blocks on
+  // its sides (D3Q19 has no body diagonals, so never the corner block); the
+  // cell is tested once against those instead of per direction
+  const int sx = x == 0 ? -1 : (x == 15 ? 1 : 0), sy = y == 0 ? -1 : (y == 15 ? 1 : 0);
+  auto stored = [&](int dx, int dy, int dz) { return nbs[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] >= 0; };
+  const bool xy_ok = !CHECK || (stored(sx, 0, 0) && stored(0, sy, 0) && stored(sx, sy, 0));
   for (int z = z0; z < z0 + planes; ++z) {
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
     if (flags[c]) continue;
     T d[kQ];
-    if (!pull_cell<S, CHECK>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
-      status[kStatusRange] = 6;
-      continue;
+    if constexpr (CHECK && sizeof(S) == 8) {
+      // FP64 keeps the per-direction test: the per-cell one costs it
+      // registers (occupancy 3 -> 2)
+      if (!pull_cell<S, true>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
+        status[kStatusRange] = 6;
+        continue;
+      }
+    } else {
+      if (CHECK) {
+        const int sz = z == 0 ? -1 : (z == 15 ? 1 : 0);
+        if (!(xy_ok && stored(0, 0, sz) && stored(sx, 0, sz) && stored(0, sy, sz))) {
+          status[kStatusRange] = 6;
+          continue;
+        }
+      }
+      pull_cell<S, false>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
     }
     const T drho = lbm_collide<T>(d, T(a.sp), T(a.sm), T(a.sb), T(a.F[0]), T(a.F[1]), T(a.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
