@@ -741,12 +741,12 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t lin, uint32_t G) {
   return xcd * q8 + min(xcd, r8) + ord;
 }
 
-// planes z0 .. z0 + planes - 1 of one block; CHECK: test per source that
-// its block is stored (needed only when a neighbour slot is missing)
+// plane z of one block; CHECK: test that the blocks a cell's pulls reach are
+// stored (needed only when a neighbour slot is missing)
 template <typename S, bool CHECK>
-__device__ __forceinline__ void sweep_planes(const S* __restrict__ src, S* __restrict__ dst,
-                                             const uint8_t* __restrict__ flags, int* __restrict__ status,
-                                             const LevelArgs& a, const int* nbs, int slot, int z0, int planes) {
+__device__ __forceinline__ void sweep_plane(const S* __restrict__ src, S* __restrict__ dst,
+                                            const uint8_t* __restrict__ flags, int* __restrict__ status,
+                                            const LevelArgs& a, const int* nbs, int slot, int z) {
   using T = typename Store<S>::T;
   const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
   // CHECK: the pulls of a cell reach the face and edge neighbour blocks on
@@ -755,23 +755,23 @@ __device__ __forceinline__ void sweep_planes(const S* __restrict__ src, S* __res
   const int sx = x == 0 ? -1 : (x == 15 ? 1 : 0), sy = y == 0 ? -1 : (y == 15 ? 1 : 0);
   auto stored = [&](int dx, int dy, int dz) { return nbs[(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)] >= 0; };
   const bool xy_ok = !CHECK || (stored(sx, 0, 0) && stored(0, sy, 0) && stored(sx, sy, 0));
-  for (int z = z0; z < z0 + planes; ++z) {
+  {
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
-    if (flags[c]) continue;
+    if (flags[c]) return;
     T d[kQ];
     if constexpr (CHECK && sizeof(S) == 8) {
       // FP64 keeps the per-direction test: the per-cell one costs it
       // registers (occupancy 3 -> 2)
       if (!pull_cell<S, true>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
         status[kStatusRange] = 6;
-        continue;
+        return;
       }
     } else {
       if (CHECK) {
         const int sz = z == 0 ? -1 : (z == 15 ? 1 : 0);
         if (!(xy_ok && stored(0, 0, sz) && stored(sx, 0, sz) && stored(0, sy, sz))) {
           status[kStatusRange] = 6;
-          continue;
+          return;
         }
       }
       pull_cell<S, false>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
@@ -785,7 +785,9 @@ __device__ __forceinline__ void sweep_planes(const S* __restrict__ src, S* __res
 }
 
 // interior blocks of a level: pull + collide, cells with flags left out.
-// gridDim.y workgroups share a block, each taking kBlock / gridDim.y planes.
+// One workgroup per plane of a block (gridDim.y = 16), one thread per cell:
+// straight-line code needs 62 registers in FP16 and FP32 (124 in FP64)
+// against 109 (166) for a loop over planes, and holds twice the waves.
 // FP32 and FP16 storage number the work XCD-contiguously (3-4 % faster on the
 // 3-level workload); FP64 keeps launch order (3 % slower otherwise).
 template <typename S>
@@ -804,10 +806,10 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
     all_stored = ok;
   }
   __syncthreads();
-  const int planes = kBlock / gridDim.y, z0 = (int)(item % gridDim.y) * planes;
+  const int z = (int)(item % gridDim.y);
   // one test per workgroup instead of one per direction and cell
-  if (all_stored) sweep_planes<S, false>(src, dst, flags, status, a, nbs, slot, z0, planes);
-  else sweep_planes<S, true>(src, dst, flags, status, a, nbs, slot, z0, planes);
+  if (all_stored) sweep_plane<S, false>(src, dst, flags, status, a, nbs, slot, z);
+  else sweep_plane<S, true>(src, dst, flags, status, a, nbs, slot, z);
 }
 
 // ghost cells (the band of each ghost block listed in band[band_off[g] ..
@@ -1250,16 +1252,9 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
     if (V.n_int) {
-      // workgroups per block: each takes 16 / gridDim.y planes.  Every
-      // workgroup holds one plane of 256 cells in flight at a time, so the
-      // split sets how many loads the launch keeps outstanding.  Levels with
-      // few blocks take one plane per workgroup; large levels take one
-      // plane per workgroup in FP64, two in FP32 and four in FP16, about
-      // the same bytes per workgroup (measured on the 3-level workload
-      // against 1, 2, 4, 8 and 16 workgroups per block: whole blocks per
-      // workgroup were 6 / 4 / 7 % slower in FP64 / FP32 / FP16)
-      const int split = V.n_int < 1024 ? 16 : (sizeof(S) == 8 ? 16 : (sizeof(S) == 4 ? 8 : 4));
-      const dim3 grid(V.n_int, split);
+      // one workgroup per plane of each block (measured on the 3-level
+      // workload against whole blocks and 2, 4 or 8 planes per workgroup)
+      const dim3 grid(V.n_int, kBlock);
       k_level_sweep<S><<<grid, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
                                                     (const int*)(c->ws + V.off_int), c->status(), a);
       HIP_TRY(c, hipGetLastError());
