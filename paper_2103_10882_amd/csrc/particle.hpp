@@ -301,6 +301,133 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
   }
 }
 
+// Particle-link cells of sphere pi with four lanes per cell: lane s builds
+// the incoming populations of directions q = 1 + s + 4k with the rules of
+// boundary_cell (plain pull, halfway wall, Eq. 10 on particle links) and
+// accumulates their link forces and torques; the group's populations meet
+// in LDS, and its first lane collides and stores the cell.  A wave so runs
+// a quarter of the per-direction chain of one cell per lane.  Force and
+// torque partials go to the same per-wave slots as k_boundary_particles.
+constexpr int kLinkLanes = 8;
+template <typename S, typename A>
+__global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S* __restrict__ dst,
+                                                    const uint8_t* __restrict__ flags,
+                                                    const uint16_t* __restrict__ owner,
+                                                    const DevParticle* __restrict__ parts,
+                                                    const uint32_t* __restrict__ links, const int* __restrict__ llen,
+                                                    double* __restrict__ slots, int* __restrict__ status,
+                                                    SweepParams p, A ad) {
+  using T = typename Store<S>::T;
+  constexpr int kCells = 256 / kLinkLanes;
+  __shared__ T din[kCells][kQ];
+  const int pi = blockIdx.y;
+  const int len = llen[pi];
+  const uint32_t* list = links + (size_t)pi * ((size_t)p.box * p.box * p.box);
+  const uint32_t N = ad.N;
+  const int n[3] = {p.nx, p.ny, p.nz};
+  const int g = threadIdx.x / kLinkLanes, s = threadIdx.x % kLinkLanes;
+  double px[3], pu[3], pw[3];
+  for (int a = 0; a < 3; ++a) { px[a] = parts[pi].x[a]; pu[a] = parts[pi].u[a]; pw[a] = parts[pi].w[a]; }
+  const double pr = parts[pi].r;
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  bool bad_list = false, unstored = false, foreign = false;
+  // rounds are uniform over the workgroup (base depends on blockIdx only)
+  for (int base = blockIdx.x * kCells; base < len; base += gridDim.x * kCells) {
+    const int i = base + g;
+    int x = 0, y = 0, z = 0;
+    uint32_t c = 0;
+    bool active = i < len;
+    if (active && !link_cell<A>(flags, owner, parts, pi, (int)list[i], p, ad, x, y, z, c)) {
+      bad_list = true;
+      active = false;
+    }
+    if (active) {
+      if (s == 0) din[g][0] = Store<S>::load(src[c]);
+#pragma unroll
+      for (int k = 0; k < (kQ - 2) / kLinkLanes + 1; ++k) {
+        const int q = 1 + s + kLinkLanes * k;
+        if (q >= kQ) break;
+        const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
+        const int qq = opp_of(q);
+        int wa = 0, ws = 0;
+        uint32_t si = c;
+        const int st = ad.locate(x - cq[0], y - cq[1], z - cq[2], si, wa, ws);
+        unstored = unstored || st < 0;
+        si = st < 0 ? c : si;
+        const uint8_t sf = st == 1 ? flags[si] : 0;
+        const int pq = owner[si];
+        int wa2 = 0, ws2 = 0;
+        uint32_t ti = c;
+        const int st2 = ad.locate(x + cq[0], y + cq[1], z + cq[2], ti, wa2, ws2);
+        ti = st2 == 1 ? ti : c;
+        const uint8_t tf = flags[ti];
+        const T v = Store<S>::load(src[(size_t)q * N + si]);
+        const T own_q = Store<S>::load(src[(size_t)q * N + c]);
+        const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
+        const bool wall = st == 0, link = wall || (sf & kSolid);
+        const bool tok = link && !wall && st2 == 1 && !(tf & kSolid);
+        const T sec = Store<S>::load(src[(size_t)qq * N + (tok ? ti : c)]);
+        T out = v;
+        if (link && wall) {
+          // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
+          double cv = 0.0;
+          if (wa == p.wall_axis)
+            cv = -(cq[0] * p.wall_v[ws][0] + cq[1] * p.wall_v[ws][1] + cq[2] * p.wall_v[ws][2]);
+          out = own_qq - T(6.0 * w_of(q) * cv);
+        } else if (link) {
+          foreign = foreign || pq != pi;
+          double off[3];
+          sphere_offset(px, x + 0.5, y + 0.5, z + 0.5, n[0], n[1], n[2], p.per, off);
+          const double delta = ray_delta(off, -cq[0], -cq[1], -cq[2], pr);
+          const double rb[3] = {off[0] - delta * cq[0], off[1] - delta * cq[1], off[2] - delta * cq[2]};
+          const double vw[3] = {pu[0] + (pw[1] * rb[2] - pw[2] * rb[1]),
+                                pu[1] + (pw[2] * rb[0] - pw[0] * rb[2]),
+                                pu[2] + (pw[0] * rb[1] - pw[1] * rb[0])};
+          double kappa = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
+          double alpha = 4.0 / (1.0 + 2.0 * delta);
+          if (!tok) { kappa = 0.0; alpha = 2.0; }
+          const double cqv = -(cq[0] * vw[0] + cq[1] * vw[1] + cq[2] * vw[2]);
+          T val = own_qq - T(3.0 * alpha * w_of(q) * cqv);
+          if (tok) val = val + T(kappa) * (sec - own_q);
+          out = val;
+          const double a0 = (double)own_qq, a1 = (double)val;
+          double Fq[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) Fq[a] = (-cq[a] - vw[a]) * a0 + (-cq[a] + vw[a]) * a1;
+          Fl[0] += Fq[0]; Fl[1] += Fq[1]; Fl[2] += Fq[2];
+          Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
+          Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
+          Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
+        }
+        din[g][q] = out;
+      }
+    }
+    __syncthreads();
+    if (active && s == 0) {
+      T d[kQ];
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) d[q] = din[g][q];
+      const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+      if (!(drho == drho)) status[kStatusUnstable] = 1;
+      SrBits rb(c, p.seed);
+#pragma unroll
+      for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store_sr(d[q], rb.next());
+    }
+    __syncthreads();
+  }
+  if (bad_list) status[kStatusRange] = 9;
+  if (unstored) status[kStatusRange] = 5;
+  if (foreign) status[kStatusRange] = 2;
+  double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
+  if ((threadIdx.x & 63) == 0) {
+    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * 6;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) o[j] = v[j];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // mapping (Sec. 2.3): a cell is solid for the first sphere whose centre lies
 // within r of its centre; a fluid cell next to a solid one carries the

@@ -37,6 +37,10 @@ namespace vm {
 namespace {
 
 constexpr uint8_t kIface = 0x10;   // interior cell with a coalescence pull
+// workgroups per sphere of the finest level's link-cell pass: 256 / lanes
+// cells each, 8192 cells a round, so that a sphere's link cells (about
+// 4 pi r^2) fit one round up to r ~ 25
+constexpr int kRefineLinkGroups = 32 * kLinkLanes;
 // deepest hierarchy: the per-level seeds step by 8 per finest step, and the
 // migration kernel takes per-level tables by value
 constexpr int kMaxLevels = 8;
@@ -1275,7 +1279,7 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
     if (l == f.L && np) {
       const SweepParams p = finest_params(c);
       const LinkLists ll = c->links();
-      k_boundary_particles<S, BAddr><<<dim3(kLinkGroups, np), dim3(256), 0, c->stream>>>(
+      k_link_cells<S, BAddr><<<dim3(kRefineLinkGroups, np), dim3(256), 0, c->stream>>>(
           (const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags), (const uint16_t*)(c->ws + f.off_owner),
           c->parts(), ll.links, ll.len, c->slots(), c->status(), p, finest_addr(c));
       HIP_TRY(c, hipGetLastError());
@@ -1500,7 +1504,7 @@ int refine_plan(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  c->slot_stride = (size_t)kLinkGroups * 4 * 6;
+  c->slot_stride = (size_t)kRefineLinkGroups * 4 * 6;
   const int np = (int)c->spheres.size();
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };
