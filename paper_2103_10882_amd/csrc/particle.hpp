@@ -301,13 +301,15 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
   }
 }
 
-// Particle-link cells of sphere pi with four lanes per cell: lane s builds
-// the incoming populations of directions q = 1 + s + 4k with the rules of
-// boundary_cell (plain pull, halfway wall, Eq. 10 on particle links) and
-// accumulates their link forces and torques; the group's populations meet
-// in LDS, and its first lane collides and stores the cell.  A wave so runs
-// a quarter of the per-direction chain of one cell per lane.  Force and
-// torque partials go to the same per-wave slots as k_boundary_particles.
+// Particle-link cells of sphere pi with kLinkLanes lanes per cell: lane s
+// builds the incoming populations of directions q = 1 + s + kLinkLanes k
+// with the rules of boundary_cell (plain pull, halfway wall, Eq. 10 on
+// particle links) and accumulates their link forces and torques; the
+// group's populations meet in LDS, and its first lane collides and stores
+// the cell.  A lane so runs the per-direction chain of two or three
+// directions instead of eighteen (measured against 1, 2, 4 and 16 lanes on
+// the 3-level workload).  Force and torque partials go to per-wave slots as
+// in k_boundary_particles, one per wave of the launch.
 constexpr int kLinkLanes = 8;
 template <typename S, typename A>
 __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S* __restrict__ dst,
