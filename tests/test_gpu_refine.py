@@ -472,3 +472,46 @@ def test_rotation_only_sphere_refined(env):
     rel = compare_levels(sim, ref, 2)
     say(f"  w {wg}, population rel err {rel:.2e}")
     assert rel <= 1e-11
+
+
+def test_large_sphere_refined(env):
+    """A sphere of radius 27 on the finest level of a 2-level grid: more link
+    cells than the finest level's link-cell pass takes in one round (256
+    workgroups of 32 cells), so its later rounds run; F/T every coarse step,
+    the particle and the populations follow the oracle."""
+    pkg, oracle = env
+    n0 = (96, 64, 64)          # room for level-0 leaves beyond the sphere's box in x
+    r = 27.0
+    centre = (64.3, 63.8, 64.4)
+    c = cfg_of(n0, 2, omega=1.7, F=(1e-6, -2e-6, 3e-6))
+    s = synth.sphere(centre, r, density_ratio=20.0, cv=0.5, fixed=False, u=(0.01, -0.005, 0.02))
+    # link cells: fluid cells with a D3Q19 neighbour inside the sphere
+    Z, Y, X = np.meshgrid(np.arange(128) + 0.5, np.arange(128) + 0.5, np.arange(192) + 0.5, indexing="ij")
+    inside = (X - centre[0]) ** 2 + (Y - centre[1]) ** 2 + (Z - centre[2]) ** 2 <= r * r
+    near = np.zeros_like(inside)
+    for q in range(1, 19):
+        cx, cy, cz = oracle.lattice()[0][q]
+        near |= np.roll(inside, (-int(cz), -int(cy), -int(cx)), axis=(0, 1, 2))
+    n_links = int((near & ~inside).sum())
+    assert n_links > 256 * 32, n_links
+    u0 = synth.velocity_perturbation(n0, seed=23)
+    say(f"case refined96x64x64 L2 large sphere r={r} ({n_links} link cells) f64")
+    sim = pkg.Sim(c, [s], storage="f64", history=8, check_every=4)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, spheres=[s], check_every=4)
+    ref.init(1.0, u0)
+    assert 0 < len(sim.level_blocks(0)) and 0 < len(sim.level_blocks(1))
+    for k in range(1, 5):
+        sim.step(1)
+        ref.step(1)
+        Fg, Tg = sim.force_torque(0)
+        Fo, To = ref.force_torque(0)
+        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), r * np.abs(Fo).max()), (k, Tg, To)
+    sim.sync()
+    xg, ug, _ = sim.particle(0)
+    xo, uo, _ = ref.particle(0)
+    assert np.abs(xg - xo).max() < 1e-11 and np.abs(ug - uo).max() < 1e-12
+    rel = compare_levels(sim, ref, 2)
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-11
