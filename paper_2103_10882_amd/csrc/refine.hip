@@ -70,6 +70,7 @@ struct Forest {
   bool flow = false;          // curl-sensor criterion on
   int refinements = 0;
   long long coarse_steps = 0;
+  bool side_pending = false;  // a particle update runs on the side stream
   struct Lev {
     int n[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
     long npos = 0;
@@ -1245,9 +1246,22 @@ int explode(vmlbm_ctx* c, int l) {
   });
 }
 
+// the main stream waits for a particle update left on the side stream
+int join_side(vmlbm_ctx* c) {
+  Forest& f = *c->forest;
+  if (!f.side_pending) return VMLBM_OK;
+  HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  f.side_pending = false;
+  return VMLBM_OK;
+}
+
 // sub: 0 or 1, the first or second step of level l within a level-(l-1) step
 int sweep_level(vmlbm_ctx* c, int l, int sub) {
   Forest& f = *c->forest;
+  if (l == f.L) {
+    int rj = join_side(c);
+    if (rj) return rj;
+  }
   Forest::Lev& V = f.lv[l];
   const LevelArgs a = level_args(c, l, V.tab);
   void* src = c->ws + V.off_pdf[V.cur];
@@ -1297,28 +1311,42 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
       u.step = (int)(c->fine_steps_done % std::max(c->cfg.history, 1));
       u.hist_len = std::max(c->cfg.history, 1);
       u.np = np;
-      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, u, c->stream));
+      // After the second of two finest steps the coarser level's sweep
+      // comes next and touches no particle data, so the particle update
+      // runs beside it on the side stream; the next finest step, the end
+      // of the coarse step and the layout check join it.
+      hipStream_t ps = c->stream;
+      if (sub == 1 && f.L > 0) {
+        HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
+        HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        ps = c->side;
+      }
+      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, u, ps));
       if (c->moving) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;
           const int rb = p.box + 1;
           dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
-          k_refill<S, BAddr><<<grid, block, 0, c->stream>>>((S*)(c->ws + V.off_pdf[V.cur]),
+          k_refill<S, BAddr><<<grid, block, 0, ps>>>((S*)(c->ws + V.off_pdf[V.cur]),
                                                              (const uint8_t*)(c->ws + V.off_flags),
                                                              (const uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
                                                              finest_addr(c), c->status());
           HIP_TRY(c, hipGetLastError());
-          k_remap<BAddr><<<grid, block, 0, c->stream>>>((uint8_t*)(c->ws + V.off_flags),
-                                                        (uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
-                                                        finest_addr(c), c->status());
+          k_remap<BAddr><<<grid, block, 0, ps>>>((uint8_t*)(c->ws + V.off_flags),
+                                                 (uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
+                                                 finest_addr(c), c->status());
           HIP_TRY(c, hipGetLastError());
           const LinkLists ll = c->links();
           HIP_TRY(c, launch_link_lists<BAddr>((const uint8_t*)(c->ws + V.off_flags),
                                               (const uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
-                                              finest_addr(c), ll.count, ll.links, ll.len, c->stream));
+                                              finest_addr(c), ll.count, ll.links, ll.len, ps));
           return VMLBM_OK;
         });
         if (rc) return rc;
+      }
+      if (ps != c->stream) {
+        HIP_TRY(c, hipEventRecord(c->ev_join, c->side));
+        f.side_pending = true;
       }
     }
     c->fine_steps_done += 1;
@@ -1619,6 +1647,8 @@ int refine_step(vmlbm_ctx* c, int n) {
   Forest& f = *c->forest;
   for (int s = 0; s < n; ++s) {
     int rc = step_level(c, 0, 0);
+    if (rc) return rc;
+    rc = join_side(c);
     if (rc) return rc;
     c->steps_done += 1;
     f.coarse_steps += 1;
