@@ -71,6 +71,7 @@ struct Forest {
   int refinements = 0;
   long long coarse_steps = 0;
   bool side_pending = false;  // a particle update runs on the side stream
+  DevParticle* host_parts = nullptr;  // pinned copy of the particle records for the layout check
   struct Lev {
     int n[3] = {0, 0, 0}, nb[3] = {0, 0, 0};
     long npos = 0;
@@ -1116,7 +1117,10 @@ __global__ __launch_bounds__(256) void k_migrate(S* __restrict__ dst, const int*
   }
 }
 
-void forest_free(Forest* f) { delete f; }
+void forest_free(Forest* f) {
+  if (f && f->host_parts) (void)hipHostFree(f->host_parts);
+  delete f;
+}
 
 }  // namespace
 
@@ -1417,13 +1421,15 @@ int check_layout(vmlbm_ctx* c) {
   Forest& f = *c->forest;
   const int np = (int)c->spheres.size();
   std::vector<vmlbm_sphere> sph = c->spheres;
+  // the positions come back by one copy on the stream into pinned memory,
+  // queued behind the step, and one synchronisation
+  if (np && !f.host_parts)
+    HIP_TRY(c, hipHostMalloc((void**)&f.host_parts, np * sizeof(DevParticle), hipHostMallocDefault));
+  if (np)
+    HIP_TRY(c, hipMemcpyAsync(f.host_parts, c->parts(), np * sizeof(DevParticle), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (np) {
-    std::vector<DevParticle> hp(np);
-    HIP_TRY(c, hipMemcpy(hp.data(), c->parts(), np * sizeof(DevParticle), hipMemcpyDeviceToHost));
-    for (int i = 0; i < np; ++i)
-      for (int a = 0; a < 3; ++a) sph[i].x[a] = hp[i].x[a];
-  }
+  for (int i = 0; i < np; ++i)
+    for (int a = 0; a < 3; ++a) sph[i].x[a] = f.host_parts[i].x[a];
   std::vector<int> box = sphere_boxes(sph);
   if (box == f.boxes && !f.flow) return VMLBM_OK;
   std::vector<int8_t> t = layout_targets(f, box);
