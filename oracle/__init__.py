@@ -62,6 +62,8 @@ def lib():
             ("ora_init", [vp, ctypes.c_double, ctypes.c_void_p]),
             ("ora_init_fields", [vp, ctypes.c_void_p, ctypes.c_void_p]),
             ("ora_step", [vp, ctypes.c_int]),
+            ("ora_refill_cell", [vp, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int, ctypes.c_void_p]),
             ("ora_post_collision", [vp, ctypes.c_void_p]),
             ("ora_pre_collision", [vp, ctypes.c_void_p]),
             ("ora_owner", [vp, ctypes.c_void_p]),
@@ -245,6 +247,20 @@ class Uniform:
 
     def step(self, n=1):
         _check(lib().ora_step(self.h, int(n)), "step")
+
+    def refill_cell(self, f_pre, old_owner, cell, pid):
+        """Refill of cell (x, y, z) uncovered by sphere pid, computed on the
+        pre-collision state f_pre [19][nz][ny][nx] with the mapping before
+        the re-mapping old_owner [nz][ny][nx] (-1 fluid); replaces the
+        oracle's state by f_pre.  Returns the cell's 19 populations."""
+        f = np.ascontiguousarray(f_pre, dtype=np.float64)
+        o = np.ascontiguousarray(old_owner, dtype=np.int32)
+        assert f.size == 19 * self.N and o.size == self.N
+        out = np.zeros(19)
+        x, y, z = (int(v) for v in cell)
+        _check(lib().ora_refill_cell(self.h, f.ctypes.data, o.ctypes.data, x, y, z, int(pid), out.ctypes.data),
+               "refill_cell")
+        return out
 
     def _shape(self):
         nx, ny, nz = self.n

@@ -10,12 +10,11 @@
 // Readings of points the paper leaves open are marked "reading:".
 //
 // Pins (tests/test_oracle_pins.py, tests/test_oracle_refine.py): every
-// function is checked against closed forms, invariants or brute force,
-// except one part: the estimate of the velocity gradient used by the refill
-// (central differences over the axis neighbours) is parity unpinned -- the
-// paper only cites the refill scheme.  The refill populations for a given
-// strain rate are pinned by their moments (density, momentum, and the
-// Chapman-Enskog first-order stress).
+// function is checked against closed forms, invariants or brute force.  The
+// refill (the paper only cites its scheme) is pinned in two parts: its
+// populations for a given strain rate by their moments (density, momentum,
+// and the Chapman-Enskog first-order stress), and its estimate of the strain
+// rate by linear velocity fields, on which central differences are exact.
 //
 // Only tests/, the smoke check and the benchmark's CPU-baseline leg load this
 // library.  It shares no code with the GPU library.
@@ -462,6 +461,21 @@ int ora_set_sphere_motion(void* h, int id, const double u[3], const double w[3],
     s.u[a] = fixed ? 0.0 : u[a];
     s.w[a] = fixed == 1 ? 0.0 : w[a];
   }
+  return 0;
+}
+
+// the refill of one cell on a given pre-collision state and old mapping
+// (test entry point for the gradient estimate)
+int ora_refill_cell(void* h, const double* f_pre, const int* old_owner, int x, int y, int z, int pid,
+                    double out[19]) {
+  auto* G = static_cast<Grid<double>*>(h);
+  if (!G || !f_pre || !old_owner || !out || pid < 0 || pid >= (int)G->sph.size()) return -1;
+  if (x < 0 || y < 0 || z < 0 || x >= G->nx || y >= G->ny || z >= G->nz) return -1;
+  G->fn.assign(f_pre, f_pre + 19 * G->N);
+  std::vector<int> old_own(old_owner, old_owner + G->N);
+  refill_cell(*G, old_own, x, y, z, pid);
+  const long c = G->idx(x, y, z);
+  for (int q = 0; q < 19; ++q) out[q] = G->fn[q * G->N + c];
   return 0;
 }
 

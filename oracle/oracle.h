@@ -7,10 +7,10 @@
  * the smoke check and the benchmark's CPU-baseline leg load it.  It shares no
  * code, header, table or helper with the GPU library.
  *
- * Parity unpinned: the estimate of the velocity gradient that the refill of
- * an uncovered cell uses (central differences over the axis neighbours, a
- * reading of a scheme the paper only cites).  The refill populations given
- * a strain rate are pinned by their moments.
+ * The refill of an uncovered cell follows a scheme the paper only cites; its
+ * populations given a strain rate are pinned by their moments, and its
+ * strain-rate estimate (central differences over the axis neighbours) by
+ * linear velocity fields, which it must reproduce exactly.
  *
  * Conventions: lattice units of the finest level; cell (i,j,k) has its centre
  * at (i+1/2, j+1/2, k+1/2); population arrays are [19][nz][ny][nx] C order.
@@ -70,6 +70,13 @@ int ora_init(void* h, double rho, const double* u0 /* [3][nz][ny][nx] or NULL */
 /* same with a density per cell ([nz][ny][nx]) */
 int ora_init_fields(void* h, const double* rho, const double* u0);
 int ora_step(void* h, int nsteps);
+/* Refill of cell (x,y,z) uncovered by sphere pid (Sec. 2.3), computed on the
+ * pre-collision state f_pre [19][cells] with the mapping before the
+ * re-mapping old_owner [cells] (-1 fluid, else sphere id), with the spheres'
+ * current states; out[19] = its pre-collision populations.  The grid's own
+ * state is replaced by f_pre.  Test entry point. */
+int ora_refill_cell(void* h, const double* f_pre, const int* old_owner, int x, int y, int z, int pid,
+                    double out[19]);
 int ora_post_collision(void* h, double* out);  /* f~(n), solid cells = 0 */
 int ora_pre_collision(void* h, double* out);   /* f(n), solid cells = 0 */
 int ora_owner(void* h, int* out);              /* -1 fluid, else sphere id */

@@ -307,6 +307,129 @@ def test_refill_populations_moments(ora):
         assert np.abs(ora.refill_populations(rho, v, np.zeros((3, 3)), omega) - ora.equilibrium(rho, v)).max() == 0.0
 
 
+def _refill_case(ora, n, periodic, wall_velocity, X0, field, rho_of, F, spheres, old_solid, omega=1.3):
+    """Pre-collision state whose fluid cells hold f^eq(rho, u - F/2), so that
+    the oracle's velocity u = sum c f + F/2 equals field(x) at the cell
+    centre x; old_solid maps cells to the sphere that covered them before the
+    re-mapping (their populations are garbage and must not be read).  Returns
+    the refilled populations of X0 (uncovered by sphere 0), the density,
+    velocity and strain rate recovered from their moments, and the mean
+    density of the neighbours that held fluid."""
+    cfg = synth.base_config(n, periodic=periodic, omega=omega, body_force=F, wall_velocity=wall_velocity)
+    ref = ora.Uniform(cfg, spheres)
+    nx, ny, nz = n
+    f = np.zeros((19, nz, ny, nx))
+    own = -np.ones((nz, ny, nx), dtype=np.int32)
+    rng = np.random.default_rng(7)
+    for (x, y, z), pid in old_solid.items():
+        own[z, y, x] = pid
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if own[z, y, x] >= 0:
+                    f[:, z, y, x] = rng.uniform(-3.0, 3.0, 19)
+                    continue
+                xc = np.array([x + 0.5, y + 0.5, z + 0.5])
+                f[:, z, y, x] = ora.equilibrium(rho_of(x, y, z), field(xc) - 0.5 * np.asarray(F))
+    own[X0[2], X0[1], X0[0]] = 0
+    f[:, X0[2], X0[1], X0[0]] = rng.uniform(-3.0, 3.0, 19)
+    out = ref.refill_cell(f, own, X0, 0)
+    c, _, _ = ora.lattice()
+    rho = out.sum()
+    v = c.T @ out
+    Pi = np.einsum("qa,qb,q->ab", c, c, out)
+    S = -1.5 * omega * (Pi - rho / 3.0 * np.eye(3) - np.outer(v, v))
+    rhos = []
+    for q in range(1, 19):
+        k = [X0[a] + c[q, a] for a in range(3)]
+        if any(not periodic[a] and not 0 <= k[a] < n[a] for a in range(3)):
+            continue
+        k = [k[a] % n[a] for a in range(3)]
+        if own[k[2], k[1], k[0]] < 0:
+            rhos.append(rho_of(*k))
+    return rho, v, S, np.mean(rhos), len(rhos)
+
+
+def _rigid(s, xc):
+    d = np.asarray(xc) - np.asarray(s["x"])
+    return np.asarray(s["u"]) + np.cross(s["w"], d)
+
+
+def test_refill_gradient_linear_field(ora):
+    """Refill strain-rate estimate (Sec. 2.3, after the cited Dorschner
+    refill): central differences over the six axis neighbours are exact for
+    a linear velocity field u = u0 + A (x - x0), so the refilled cell must
+    carry S = (A + A^T)/2 to round-off, for a non-symmetric A (the skew part
+    cannot reach the populations: c_q c_q - I/3 is symmetric); its density
+    is the mean over the D3Q19 neighbours that held fluid (a neighbour
+    covered by another sphere before the re-mapping is left out, whatever
+    its populations), and its velocity the rigid-body velocity of the sphere
+    that uncovered it.  The body force checks the F/2 shift of the
+    neighbours' velocity."""
+    n = (7, 7, 7)
+    X0 = (3, 3, 3)
+    x0 = np.array(X0) + 0.5
+    A = np.array([[2e-3, -7e-3, 4e-3], [5e-3, -1e-3, 6e-3], [-3e-3, 8e-3, -1e-3]])
+    u0 = np.array([0.02, -0.01, 0.015])
+    field = lambda xc: u0 + A @ (xc - x0)
+    rho_of = lambda x, y, z: 1.0 + 1e-3 * (3 * x - 2 * y + z) + 1e-4 * x * y
+    s0 = synth.sphere((5.1, 2.7, 3.4), 1.2, fixed=False, u=(0.01, 0.02, -0.005), w=(0.003, -0.002, 0.004))
+    s1 = synth.sphere((5.6, 5.4, 3.5), 1.0, fixed=False, u=(-0.01, 0.0, 0.0), w=(0.0, 0.0, 0.01))
+    rho, v, S, rho_mean, cnt = _refill_case(ora, n, (1, 1, 1), ((0, 0, 0), (0, 0, 0)), X0, field, rho_of,
+                                            (2e-5, -1e-5, 3e-5), [s0, s1], {(4, 4, 3): 1})
+    assert cnt == 17
+    assert abs(rho - rho_mean) < 1e-15
+    assert np.abs(v - _rigid(s0, x0)).max() < 1e-16
+    Ssym = 0.5 * (A + A.T)
+    assert np.abs(S - Ssym).max() < 1e-14
+
+
+def test_refill_gradient_solid_neighbour(ora):
+    """A solid axis neighbour takes the rigid-body velocity of the sphere
+    covering it, at its own cell centre.  The fluid field is that sphere's
+    rigid motion plus B (x - x0) with B e_x = 0, so it passes through the
+    solid neighbour at +x exactly, and S = (B + B^T)/2 (the rigid rotation
+    is skew and drops out).  Taking the fluid velocity of the solid cell, the
+    rigid velocity of the other sphere, or the rigid velocity at the refilled
+    cell's centre each moves S by at least the rotation rate."""
+    n = (7, 7, 7)
+    X0 = (3, 3, 3)
+    x0 = np.array(X0) + 0.5
+    B = np.array([[0.0, 3e-3, -2e-3], [0.0, 1e-3, 5e-3], [0.0, -4e-3, 2e-3]])
+    s0 = synth.sphere((1.9, 3.6, 3.3), 1.1, fixed=False, u=(0.01, -0.02, 0.0), w=(-0.004, 0.002, 0.006))
+    s1 = synth.sphere((5.2, 3.4, 3.6), 0.9, fixed=False, u=(0.004, 0.01, -0.003), w=(0.008, -0.006, 0.01))
+    field = lambda xc: _rigid(s1, xc) + B @ (xc - x0)
+    rho_of = lambda x, y, z: 1.0 - 2e-3 * z + 1e-3 * x
+    rho, v, S, rho_mean, cnt = _refill_case(ora, n, (1, 1, 1), ((0, 0, 0), (0, 0, 0)), X0, field, rho_of,
+                                            (0.0, 0.0, 1e-5), [s0, s1], {(4, 3, 3): 1})
+    assert cnt == 17
+    assert abs(rho - rho_mean) < 1e-15
+    assert np.abs(v - _rigid(s0, x0)).max() < 1e-16
+    Bsym = 0.5 * (B + B.T)
+    assert np.abs(S - Bsym).max() < 1e-14
+
+
+def test_refill_gradient_wall_neighbour(ora):
+    """An axis neighbour beyond a no-slip wall takes the wall's velocity
+    (reading: as the value at that neighbour's centre, one cell from the
+    refilled cell).  A linear field through the wall velocity at that point
+    is then reproduced exactly: S = (A + A^T)/2."""
+    n = (7, 7, 6)
+    X0 = (3, 3, 0)
+    x0 = np.array(X0) + 0.5
+    Uw = np.array([0.012, -0.007, 0.0])
+    A = np.array([[1e-3, 2e-3, 6e-3], [-2e-3, 3e-3, -5e-3], [4e-3, 1e-3, -4e-3]])
+    field = lambda xc: Uw + A @ (xc - (x0 - np.array([0.0, 0.0, 1.0])))
+    rho_of = lambda x, y, z: 1.0 + 1e-3 * (x - y) + 2e-3 * z
+    s0 = synth.sphere((3.3, 5.2, 1.8), 1.3, fixed=False, u=(0.005, 0.0, 0.01), w=(0.0, 0.004, -0.002))
+    rho, v, S, rho_mean, cnt = _refill_case(ora, n, (1, 1, 0), (tuple(Uw), (0, 0, 0)), X0, field, rho_of,
+                                            (1e-5, 0.0, 0.0), [s0], {})
+    assert cnt == 13
+    assert abs(rho - rho_mean) < 1e-15
+    assert np.abs(v - _rigid(s0, x0)).max() < 1e-16
+    assert np.abs(S - 0.5 * (A + A.T)).max() < 1e-14
+
+
 # --------------------------------------------------------------------------
 # particle update (Sec. 2.2, Sec. 3.3, Algorithm 1): closed forms
 # --------------------------------------------------------------------------
