@@ -208,7 +208,9 @@ int vmlbm_level_blocks(vmlbm_ctx* ctx, int level, int* count, int* origin);
 int vmlbm_refinements(vmlbm_ctx* ctx, int* count);
 
 /* Set the differentiable parameters: body force magnitude along +z and
- * omega (Lambda held fixed, so s- follows omega). */
+ * omega (Lambda held fixed, so s- follows omega).  Checkpoints of an earlier
+ * vmlbm_forward_ckpt no longer count: vmlbm_adjoint then needs a new forward
+ * pass. */
 int vmlbm_set_params(vmlbm_ctx* ctx, double body_force_z, double omega);
 
 /* Forward pass for the time-averaged drag of a fixed sphere:
@@ -219,7 +221,8 @@ int vmlbm_forward_ckpt(vmlbm_ctx* ctx, int sphere, int n_steps, int avg_from, in
                        double* J);
 
 /* Reverse pass of the last vmlbm_forward_ckpt: grad = dJ * (dJ/dF_z, dJ/domega)
- * by the discrete adjoint with segment recomputation. */
+ * by the discrete adjoint with segment recomputation.  VMLBM_ESTATE if no
+ * forward pass ran since the parameters were last set. */
 int vmlbm_adjoint(vmlbm_ctx* ctx, double dJ, double grad[2]);
 
 /* Destroy the context (the workspace stays the caller's). */

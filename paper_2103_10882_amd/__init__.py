@@ -317,12 +317,23 @@ class Sim:
     # --- differentiation ------------------------------------------------------
     def set_params(self, body_force_z, omega):
         self._check(self.L.vmlbm_set_params(self.h, float(body_force_z), float(omega)), "set_params")
+        self._params = (float(body_force_z), float(omega))
+        self._adj_run = None
 
     def forward_ckpt(self, sphere, n_steps, avg_from, ckpt_every):
         J = np.zeros(1)
+        self._adj_run = None
         self._check(self.L.vmlbm_forward_ckpt(self.h, sphere, n_steps, avg_from, ckpt_every, _ptr(J)),
                     "forward_ckpt")
+        params = getattr(self, "_params", None)
+        if params is not None:
+            self._adj_run = params + (sphere, n_steps, avg_from)
         return float(J[0])
+
+    def adjoint_run(self):
+        """(F_z, omega, sphere, n_steps, avg_from) of the forward run whose
+        checkpoints the simulation holds, or None."""
+        return getattr(self, "_adj_run", None)
 
     def adjoint(self, dJ=1.0):
         g = np.zeros(2)
@@ -343,10 +354,18 @@ def _drag_grad_function():
             sim.set_params(float(force_z), float(omega))
             J = sim.forward_ckpt(sphere, n_steps, avg_from, ckpt_every)
             ctx.sim = sim
+            ctx.run = (float(force_z), float(omega), sphere, n_steps, avg_from, ckpt_every)
             return torch.tensor(J, dtype=torch.float64)
 
         @staticmethod
         def backward(ctx, gJ):
+            # the simulation's checkpoints belong to its last forward run;
+            # another drag() on the same sim since this one replaced them,
+            # so this run's trajectory is recomputed first
+            F, om, sphere, n_steps, avg_from, ckpt_every = ctx.run
+            if ctx.sim.adjoint_run() != (F, om, sphere, n_steps, avg_from):
+                ctx.sim.set_params(F, om)
+                ctx.sim.forward_ckpt(sphere, n_steps, avg_from, ckpt_every)
             g = ctx.sim.adjoint(float(gJ))
             return (torch.tensor(g[0], dtype=torch.float64), torch.tensor(g[1], dtype=torch.float64),
                     None, None, None, None, None)

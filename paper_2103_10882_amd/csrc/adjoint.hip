@@ -33,6 +33,7 @@ template <> struct Lam<double> { using L = double; };
 struct AdjState {
   int n_steps = 0, avg_from = 0, ckpt_every = 0, sphere = 0;
   bool have_forward = false;
+  double F[3] = {0.0, 0.0, 0.0}, sp = 0.0;   // parameters the checkpoints were taken with
   size_t off_ckpt = 0, off_seg = 0, off_lam[2] = {0, 0}, off_g = 0;
   size_t state_bytes = 0, lam_bytes = 0;
   int n_ckpt = 0;
@@ -200,12 +201,13 @@ __global__ __launch_bounds__(256) void k_adj_boundary(const S* __restrict__ s, c
     T d[kQ], lam[kQ], nu[kQ], kap[kQ];
     uint32_t mask = 0;
     int pid = -1;
-    double Fl[3] = {0, 0, 0}, Tl[3] = {0, 0, 0};
+    double Fl[3] = {0, 0, 0}, Tl[3] = {0, 0, 0}, Kl[3] = {0, 0, 0}, Bl[3] = {0, 0, 0};
     UAddr ad;
     ad.n[0] = p.nx; ad.n[1] = p.ny; ad.n[2] = p.nz;
     ad.per[0] = ad.per[1] = ad.per[2] = 1;
     ad.N = p.N;
-    boundary_cell<S, UAddr>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status, &mask, kap, pi);
+    boundary_cell<S, UAddr>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, Kl, Bl, status, &mask, kap,
+                            pi);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) lam[q] = T(lin[(size_t)q * N + c]);
     collide_adjoint<T>(d, lam, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]), dsm_dw, nu, gF, gW);
@@ -319,6 +321,8 @@ extern "C" {
 int vmlbm_set_params(vmlbm_ctx* c, double body_force_z, double omega) {
   if (!c) return VMLBM_EINVAL;
   if (!(omega > 0.0 && omega < 2.0)) return fail(c, VMLBM_EINVAL, "omega must lie in (0, 2)");
+  // checkpoints taken with other parameters no longer belong to them
+  if (c->adj) c->adj->have_forward = false;
   c->F[2] = body_force_z;
   c->sp = omega;
   c->sm = s_minus_of(omega, c->cfg.magic);
@@ -367,6 +371,8 @@ int vmlbm_forward_ckpt(vmlbm_ctx* c, int sphere, int n_steps, int avg_from, int 
   A.avg_from = avg_from;
   A.ckpt_every = ckpt_every;
   A.sphere = sphere;
+  for (int a = 0; a < 3; ++a) A.F[a] = c->F[a];
+  A.sp = c->sp;
   A.have_forward = true;
   return VMLBM_OK;
 }
@@ -375,6 +381,8 @@ int vmlbm_adjoint(vmlbm_ctx* c, double dJ, double grad[2]) {
   if (!c || !grad) return VMLBM_EINVAL;
   if (!c->adj || !c->adj->have_forward) return fail(c, VMLBM_ESTATE, "vmlbm_forward_ckpt must run first");
   AdjState& A = *c->adj;
+  if (A.sp != c->sp || A.F[0] != c->F[0] || A.F[1] != c->F[1] || A.F[2] != c->F[2])
+    return fail(c, VMLBM_ESTATE, "parameters changed since vmlbm_forward_ckpt: run it again");
   const SweepParams p = sweep_params(c);
   const int np = (int)c->spheres.size();
   const int K = A.ckpt_every, N = A.n_steps, W = N - A.avg_from;

@@ -64,7 +64,7 @@ void plan_uniform(vmlbm_ctx* c) {
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
   // one slot of 6 doubles per wave of the link-cell pass of a sphere
-  c->slot_stride = (size_t)kLinkGroups * 4 * 6;
+  c->slot_stride = (size_t)kLinkGroups * 4 * kSlotWords;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   c->off_status = take(kStatusWords * sizeof(int));

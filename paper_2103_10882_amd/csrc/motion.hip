@@ -95,26 +95,36 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
                                                        double* __restrict__ hist, int* __restrict__ status,
                                                        SweepParams p, UpdateParams u) {
   const int pi = blockIdx.x;
-  __shared__ double red[6][256];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
+  __shared__ double red[kSlotWords][256];
+  double acc[kSlotWords];
+#pragma unroll
+  for (int j = 0; j < kSlotWords; ++j) acc[j] = 0.0;
   double* s = slots + (size_t)pi * p.slot_stride;
-  const int nslots = (int)(p.slot_stride / 6);
+  const int nslots = (int)(p.slot_stride / kSlotWords);
   for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc[j] += s[(size_t)k * 6 + j];
+    for (int j = 0; j < kSlotWords; ++j) acc[j] += s[(size_t)k * kSlotWords + j];
   }
 #pragma unroll
-  for (int j = 0; j < 6; ++j) red[j][threadIdx.x] = acc[j];
+  for (int j = 0; j < kSlotWords; ++j) red[j][threadIdx.x] = acc[j];
   __syncthreads();
   for (int h = blockDim.x / 2; h > 0; h >>= 1) {
     if ((int)threadIdx.x < h)
 #pragma unroll
-      for (int j = 0; j < 6; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
+      for (int j = 0; j < kSlotWords; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
   DevParticle& P = parts[pi];
-  double F[3] = {red[0][0], red[1][0], red[2][0]}, T[3] = {red[3][0], red[4][0], red[5][0]};
+  // deviation parts plus the weight constants (Eq. 11 on f = w + d): the
+  // integer sums K and L x K give K / 36 and L x K / 72 - x_p x K / 36
+  const double K[3] = {red[6][0], red[7][0], red[8][0]}, B[3] = {red[9][0], red[10][0], red[11][0]};
+  const double Fc[3] = {K[0] / 36.0, K[1] / 36.0, K[2] / 36.0};
+  const double Tc[3] = {B[0] / 72.0 - (P.x[1] * Fc[2] - P.x[2] * Fc[1]),
+                        B[1] / 72.0 - (P.x[2] * Fc[0] - P.x[0] * Fc[2]),
+                        B[2] / 72.0 - (P.x[0] * Fc[1] - P.x[1] * Fc[0])};
+  double F[3] = {red[0][0] + Fc[0], red[1][0] + Fc[1], red[2][0] + Fc[2]};
+  double T[3] = {red[3][0] + Tc[0], red[4][0] + Tc[1], red[5][0] + Tc[2]};
   particle_update(P, F, T, status, p, u);
   for (int a = 0; a < 3; ++a) { P.Fprev[a] = F[a]; P.Tprev[a] = T[a]; }
   P.have_prev = 1;

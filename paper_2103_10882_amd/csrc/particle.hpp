@@ -13,10 +13,18 @@ namespace vm {
 // Slow path for a fluid cell with wall or particle links: builds the 19
 // incoming populations with Eq. 10 (CLI) on particle links and halfway
 // bounce-back on walls, and accumulates the link forces of Eq. 11 and their
-// torques (Eq. 12) in FP64.  The constant part 2 w_q c_q of each link force
-// is left out: summed over the closed surface of a body it vanishes exactly
-// (every lattice line enters and leaves the body equally often), and so does
-// its torque (entry and exit points of a line differ by a multiple of c_q).
+// torques (Eq. 12) in FP64.  Populations are held as deviations d = f - w,
+// so the link force splits into a deviation part (Fl, Tl) and the constant
+// part of the weights: with c_qq the direction into the solid,
+// (c_qq - v) w + (c_qq + v) w = 2 w c_qq.  Over a body whose every lattice
+// line enters and leaves through fluid these constants cancel, but a line
+// that leaves the body into a domain wall has no exit link, so they are
+// kept, and summed exactly: K = 36 * 2 w c_qq is an integer vector, and the
+// torque arm x_b - x_p = (x - x_p) + delta c_qq contributes only through
+// x - x_p (c_qq x c_qq = 0), whose unwrapped cell centre L = 2 (x - x_p + x_p)
+// is an odd integer vector.  Kl accumulates K and Bl accumulates L x K;
+// the constant force is then Kl / 36 and its torque Bl / 72 - x_p x Kl / 36,
+// both exactly zero where the constants cancel.
 // `sphere` >= 0 names the particle whose links the caller expects: its state
 // is then read once instead of per link (a link of another particle still
 // sets pid to that one, for the caller's check).  Every stage issues the
@@ -28,6 +36,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
                               const uint16_t* __restrict__ owner, const DevParticle* __restrict__ parts,
                               const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
                               typename Store<S>::T (&d)[kQ], int& pid, double (&Fl)[3], double (&Tl)[3],
+                              double (&Kl)[3], double (&Bl)[3],
                               int* __restrict__ status, uint32_t* link_mask = nullptr,
                               typename Store<S>::T* kappa_out = nullptr, int sphere = -1) {
   using T = typename Store<S>::T;
@@ -145,7 +154,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     T val = own_qq - T(3.0 * alpha * w * cqv);
     if (tok[q]) val = val + T(kappa) * (sec[q] - own[q]);
     d[q] = val;
-    // link force: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
+    // link force, deviation part: (c_qq - v) d~_qq(x) + (c_qq + v) d_q(x, t+1)
     const double a0 = (double)own_qq, a1 = (double)val;
     double Fq[3];
 #pragma unroll
@@ -156,6 +165,14 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
     Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
     Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
     Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
+    // constant part, exact: K = 36 * 2 w c_qq, L = unwrapped 2 x
+    const double kw = q <= 6 ? 4.0 : 2.0;
+    const double K[3] = {-kw * cq[0], -kw * cq[1], -kw * cq[2]};
+    const double L[3] = {rint(2.0 * (off[0] + px[0])), rint(2.0 * (off[1] + px[1])), rint(2.0 * (off[2] + px[2]))};
+    Kl[0] += K[0]; Kl[1] += K[1]; Kl[2] += K[2];
+    Bl[0] += L[1] * K[2] - L[2] * K[1];
+    Bl[1] += L[2] * K[0] - L[0] * K[2];
+    Bl[2] += L[0] * K[1] - L[1] * K[0];
   }
   if (unstored) status[kStatusRange] = 5;
   if (mixed) status[kStatusRange] = 2;
@@ -256,6 +273,21 @@ inline hipError_t launch_link_lists(const uint8_t* flags, const uint16_t* owner,
   return hipGetLastError();
 }
 
+// Wave sums of one wave's force/torque partials into its slot (the constant
+// sums are integers and add exactly).
+__device__ __forceinline__ void write_force_slot(double* __restrict__ slots, const SweepParams& p, int pi,
+                                                 const double (&Fl)[3], const double (&Tl)[3],
+                                                 const double (&Kl)[3], const double (&Bl)[3]) {
+  double v[kSlotWords] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2], Kl[0], Kl[1], Kl[2], Bl[0], Bl[1], Bl[2]};
+#pragma unroll
+  for (int j = 0; j < kSlotWords; ++j) v[j] = wave_sum(v[j]);
+  if ((threadIdx.x & 63) == 0) {
+    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * kSlotWords;
+#pragma unroll
+    for (int j = 0; j < kSlotWords; ++j) o[j] = v[j];
+  }
+}
+
 // Particle-link cells: kLinkGroups workgroups per sphere stride over its
 // link list.  Every wave writes its FP64 partial force/torque (zero if it
 // held no link) to its own slot, so the per-sphere reduction reads a fixed
@@ -273,7 +305,7 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
   const int pi = blockIdx.y;
   const int len = llen[pi];
   const uint32_t* list = links + (size_t)pi * ((size_t)p.box * p.box * p.box);
-  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0}, Kl[3] = {0.0, 0.0, 0.0}, Bl[3] = {0.0, 0.0, 0.0};
   for (int i = blockIdx.x * 256 + threadIdx.x; i < len; i += gridDim.x * 256) {
     int x, y, z;
     uint32_t c;
@@ -283,7 +315,8 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
     }
     int pid = -1;
     T d[kQ];
-    boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, status, nullptr, nullptr, pi);
+    boundary_cell<S, A>(src, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, Kl, Bl, status, nullptr, nullptr,
+                        pi);
     if (pid >= 0 && pid != pi) status[kStatusRange] = 2;
     const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
@@ -291,14 +324,7 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
 #pragma unroll
     for (int q = 0; q < kQ; ++q) dst[(size_t)q * ad.N + c] = Store<S>::store_sr(d[q], rb.next());
   }
-  double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
-#pragma unroll
-  for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
-  if ((threadIdx.x & 63) == 0) {
-    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * 6;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) o[j] = v[j];
-  }
+  write_force_slot(slots, p, pi, Fl, Tl, Kl, Bl);
 }
 
 // Particle-link cells of sphere pi with kLinkLanes lanes per cell: lane s
@@ -331,7 +357,7 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
   double px[3], pu[3], pw[3];
   for (int a = 0; a < 3; ++a) { px[a] = parts[pi].x[a]; pu[a] = parts[pi].u[a]; pw[a] = parts[pi].w[a]; }
   const double pr = parts[pi].r;
-  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0}, Kl[3] = {0.0, 0.0, 0.0}, Bl[3] = {0.0, 0.0, 0.0};
   bool bad_list = false, unstored = false, foreign = false;
   // rounds are uniform over the workgroup (base depends on blockIdx only)
   for (int base = blockIdx.x * kCells; base < len; base += gridDim.x * kCells) {
@@ -400,6 +426,15 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
           Tl[0] += rb[1] * Fq[2] - rb[2] * Fq[1];
           Tl[1] += rb[2] * Fq[0] - rb[0] * Fq[2];
           Tl[2] += rb[0] * Fq[1] - rb[1] * Fq[0];
+          // constant part of the weights, exact (as in boundary_cell)
+          const double kw = q <= 6 ? 4.0 : 2.0;
+          const double K[3] = {-kw * cq[0], -kw * cq[1], -kw * cq[2]};
+          const double L[3] = {rint(2.0 * (off[0] + px[0])), rint(2.0 * (off[1] + px[1])),
+                               rint(2.0 * (off[2] + px[2]))};
+          Kl[0] += K[0]; Kl[1] += K[1]; Kl[2] += K[2];
+          Bl[0] += L[1] * K[2] - L[2] * K[1];
+          Bl[1] += L[2] * K[0] - L[0] * K[2];
+          Bl[2] += L[0] * K[1] - L[1] * K[0];
         }
         din[g][q] = out;
       }
@@ -420,14 +455,7 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
   if (bad_list) status[kStatusRange] = 9;
   if (unstored) status[kStatusRange] = 5;
   if (foreign) status[kStatusRange] = 2;
-  double v[6] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2]};
-#pragma unroll
-  for (int j = 0; j < 6; ++j) v[j] = wave_sum(v[j]);
-  if ((threadIdx.x & 63) == 0) {
-    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * 6;
-#pragma unroll
-    for (int j = 0; j < 6; ++j) o[j] = v[j];
-  }
+  write_force_slot(slots, p, pi, Fl, Tl, Kl, Bl);
 }
 
 // ---------------------------------------------------------------------------

@@ -1538,7 +1538,7 @@ int refine_plan(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  c->slot_stride = (size_t)kRefineLinkGroups * 4 * 6;
+  c->slot_stride = (size_t)kRefineLinkGroups * 4 * kSlotWords;
   const int np = (int)c->spheres.size();
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };

@@ -79,10 +79,10 @@ __global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ sr
   const uint8_t fl = flags[c];
   if ((fl & kSolid) || (fl & kNearP) || !(fl & kNearW)) return;
   int pid = -1;
-  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0};
+  double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0}, Kl[3] = {0.0, 0.0, 0.0}, Bl[3] = {0.0, 0.0, 0.0};
   T d[kQ];
   const UAddr ad = uaddr(p);
-  boundary_cell<S, UAddr>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, status);
+  boundary_cell<S, UAddr>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, Kl, Bl, status);
   const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   SrBits rb(c, p.seed);

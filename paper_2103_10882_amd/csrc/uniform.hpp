@@ -19,13 +19,16 @@ struct SweepParams {
   double F[3];            // fluid body force
   uint32_t N;             // cells
   int box;                // edge of a sphere's box (cells); holds all its link cells
-  size_t slot_stride;     // doubles per sphere in the force-slot array (6 per wave)
+  size_t slot_stride;     // doubles per sphere in the force-slot array (kSlotWords per wave)
   uint32_t seed;          // stochastic-rounding stream of this sweep
 };
 
 // Workgroups per sphere of the link-cell pass; each of their waves owns one
-// force/torque slot of 6 doubles.
+// force/torque slot of kSlotWords doubles: the deviation parts of force and
+// torque, then the integer sums K and L x K of the weight constants (see
+// boundary_cell).
 constexpr int kLinkGroups = 32;
+constexpr int kSlotWords = 12;
 inline int link_chunks(int box) { return (box * box * box + 255) / 256; }
 
 // Per-sphere lists of link cells in box order: counts per 256-cell chunk of

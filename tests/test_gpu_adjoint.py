@@ -64,6 +64,31 @@ def test_autograd_function(env):
     assert abs(w.grad.item() - g_o[1]) <= 1e-9 * abs(g_o[1])
 
 
+def test_drag_twice_before_backward(env):
+    """Two drag evaluations on one simulation before the first one's
+    backward (a finite-difference probe in between): the first gradient
+    still belongs to its own parameters.  The library refuses an adjoint
+    whose checkpoints were taken with other parameters."""
+    import torch
+    pkg, oracle = env
+    cfg, sph, N, A, K = small_case()
+    say("case drag-twice24 f64")
+    sim = pkg.Sim(cfg, sph, storage="f64", history=N - A, adjoint_steps=N, ckpt_every=K)
+    F = torch.tensor(1e-5, dtype=torch.float64, requires_grad=True)
+    w = torch.tensor(1.6, dtype=torch.float64, requires_grad=True)
+    J = pkg.drag(F, w, sim, 0, N, A, K)
+    with torch.no_grad():
+        pkg.drag(torch.tensor(1.1e-5, dtype=torch.float64), torch.tensor(1.55, dtype=torch.float64), sim, 0, N, A, K)
+    J.backward()
+    _, g_o = oracle.drag_gradient(cfg, sph, N, A)
+    assert abs(F.grad.item() - g_o[0]) <= 1e-9 * abs(g_o[0])
+    assert abs(w.grad.item() - g_o[1]) <= 1e-9 * abs(g_o[1])
+    sim.set_params(1e-5, 1.6)
+    with pytest.raises(pkg.VmlbmError) as e:
+        sim.adjoint(1.0)
+    assert e.value.code == -4
+
+
 def test_adjoint_full_size_fd(env):
     """128^3, r = 10, 2000 steps, window 1500..1999, checkpoints every 50:
     FP32 adjoint vs FP64 adjoint, and FP64 adjoint vs central differences of

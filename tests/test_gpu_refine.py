@@ -125,8 +125,8 @@ def test_moving_sphere_rerefinement(env, lb):
         ref.step(1)
         Fg, Tg = sim.force_torque(0)
         Fo, To = ref.force_torque(0)
-        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
-        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), 5.5 * np.abs(Fo).max()), (k, Tg, To)
+        assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), 5.5 * np.abs(Fo).max()), (k, Tg, To)
     sim.sync()
     nref = sim.refinements()
     _, _, nref_o = ref.counters()
@@ -137,7 +137,7 @@ def test_moving_sphere_rerefinement(env, lb):
     assert np.abs(xg - xo).max() < 1e-11
     rel = compare_levels(sim, ref, 3)
     say(f"  population rel err {rel:.2e}")
-    assert rel <= 1e-11
+    assert rel <= 1e-12
     # finest-level mapping
     org = sim.level_blocks(2)
     og = sim.owner(2).reshape(len(org), 16, 16, 16)
@@ -168,13 +168,13 @@ def test_refined_layout_across_periodic_boundary(env):
         ref.step(1)
         Fg, Tg = sim.force_torque(0)
         Fo, To = ref.force_torque(0)
-        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
-        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), 6.0 * np.abs(Fo).max()), (k, Tg, To)
+        assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), 6.0 * np.abs(Fo).max()), (k, Tg, To)
     sim.sync()
     assert sim.refinements() == ref.counters()[2] >= 1
     rel = compare_levels(sim, ref, 2)
     say(f"  refinements {sim.refinements()}; population rel err {rel:.2e}")
-    assert rel <= 1e-11
+    assert rel <= 1e-12
 
 
 def test_single_level_block_grid_equals_uniform(env):
@@ -424,8 +424,8 @@ def test_two_spheres_refined(env):
         for i, r in ((0, 6.5), (1, 5.5)):
             Fg, Tg = sim.force_torque(i)
             Fo, To = ref.force_torque(i)
-            assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, i, Fg, Fo)
-            assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), r * np.abs(Fo).max()), (k, i, Tg, To)
+            assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, i, Fg, Fo)
+            assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), r * np.abs(Fo).max()), (k, i, Tg, To)
     sim.sync()
     assert sim.refinements() == ref.counters()[2] >= 1
     for i in range(2):
@@ -434,7 +434,7 @@ def test_two_spheres_refined(env):
         assert np.abs(xg - xo).max() < 1e-11 and np.abs(ug - uo).max() < 1e-12
     rel = compare_levels(sim, ref, 3)
     say(f"  refinements {sim.refinements()}; population rel err {rel:.2e}")
-    assert rel <= 1e-11
+    assert rel <= 1e-12
 
 
 def test_rotation_only_sphere_refined(env):
@@ -462,8 +462,8 @@ def test_rotation_only_sphere_refined(env):
         ref.step(1)
         Fg, Tg = sim.force_torque(0)
         Fo, To = ref.force_torque(0)
-        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
-        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), 5.0 * np.abs(Fo).max()), (k, Tg, To)
+        assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), 5.0 * np.abs(Fo).max()), (k, Tg, To)
     sim.sync()
     xg, ug, wg = sim.particle(0)
     xo, uo, wo = ref.particle(0)
@@ -471,7 +471,7 @@ def test_rotation_only_sphere_refined(env):
     assert np.abs(wg - wo).max() <= 1e-12 * np.abs(wo).max() and np.abs(wo).max() > 0
     rel = compare_levels(sim, ref, 2)
     say(f"  w {wg}, population rel err {rel:.2e}")
-    assert rel <= 1e-11
+    assert rel <= 1e-12
 
 
 def test_large_sphere_refined(env):
@@ -506,12 +506,12 @@ def test_large_sphere_refined(env):
         ref.step(1)
         Fg, Tg = sim.force_torque(0)
         Fo, To = ref.force_torque(0)
-        assert np.abs(Fg - Fo).max() <= 1e-9 * np.abs(Fo).max(), (k, Fg, Fo)
-        assert np.abs(Tg - To).max() <= 1e-9 * max(np.abs(To).max(), r * np.abs(Fo).max()), (k, Tg, To)
+        assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), r * np.abs(Fo).max()), (k, Tg, To)
     sim.sync()
     xg, ug, _ = sim.particle(0)
     xo, uo, _ = ref.particle(0)
     assert np.abs(xg - xo).max() < 1e-11 and np.abs(ug - uo).max() < 1e-12
     rel = compare_levels(sim, ref, 2)
     say(f"  population rel err {rel:.2e}")
-    assert rel <= 1e-11
+    assert rel <= 1e-12

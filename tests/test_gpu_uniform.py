@@ -35,13 +35,20 @@ def pop_rel(fg, fo):
 
 
 def check_ft(sim, ref, nsph, radius, tol=1e-10, where=""):
+    """Force within tol of |F|, torque within tol of max(|T|, r |F|), every
+    sphere; returns the worst error as a fraction of those scales."""
+    worst = 0.0
     for i in range(nsph):
         Fg, Tg = sim.force_torque(i)
         Fo, To = ref.force_torque(i)
         fs = np.abs(Fo).max()
-        assert np.abs(Fg - Fo).max() <= tol * max(fs, 1e-30), (where, i, Fg, Fo)
+        ef = np.abs(Fg - Fo).max() / max(fs, 1e-30)
+        assert ef <= tol, (where, i, Fg, Fo)
         ts = max(np.abs(To).max(), radius * fs)
-        assert np.abs(Tg - To).max() <= tol * ts, (where, i, Tg, To)
+        et = np.abs(Tg - To).max() / max(ts, 1e-30)
+        assert et <= tol, (where, i, Tg, To)
+        worst = max(worst, ef, et)
+    return worst
 
 
 @pytest.mark.parametrize("lb", [1.0, 100.0])
@@ -131,6 +138,7 @@ def test_moving_sphere_walls_parity(env, lb):
     ref = oracle.Uniform(cfg, [s])
     ref.init()
     changed = 0
+    worst = 0.0
     prev = ref.owner()
     for k in range(1, 161):
         sim.step(1)
@@ -140,18 +148,18 @@ def test_moving_sphere_walls_parity(env, lb):
         assert flips == 0, f"step {k}: {flips} mapping differences"
         changed += int((oo != prev).sum())
         prev = oo
-        check_ft(sim, ref, 1, 5.2, tol=1e-9, where=f"step {k}")
+        worst = max(worst, check_ft(sim, ref, 1, 5.2, where=f"step {k}"))
     sim.sync()
     xg, ug, wg = sim.particle(0)
     xo, uo, wo = ref.particle(0)
-    say(f"  cells re-mapped {changed}; x {xg} vs {xo}")
+    say(f"  cells re-mapped {changed}; x {xg} vs {xo}; worst F/T error {worst:.2e} of the bar's scale")
     assert changed > 100
     assert np.abs(xg - xo).max() < 1e-11
     assert np.abs(ug - uo).max() < 1e-12 * max(1.0, np.abs(uo).max() * 1e3)
     assert np.abs(wg - wo).max() < 1e-12
     rel = pop_rel(sim.populations(), ref.post_collision())
     say(f"  population rel err {rel:.2e}")
-    assert rel <= 1e-11
+    assert rel <= 1e-12
     h = sim.history(0, 16)
     assert np.abs(h[-1, 6:9] - xg).max() == 0.0
 
@@ -205,7 +213,8 @@ def pulled(f, c):
     return np.stack([np.roll(f[q], shift=(c[q, 2], c[q, 1], c[q, 0]), axis=(0, 1, 2)) for q in range(19)])
 
 
-@pytest.mark.parametrize("case,lb", [("box130", 1.0), ("sphere32", 1.0), ("box130", 100.0)])
+@pytest.mark.parametrize("case,lb", [("box130", 1.0), ("sphere32", 1.0), ("box130", 100.0), ("box300", 1.0),
+                                     ("box520", 1.0)])
 def test_reduced_storage_one_step(env, case, lb):
     """One FP16 / FP32 sweep from a rough state (per-cell random velocities
     of amplitude 0.02, so neighbouring cells differ by far more than a
@@ -217,8 +226,11 @@ def test_reduced_storage_one_step(env, case, lb):
     sides start from, and the library stores it exactly."""
     pkg, ora = env
     c, w, _ = ora.lattice()
-    if case == "box130":
-        n = (130, 6, 5)
+    if case.startswith("box"):
+        # rows of 130 cells fit one workgroup; 300 and 520 split into
+        # several row segments with a ragged last one
+        nx = int(case[3:])
+        n = (nx, 6, 5) if nx == 130 else (nx, 3, 3)
         cfg = synth.base_config(n, omega=1.4, body_force=(2e-5, -1e-5, 3e-5))
         sph = []
     else:
@@ -303,19 +315,21 @@ def test_nan_injection_flags_unstable(env):
     assert e.value.code == -5
 
 
-def run_parity(pkg, oracle, cfg, sph, steps, radius, tag, tol_ft=1e-9, tol_pop=1e-11, owner_every=1):
+def run_parity(pkg, oracle, cfg, sph, steps, radius, tag, tol_ft=1e-10, tol_pop=1e-12, owner_every=1):
     say(f"case {tag}")
     sim = pkg.Sim(cfg, sph, storage="f64", history=4)
     sim.init()
     ref = oracle.Uniform(cfg, sph)
     ref.init()
+    worst = 0.0
     for k in range(1, steps + 1):
         sim.step(1)
         ref.step(1)
         if k % owner_every == 0:
             flips = int((sim.owner() != ref.owner()).sum())
             assert flips == 0, f"step {k}: {flips} mapping differences"
-        check_ft(sim, ref, len(sph), radius, tol=tol_ft, where=f"step {k}")
+        worst = max(worst, check_ft(sim, ref, len(sph), radius, tol=tol_ft, where=f"step {k}"))
+    say(f"  worst F/T error {worst:.2e} of the bar's scale")
     sim.sync()
     for i in range(len(sph)):
         xg, ug, wg = sim.particle(i)
@@ -362,6 +376,26 @@ def test_sphere_next_to_wall(env):
                             wall_velocity=((0.002, 0.0, 0.0), (0.0, 0.0, 0.0)))
     s = synth.sphere((11.6, 10.9, 5.5), 4.0, density_ratio=2.0, cv=0.5, fixed=False, u=(0.0, 0.0, -0.004))
     run_parity(pkg, oracle, cfg, [s], 80, 4.0, "wall-sphere24x22x26 f64")
+
+
+@pytest.mark.parametrize("moving", [False, True])
+def test_sphere_touching_wall(env, moving):
+    """Solid cells in the cell row next to a no-slip wall (the sphere's
+    surface 0.3 cells above the wall plane): lattice lines leave the sphere
+    into the wall with no exit link, so the constant part 2 w_q c_q of the
+    link forces (Eq. 11 on f = w + d) no longer cancels over the surface.
+    A fixed sphere, and one moving along the moving wall with rotation
+    (re-mapping and refill beside the wall)."""
+    pkg, oracle = env
+    n = (30, 22, 20)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.5, body_force=(1e-5, 0.0, 0.0),
+                            wall_velocity=((0.01, 0.0, 0.0), (0.0, 0.0, 0.0)))
+    if moving:
+        s = synth.sphere((12.4, 10.7, 4.3), 4.0, density_ratio=2.0, cv=0.5, fixed=False,
+                         u=(0.02, 0.003, 0.0), w=(0.0, 0.004, 0.002))
+    else:
+        s = synth.sphere((12.4, 10.7, 4.3), 4.0, fixed=True)
+    run_parity(pkg, oracle, cfg, [s], 80, 4.0, f"touching-wall30x22x20 moving={moving} f64")
 
 
 def test_hold_then_rotate(env):
