@@ -59,9 +59,10 @@ constexpr int kHistWords = 15;     // per sphere and step: F, T, x, u, w
 // ---------------------------------------------------------------------------
 // Random bits for stochastic rounding: one counter-based stream per (cell,
 // sweep).  An integer hash of the cell index and the sweep's seed (the
-// "lowbias32" mixer of C. Wellons' hash-prospector) starts a 32-bit linear
-// congruential sequence (PCG32's multiplier and increment) advanced once per
-// stored population; its high bits are used.
+// "lowbias32" mixer of C. Wellons' hash-prospector) starts a Weyl sequence
+// (increment 2^32 / golden ratio) advanced once per stored population.  Each
+// value is uniform on its own, which is what unbiased rounding needs, and a
+// step costs one integer add instead of a quarter-rate 32-bit multiply.
 __host__ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   x *= 0x7feb352du;
@@ -74,7 +75,7 @@ struct SrBits {
   uint32_t h;
   __device__ __forceinline__ SrBits(uint32_t cell, uint32_t seed) : h(mix32(cell ^ mix32(seed + 0x9e3779b9u))) {}
   __device__ __forceinline__ uint32_t next() {
-    h = h * 747796405u + 2891336453u;
+    h += 0x9e3779b9u;
     return h;
   }
 };
@@ -127,6 +128,15 @@ template <>
 __device__ __forceinline__ void store_nt<__half>(__half* p, __half v) {
   __builtin_nontemporal_store(__half_as_ushort(v), reinterpret_cast<unsigned short*>(p));
 }
+// the same through a global (address space 1) byte pointer
+template <typename S>
+__device__ __forceinline__ void store_nt_g(__attribute__((address_space(1))) char* p, S v) {
+  __builtin_nontemporal_store(v, (__attribute__((address_space(1))) S*)p);
+}
+template <>
+__device__ __forceinline__ void store_nt_g<__half>(__attribute__((address_space(1))) char* p, __half v) {
+  __builtin_nontemporal_store(__half_as_ushort(v), (__attribute__((address_space(1))) unsigned short*)p);
+}
 
 // ---------------------------------------------------------------------------
 // Collision of Sec. 2.1 on deviations, incompressible equilibrium (rho0 = 1),
@@ -137,7 +147,8 @@ __device__ __forceinline__ void store_nt<__half>(__half* p, __half v) {
 // 1 - s/2.  sb == sp gives TRT.  d[] holds pre-collision deviations on
 // entry and post-collision on exit.  Returns the density deviation.
 // ---------------------------------------------------------------------------
-template <typename T>
+// MRT = false drops the shell-mean terms, which vanish for sb == sp (TRT).
+template <typename T, bool MRT = true>
 __device__ __forceinline__ T lbm_collide(T (&d)[kQ], T sp, T sm, T sb, T Fx, T Fy, T Fz) {
   T drho = d[0];
 #pragma unroll
@@ -148,6 +159,7 @@ __device__ __forceinline__ T lbm_collide(T (&d)[kQ], T sp, T sm, T sb, T Fx, T F
   const T ux = jx + T(0.5) * Fx, uy = jy + T(0.5) * Fy, uz = jz + T(0.5) * Fz;
   const T usq = ux * ux + uy * uy + uz * uz;
   const T uF = ux * Fx + uy * Fy + uz * Fz;
+  if (!MRT) sb = sp;
   const T kp = T(1) - T(0.5) * sp, km = T(1) - T(0.5) * sm, kb = T(1) - T(0.5) * sb;
   // rest population: a shell of its own, so purely isotropic
   {
@@ -171,7 +183,9 @@ __device__ __forceinline__ T lbm_collide(T (&d)[kQ], T sp, T sm, T sb, T Fx, T F
     const T fm = T(0.5) * (d[q] - d[qb]);
     ne[k] = fp[k] - ep;
     se[k] = Sp;
-    if (k < 3) { nax += ne[k]; sax += Sp; } else { ndg += ne[k]; sdg += Sp; }
+    if (MRT) {
+      if (k < 3) { nax += ne[k]; sax += Sp; } else { ndg += ne[k]; sdg += Sp; }
+    }
     // odd part now; the even part below, once the shell means are known
     const T nm = fm - sm * (fm - em) + km * Sm;
     d[q] = nm;
@@ -186,7 +200,7 @@ __device__ __forceinline__ T lbm_collide(T (&d)[kQ], T sp, T sm, T sb, T Fx, T F
   for (int k = 0; k < kPairs; ++k) {
     const int q = pair_q(k), qb = opp_of(q);
     const T mn = k < 3 ? mn_ax : mn_dg, ms = k < 3 ? ms_ax : ms_dg;
-    const T np = fp[k] - sp * ne[k] - dsb * mn + kp * se[k] + dkb * ms;
+    const T np = MRT ? fp[k] - sp * ne[k] - dsb * mn + kp * se[k] + dkb * ms : fp[k] - sp * ne[k] + kp * se[k];
     d[q] = np + d[q];
     d[qb] = np + d[qb];
   }

@@ -33,26 +33,76 @@ __host__ __device__ UAddr uaddr(const SweepParams& p) {
 // with a nonzero flag are left to the boundary kernels below (solid cells are
 // not computed at all), so this kernel carries only the streaming pull and
 // the collision and keeps its register footprint small.
-template <typename S, bool FLAGS>
-__global__ __launch_bounds__(512) void k_sweep(const S* __restrict__ src, S* __restrict__ dst,
-                                               const uint8_t* __restrict__ flags, int* __restrict__ status,
-                                               SweepParams p) {
+//
+// Addressing: a workgroup holds one row segment, so the source row and plane
+// of every direction (periodic wrap included) are workgroup-uniform.  Each
+// load and store is a uniform base (population and row) plus one of three
+// per-lane x offsets, so the address arithmetic stays in scalar registers.
+// a workgroup-uniform global pointer, held in scalar registers
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ gchar* uniform_ptr(char* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (gchar*)(((uint64_t)hi << 32) | lo);
+}
+
+template <typename S, int Q>
+__device__ __forceinline__ void pull_row(const S* __restrict__ src, uint32_t N, uint32_t rm, uint32_t r0,
+                                         uint32_t rp, uint32_t pm, uint32_t p0, uint32_t pp, uint32_t xm,
+                                         uint32_t x, uint32_t xp, typename Store<S>::T (&d)[kQ]) {
+  constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
+  const uint32_t ys = cy == 1 ? rm : (cy == -1 ? rp : r0);
+  const uint32_t zs = cz == 1 ? pm : (cz == -1 ? pp : p0);
+  const char* __restrict__ row = reinterpret_cast<const char*>(src + ((size_t)Q * N + zs + ys));
+  const uint32_t xb = (cx == 1 ? xm : (cx == -1 ? xp : x)) * (uint32_t)sizeof(S);   // byte offset, 32 bits
+  d[Q] = Store<S>::load(*reinterpret_cast<const S*>(row + xb));
+}
+
+template <typename S, int... Qs>
+__device__ __forceinline__ void pull_rows(const S* __restrict__ src, uint32_t N, uint32_t rm, uint32_t r0,
+                                          uint32_t rp, uint32_t pm, uint32_t p0, uint32_t pp, uint32_t xm,
+                                          uint32_t x, uint32_t xp, typename Store<S>::T (&d)[kQ],
+                                          std::integer_sequence<int, Qs...>) {
+  (pull_row<S, Qs>(src, N, rm, r0, rp, pm, p0, pp, xm, x, xp, d), ...);
+}
+
+// A workgroup is RY row segments of BX cells (RY consecutive rows of one
+// plane); each wave lies within one row, so its row is wave-uniform.
+template <typename S, bool FLAGS, bool MRT, int BX, int RY>
+__global__ __launch_bounds__(BX * RY) void k_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                                   const uint8_t* __restrict__ flags, int* __restrict__ status,
+                                                   SweepParams p) {
   using T = typename Store<S>::T;
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y, z = blockIdx.z;
-  if (x >= p.nx) return;
-  const uint32_t N = p.N;
-  const uint32_t c = ((uint32_t)z * p.ny + y) * p.nx + x;
+  static_assert(BX % 64 == 0, "row segments are whole waves");
+  const uint32_t x = blockIdx.x * BX + (RY == 1 ? threadIdx.x : threadIdx.x % BX);
+  const int y = RY == 1 ? blockIdx.y
+                        : (int)__builtin_amdgcn_readfirstlane(blockIdx.y * RY + threadIdx.x / BX);
+  const int z = blockIdx.z;
+  if (x >= (uint32_t)p.nx || y >= p.ny) return;
+  const uint32_t N = p.N, nx = p.nx;
+  const uint32_t plane = nx * p.ny;
+  const uint32_t row0 = (uint32_t)z * plane + (uint32_t)y * nx;
+  const uint32_t c = row0 + x;
   if (FLAGS && flags[c] != 0) return;
+  const uint32_t ym = y == 0 ? p.ny - 1 : y - 1, yp = y + 1 == p.ny ? 0 : y + 1;
+  const uint32_t zm = z == 0 ? p.nz - 1 : z - 1, zp = z + 1 == p.nz ? 0 : z + 1;
+  const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
   T d[kQ];
-  const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz);
-  load_all<S>(src, N, I, x, d, std::make_integer_sequence<int, kQ>{});
-  const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
+  pull_rows<S>(src, N, ym * nx, (uint32_t)y * nx, yp * nx, zm * plane, (uint32_t)z * plane, zp * plane, xm, x, xp,
+               d, std::make_integer_sequence<int, kQ>{});
+  const T drho = lbm_collide<T, MRT>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   // streaming stores: the new state is not read again within this sweep
   SrBits rb(c, p.seed);
+  const uint32_t xb = x * (uint32_t)sizeof(S);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], Store<S>::store_sr(d[q], rb.next()));
+  for (int q = 0; q < kQ; ++q) {
+    // the row base is workgroup-uniform; stating it so keeps the compiler
+    // from folding it into a per-lane 64-bit address
+    gchar* out = uniform_ptr(reinterpret_cast<char*>(dst + ((size_t)q * N + row0)));
+    store_nt_g(out + xb, Store<S>::store_sr(d[q], rb.next()));
+  }
 }
 
 // Wall-link cells without particle links: the two boundary planes of each
@@ -170,24 +220,56 @@ hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uin
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+#ifndef VM_SWEEP_F64
+#define VM_SWEEP_F64 128, 2
+#endif
+#ifndef VM_SWEEP_F32
+#define VM_SWEEP_F32 256, 1
+#endif
+#ifndef VM_SWEEP_F16
+#define VM_SWEEP_F16 512, 1
+#endif
+template <int B, int R> struct Shape { static constexpr int bx = B, ry = R; };
+template <typename S> struct SweepShape;
+template <> struct SweepShape<double> : Shape<VM_SWEEP_F64> {};
+template <> struct SweepShape<float> : Shape<VM_SWEEP_F32> {};
+template <> struct SweepShape<__half> : Shape<VM_SWEEP_F16> {};
+
 template <typename S>
 hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int* status, const SweepParams& p,
                            bool with_flags, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
-  // one workgroup per grid row segment: the x-shifted loads of a segment
-  // stay within one workgroup's cache lines.  Segment length by measurement
-  // on 512^3: 256 cells for FP32 and FP16 storage, whole 512-cell rows for
-  // FP64.
-  const int wmax = std::is_same<S, double>::value ? 512 : 256;
-  const int bx = p.nx >= wmax ? wmax : ((p.nx + 63) / 64) * 64;
-  dim3 grid((p.nx + bx - 1) / bx, p.ny, p.nz), block(bx);
+  // One workgroup per RY row segments of BX cells: the x-shifted loads of a
+  // segment stay within one workgroup's cache lines.  Shapes by measurement
+  // on 512^3 (per storage format: the segment length, rows per workgroup);
+  // rows shorter than BX take one segment of whole waves.
+  constexpr int BX = SweepShape<S>::bx, RY = SweepShape<S>::ry;
   if (e0) {
     hipError_t er = hipEventRecord(e0, st);
     if (er != hipSuccess) return er;
   }
-  if (with_flags)
-    k_sweep<S, true><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
-  else
-    k_sweep<S, false><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+  const bool mrt = p.sb != p.sp;
+  if (p.nx >= BX) {
+    dim3 grid((p.nx + BX - 1) / BX, (p.ny + RY - 1) / RY, p.nz), block(BX * RY);
+    if (with_flags && mrt)
+      k_sweep<S, true, true, BX, RY><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+    else if (with_flags)
+      k_sweep<S, true, false, BX, RY><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+    else if (mrt)
+      k_sweep<S, false, true, BX, RY><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+    else
+      k_sweep<S, false, false, BX, RY><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+  } else {
+    // short rows: one segment of whole waves per row (at most 512 cells)
+    dim3 grid(1, p.ny, p.nz), block(((p.nx + 63) / 64) * 64);
+    if (with_flags && mrt)
+      k_sweep<S, true, true, 512, 1><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+    else if (with_flags)
+      k_sweep<S, true, false, 512, 1><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+    else if (mrt)
+      k_sweep<S, false, true, 512, 1><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+    else
+      k_sweep<S, false, false, 512, 1><<<grid, block, 0, st>>>((const S*)src, (S*)dst, flags, status, p);
+  }
   hipError_t e = hipGetLastError();
   if (e == hipSuccess && e1) e = hipEventRecord(e1, st);
   return e;
