@@ -187,6 +187,14 @@ int vmlbm_stats(vmlbm_ctx* ctx, double* cell_updates, double* seconds);
 int vmlbm_profile(vmlbm_ctx* ctx, int enable);
 int vmlbm_sweep_time(vmlbm_ctx* ctx, double* seconds, long long* launches);
 
+/* Bandwidth reference, not part of the method: a plain device copy of
+ * `bytes` (a multiple of 16) from src to dst, device pointers that must not
+ * overlap, with one 16-byte load and one streaming 16-byte store per thread,
+ * enqueued on `stream` (a hipStream_t; NULL = default stream).  The
+ * sweeps' fraction of HBM bandwidth is read against what this copy
+ * reaches.  VMLBM_EINVAL for a size that is not a multiple of 16. */
+int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
 /* Totals of the post-collision state over fluid cells: mass sum f~ and
  * momentum sum c f~ (refined grid: every level weighted by its cell volume
  * 8^-l in coarse units).  Deterministic device reduction; synchronises. */

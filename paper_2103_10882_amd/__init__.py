@@ -27,6 +27,7 @@ EXPORTS = [
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
     "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
+    "vmlbm_stream_copy",
 ]
 
 
@@ -95,6 +96,7 @@ def lib():
             "vmlbm_forward_ckpt": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
             "vmlbm_adjoint": [vp, ctypes.c_double, vp],
             "vmlbm_destroy": [vp],
+            "vmlbm_stream_copy": [vp, vp, ctypes.c_size_t, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -376,3 +378,15 @@ def _drag_grad_function():
 def drag(force_z, omega, sim, sphere=0, n_steps=2000, avg_from=1500, ckpt_every=50):
     """Differentiable time-averaged drag (torch scalars in, torch scalar out)."""
     return _drag_grad_function().apply(force_z, omega, sim, sphere, n_steps, avg_from, ckpt_every)
+
+
+def stream_copy(dst, src):
+    """Plain device copy src -> dst (torch tensors of equal byte size, a
+    multiple of 16) on torch's current stream: the bandwidth reference."""
+    import torch
+    nbytes = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == nbytes
+    rc = lib().vmlbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise VmlbmError(rc, "stream_copy")

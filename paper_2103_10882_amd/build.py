@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvmlbm.so")
 
-SOURCES = ["api.hip", "uniform.hip", "motion.hip", "refine.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "uniform.hip", "refine.hip", "adjoint.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -63,8 +63,8 @@ void plan_uniform(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  // one slot of 6 doubles per wave of the link-cell pass of a sphere
-  c->slot_stride = (size_t)kLinkGroups * 4 * kSlotWords;
+  // one force slot per workgroup of the link-cell pass of a sphere
+  c->slot_stride = (size_t)kLinkGroups * kSlotWords;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   c->off_status = take(kStatusWords * sizeof(int));
@@ -153,6 +153,15 @@ SweepParams sweep_params(const vmlbm_ctx* c) {
   return p;
 }
 
+UpdateParams update_params(const vmlbm_ctx* c, long long step) {
+  UpdateParams u{};
+  for (int a = 0; a < 3; ++a) u.g[a] = c->cfg.gravity[a];
+  u.hist_len = std::max(c->cfg.history, 1);
+  u.step = (int)(step % u.hist_len);
+  u.np = (int)c->spheres.size();
+  return u;
+}
+
 // one sweep src -> dst: boundary cells on the side stream, concurrently with
 // the interior sweep; joined back into the main stream
 int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1) {
@@ -194,12 +203,8 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
     int rc = sweep_once(c, p, src, dst, e0, e1);
     if (rc) return rc;
     if (np > 0) {
-      UpdateParams u{};
-      for (int a = 0; a < 3; ++a) u.g[a] = c->cfg.gravity[a];
-      u.step = (int)(c->steps_done % std::max(c->cfg.history, 1));
-      u.hist_len = std::max(c->cfg.history, 1);
-      u.np = np;
-      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, u, c->stream));
+      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p,
+                                      update_params(c, c->steps_done), c->stream));
       if (c->moving) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;
@@ -337,6 +342,7 @@ int vmlbm_init_equilibrium(vmlbm_ctx* c, double rho, const double* u0) {
     memset(&P, 0, sizeof(P));
     for (int a = 0; a < 3; ++a) {
       P.x[a] = s.x[a];
+      P.xold[a] = s.x[a];
       P.u[a] = s.fixed ? 0.0 : s.u[a];
       P.w[a] = s.fixed == 1 ? 0.0 : s.w[a];
     }
@@ -576,6 +582,12 @@ int vmlbm_sweep_time(vmlbm_ctx* c, double* seconds, long long* launches) {
   if (seconds) *seconds = c->sweep_seconds;
   if (launches) *launches = c->sweep_launches;
   return VMLBM_OK;
+}
+
+int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+  if (!dst || !src || bytes % 16) return VMLBM_EINVAL;
+  if (bytes / 16 > (size_t)UINT32_MAX * 256) return VMLBM_ERANGE;
+  return launch_stream_copy(dst, src, bytes, (hipStream_t)stream) == hipSuccess ? VMLBM_OK : VMLBM_EDEVICE;
 }
 
 int vmlbm_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* interior) {

@@ -1,13 +1,14 @@
 // Per-particle force/torque reduction (fixed order, FP64) fused with the
 // two-step average and the virtual-mass velocity-Verlet update (Sec. 2.2,
-// Sec. 3.3, Algorithm 1); shared by the uniform and the refined grid (on the
-// finest level).
+// Sec. 3.3, Algorithm 1); one workgroup per sphere after the link-cell pass,
+// on the uniform grid and on the refined grid's finest level.
+#pragma once
+
 #include "common.hpp"
 #include "uniform.hpp"
+#include "stencil.hpp"
 
 namespace vm {
-
-namespace {
 
 // ---------------------------------------------------------------------------
 // Particle update.  The acceleration inside the virtual force and torque is
@@ -20,9 +21,11 @@ namespace {
 // spheres (fixed = 1) are not moved; fixed = 2 (position held, rotation
 // free, Sec. 3.4.2) integrates the rotation only.
 // ---------------------------------------------------------------------------
-__device__ void particle_update(DevParticle& P, const double (&F)[3], const double (&T)[3], int* __restrict__ status,
-                                const SweepParams& p, const UpdateParams& u) {
+__device__ inline void particle_update(DevParticle& P, const double (&F)[3], const double (&T)[3],
+                                       int* __restrict__ status, const SweepParams& p, const UpdateParams& u) {
 #pragma clang fp contract(off)
+  // the mapping in place was made at the position before this update
+  for (int a = 0; a < 3; ++a) P.xold[a] = P.x[a];
   bool finite = true;
   for (int a = 0; a < 3; ++a) finite = finite && isfinite(F[a]) && isfinite(T[a]);
   if (!finite) status[kStatusUnstable] = 2;
@@ -91,40 +94,41 @@ __device__ void particle_update(DevParticle& P, const double (&F)[3], const doub
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__ parts, double* __restrict__ slots,
-                                                       double* __restrict__ hist, int* __restrict__ status,
-                                                       SweepParams p, UpdateParams u) {
-  const int pi = blockIdx.x;
-  __shared__ double red[kSlotWords][256];
+// Sum of the kSlotWords-double slots of sphere pi in a fixed order, then
+// the two-step average and the particle update; run by one whole workgroup.
+__device__ inline void reduce_update(DevParticle* __restrict__ parts, const double* __restrict__ slots,
+                                     double* __restrict__ hist, int* __restrict__ status, const SweepParams& p,
+                                     const UpdateParams& u, int pi) {
+  __shared__ double red[kSlotWords][4];
   double acc[kSlotWords];
 #pragma unroll
   for (int j = 0; j < kSlotWords; ++j) acc[j] = 0.0;
-  double* s = slots + (size_t)pi * p.slot_stride;
+  const double* s = slots + (size_t)pi * p.slot_stride;
   const int nslots = (int)(p.slot_stride / kSlotWords);
   for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
 #pragma unroll
     for (int j = 0; j < kSlotWords; ++j) acc[j] += s[(size_t)k * kSlotWords + j];
   }
 #pragma unroll
-  for (int j = 0; j < kSlotWords; ++j) red[j][threadIdx.x] = acc[j];
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h)
+  for (int j = 0; j < kSlotWords; ++j) acc[j] = wave_sum(acc[j]);
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
-      for (int j = 0; j < kSlotWords; ++j) red[j][threadIdx.x] += red[j][threadIdx.x + h];
-    __syncthreads();
-  }
+    for (int j = 0; j < kSlotWords; ++j) red[j][threadIdx.x >> 6] = acc[j];
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  double tot[kSlotWords];
+#pragma unroll
+  for (int j = 0; j < kSlotWords; ++j) tot[j] = (red[j][0] + red[j][1]) + (red[j][2] + red[j][3]);
   DevParticle& P = parts[pi];
   // deviation parts plus the weight constants (Eq. 11 on f = w + d): the
   // integer sums K and L x K give K / 36 and L x K / 72 - x_p x K / 36
-  const double K[3] = {red[6][0], red[7][0], red[8][0]}, B[3] = {red[9][0], red[10][0], red[11][0]};
+  const double K[3] = {tot[6], tot[7], tot[8]}, B[3] = {tot[9], tot[10], tot[11]};
   const double Fc[3] = {K[0] / 36.0, K[1] / 36.0, K[2] / 36.0};
   const double Tc[3] = {B[0] / 72.0 - (P.x[1] * Fc[2] - P.x[2] * Fc[1]),
                         B[1] / 72.0 - (P.x[2] * Fc[0] - P.x[0] * Fc[2]),
                         B[2] / 72.0 - (P.x[0] * Fc[1] - P.x[1] * Fc[0])};
-  double F[3] = {red[0][0] + Fc[0], red[1][0] + Fc[1], red[2][0] + Fc[2]};
-  double T[3] = {red[3][0] + Tc[0], red[4][0] + Tc[1], red[5][0] + Tc[2]};
+  double F[3] = {tot[0] + Fc[0], tot[1] + Fc[1], tot[2] + Fc[2]};
+  double T[3] = {tot[3] + Tc[0], tot[4] + Tc[1], tot[5] + Tc[2]};
   particle_update(P, F, T, status, p, u);
   for (int a = 0; a < 3; ++a) { P.Fprev[a] = F[a]; P.Tprev[a] = T[a]; }
   P.have_prev = 1;
@@ -138,12 +142,5 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
   }
 }
 
-}  // namespace
-
-hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
-                                const SweepParams& p, const UpdateParams& u, hipStream_t st) {
-  k_reduce_update<<<dim3(np), dim3(256), 0, st>>>(parts, slots, hist, status, p, u);
-  return hipGetLastError();
-}
 
 }  // namespace vm

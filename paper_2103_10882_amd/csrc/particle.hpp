@@ -7,6 +7,7 @@
 #include "common.hpp"
 #include "uniform.hpp"
 #include "stencil.hpp"
+#include "motion.hpp"
 
 namespace vm {
 
@@ -40,7 +41,6 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
                               int* __restrict__ status, uint32_t* link_mask = nullptr,
                               typename Store<S>::T* kappa_out = nullptr, int sphere = -1) {
   using T = typename Store<S>::T;
-  const uint32_t N = ad.N;
   const int n[3] = {p.nx, p.ny, p.nz};
   // pass 1: pull source of every direction and its flag
   uint32_t sidx[kQ];
@@ -60,17 +60,17 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
   for (int q = 1; q < kQ; ++q) sfl[q] = wall[q] < 0 ? flags[sidx[q]] : 0;   // sidx = c across walls
   // pass 2: plain streaming where the source is fluid (every source is a
   // stored cell, so the loads need no guard)
-  d[0] = Store<S>::load(src[c]);
+  d[0] = Store<S>::load(src[ad.pop(0, c)]);
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
-    const T v = Store<S>::load(src[(size_t)q * N + sidx[q]]);
+    const T v = Store<S>::load(src[ad.pop(q, sidx[q])]);
     if (wall[q] < 0 && !(sfl[q] & kSolid)) d[q] = v;
   }
   // pass 3: links (non-link directions read the cell itself)
   bool link[kQ];
   T own[kQ];
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) own[q] = Store<S>::load(src[(size_t)q * N + c]);
+  for (int q = 0; q < kQ; ++q) own[q] = Store<S>::load(src[ad.pop(q, c)]);
   int pq[kQ];
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
@@ -96,7 +96,7 @@ __device__ void boundary_cell(const S* __restrict__ src, const uint8_t* __restri
   for (int q = 1; q < kQ; ++q) tok[q] = tok[q] && !(tfl[q] & kSolid);
   T sec[kQ];
 #pragma unroll
-  for (int q = 1; q < kQ; ++q) sec[q] = Store<S>::load(src[(size_t)opp_of(q) * N + (tok[q] ? tidx[q] : c)]);
+  for (int q = 1; q < kQ; ++q) sec[q] = Store<S>::load(src[ad.pop(opp_of(q), tok[q] ? tidx[q] : c)]);
   // state of the expected particle, read once
   double kx[3] = {0.0, 0.0, 0.0}, ku[3] = {0.0, 0.0, 0.0}, kw[3] = {0.0, 0.0, 0.0}, kr = 0.0;
   if (sphere >= 0) {
@@ -273,18 +273,23 @@ inline hipError_t launch_link_lists(const uint8_t* flags, const uint16_t* owner,
   return hipGetLastError();
 }
 
-// Wave sums of one wave's force/torque partials into its slot (the constant
-// sums are integers and add exactly).
+// Sum of one 256-thread workgroup's force/torque partials into its slot,
+// in a fixed order: wave sums, then the four waves (the constant sums are
+// integers and add exactly).  Called by every thread of the workgroup.
 __device__ __forceinline__ void write_force_slot(double* __restrict__ slots, const SweepParams& p, int pi,
                                                  const double (&Fl)[3], const double (&Tl)[3],
                                                  const double (&Kl)[3], const double (&Bl)[3]) {
+  __shared__ double wv[4][kSlotWords];
   double v[kSlotWords] = {Fl[0], Fl[1], Fl[2], Tl[0], Tl[1], Tl[2], Kl[0], Kl[1], Kl[2], Bl[0], Bl[1], Bl[2]};
 #pragma unroll
   for (int j = 0; j < kSlotWords; ++j) v[j] = wave_sum(v[j]);
-  if ((threadIdx.x & 63) == 0) {
-    double* o = slots + (size_t)pi * p.slot_stride + (size_t)(blockIdx.x * 4 + (threadIdx.x >> 6)) * kSlotWords;
+  if ((threadIdx.x & 63) == 0)
 #pragma unroll
-    for (int j = 0; j < kSlotWords; ++j) o[j] = v[j];
+    for (int j = 0; j < kSlotWords; ++j) wv[threadIdx.x >> 6][j] = v[j];
+  __syncthreads();
+  if (threadIdx.x < kSlotWords) {
+    const int j = threadIdx.x;
+    slots[(size_t)pi * p.slot_stride + (size_t)blockIdx.x * kSlotWords + j] = (wv[0][j] + wv[1][j]) + (wv[2][j] + wv[3][j]);
   }
 }
 
@@ -322,7 +327,7 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
     if (!(drho == drho)) status[kStatusUnstable] = 1;
     SrBits rb(c, p.seed);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * ad.N + c] = Store<S>::store_sr(d[q], rb.next());
+    for (int q = 0; q < kQ; ++q) dst[ad.pop(q, c)] = Store<S>::store_sr(d[q], rb.next());
   }
   write_force_slot(slots, p, pi, Fl, Tl, Kl, Bl);
 }
@@ -334,43 +339,58 @@ __global__ __launch_bounds__(256) void k_boundary_particles(const S* __restrict_
 // group's populations meet in LDS, and its first lane collides and stores
 // the cell.  A lane so runs the per-direction chain of two or three
 // directions instead of eighteen (measured against 1, 2, 4 and 16 lanes on
-// the 3-level workload).  Force and torque partials go to per-wave slots as
-// in k_boundary_particles, one per wave of the launch.
+// the 3-level workload).
+// Work: workgroup b of G takes the box cells b, b + G, b + 2G, ... (256 of
+// them) of the sphere's box, finds its link cells from the current mapping,
+// and compacts them in LDS, so no link list has to be built after a
+// re-mapping; the stride spreads the surface evenly over the workgroups
+// (consecutive cells would leave a few workgroups with most of the link
+// cells).  Force and torque partials go to one slot per workgroup.
 constexpr int kLinkLanes = 8;
 template <typename S, typename A>
 __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S* __restrict__ dst,
                                                     const uint8_t* __restrict__ flags,
                                                     const uint16_t* __restrict__ owner,
                                                     const DevParticle* __restrict__ parts,
-                                                    const uint32_t* __restrict__ links, const int* __restrict__ llen,
                                                     double* __restrict__ slots, int* __restrict__ status,
                                                     SweepParams p, A ad) {
   using T = typename Store<S>::T;
   constexpr int kCells = 256 / kLinkLanes;
   __shared__ T din[kCells][kQ];
+  __shared__ uint32_t list[256];
+  __shared__ int wcount[4];
   const int pi = blockIdx.y;
-  const int len = llen[pi];
-  const uint32_t* list = links + (size_t)pi * ((size_t)p.box * p.box * p.box);
-  const uint32_t N = ad.N;
+  // link cells among this workgroup's box cells, in box order
+  {
+    const int k = blockIdx.x + threadIdx.x * gridDim.x;
+    int x, y, z;
+    uint32_t c;
+    const bool in = link_cell<A>(flags, owner, parts, pi, k, p, ad, x, y, z, c);
+    const unsigned long long m = __ballot(in);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) wcount[wave] = __popcll(m);
+    __syncthreads();
+    int base = 0;
+    for (int w = 0; w < wave; ++w) base += wcount[w];
+    if (in) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)k;
+    __syncthreads();
+  }
+  const int len = wcount[0] + wcount[1] + wcount[2] + wcount[3];
   const int n[3] = {p.nx, p.ny, p.nz};
   const int g = threadIdx.x / kLinkLanes, s = threadIdx.x % kLinkLanes;
   double px[3], pu[3], pw[3];
   for (int a = 0; a < 3; ++a) { px[a] = parts[pi].x[a]; pu[a] = parts[pi].u[a]; pw[a] = parts[pi].w[a]; }
   const double pr = parts[pi].r;
   double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0}, Kl[3] = {0.0, 0.0, 0.0}, Bl[3] = {0.0, 0.0, 0.0};
-  bool bad_list = false, unstored = false, foreign = false;
-  // rounds are uniform over the workgroup (base depends on blockIdx only)
-  for (int base = blockIdx.x * kCells; base < len; base += gridDim.x * kCells) {
+  bool unstored = false, foreign = false;
+  // rounds are uniform over the workgroup
+  for (int base = 0; base < len; base += kCells) {
     const int i = base + g;
     int x = 0, y = 0, z = 0;
     uint32_t c = 0;
-    bool active = i < len;
-    if (active && !link_cell<A>(flags, owner, parts, pi, (int)list[i], p, ad, x, y, z, c)) {
-      bad_list = true;
-      active = false;
-    }
+    const bool active = i < len && link_cell<A>(flags, owner, parts, pi, (int)list[i], p, ad, x, y, z, c);
     if (active) {
-      if (s == 0) din[g][0] = Store<S>::load(src[c]);
+      if (s == 0) din[g][0] = Store<S>::load(src[ad.pop(0, c)]);
 #pragma unroll
       for (int k = 0; k < (kQ - 2) / kLinkLanes + 1; ++k) {
         const int q = 1 + s + kLinkLanes * k;
@@ -389,12 +409,12 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
         const int st2 = ad.locate(x + cq[0], y + cq[1], z + cq[2], ti, wa2, ws2);
         ti = st2 == 1 ? ti : c;
         const uint8_t tf = flags[ti];
-        const T v = Store<S>::load(src[(size_t)q * N + si]);
-        const T own_q = Store<S>::load(src[(size_t)q * N + c]);
-        const T own_qq = Store<S>::load(src[(size_t)qq * N + c]);
+        const T v = Store<S>::load(src[ad.pop(q, si)]);
+        const T own_q = Store<S>::load(src[ad.pop(q, c)]);
+        const T own_qq = Store<S>::load(src[ad.pop(qq, c)]);
         const bool wall = st == 0, link = wall || (sf & kSolid);
         const bool tok = link && !wall && st2 == 1 && !(tf & kSolid);
-        const T sec = Store<S>::load(src[(size_t)qq * N + (tok ? ti : c)]);
+        const T sec = Store<S>::load(src[ad.pop(qq, tok ? ti : c)]);
         T out = v;
         if (link && wall) {
           // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
@@ -448,11 +468,10 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
       if (!(drho == drho)) status[kStatusUnstable] = 1;
       SrBits rb(c, p.seed);
 #pragma unroll
-      for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store_sr(d[q], rb.next());
+      for (int q = 0; q < kQ; ++q) dst[ad.pop(q, c)] = Store<S>::store_sr(d[q], rb.next());
     }
     __syncthreads();
   }
-  if (bad_list) status[kStatusRange] = 9;
   if (unstored) status[kStatusRange] = 5;
   if (foreign) status[kStatusRange] = 2;
   write_force_slot(slots, p, pi, Fl, Tl, Kl, Bl);
@@ -464,11 +483,14 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
 // particle-link flag and the id of that sphere, one next to a wall the
 // wall-link flag
 // ---------------------------------------------------------------------------
+// OLD: with the positions the mapping in place was made with (xold) rather
+// than the current ones
+template <bool OLD = false>
 __device__ inline int cell_owner(int x, int y, int z, const DevParticle* __restrict__ parts, int np,
                                  const SweepParams& p) {
   for (int i = 0; i < np; ++i) {
     double off[3];
-    sphere_offset(parts[i].x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
+    sphere_offset(OLD ? parts[i].xold : parts[i].x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
     if (inside_sphere(off, parts[i].r)) return i;
   }
   return -1;
@@ -512,49 +534,23 @@ __device__ void map_cell(int x, int y, int z, uint32_t c, uint8_t* __restrict__ 
   owner[c] = link < 0 ? 0 : (uint16_t)link;
 }
 
-template <typename A>
-__global__ __launch_bounds__(256) void k_remap(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
-                                               const DevParticle* __restrict__ parts, int np, SweepParams p,
-                                               A ad, int* __restrict__ status) {
-  const int pi = blockIdx.y;
-  const DevParticle& P = parts[pi];
-  if (P.fixed) return;
-  const int rb = p.box + 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= rb * rb * rb) return;
-  int x, y, z, wa = 0, ws = 0;
-  uint32_t c = 0;
-  if (!box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1) return;
-  map_cell<A>(x, y, z, c, flags, owner, parts, np, p, ad, status);
-}
-
 // ---------------------------------------------------------------------------
 // refill of cells uncovered by a moving sphere (Sec. 2.3, after Dorschner):
 // rho = mean density of the D3Q19 neighbours that held fluid before the
 // re-mapping; v = rigid-body velocity; strain rate S from central differences
 // over the axis neighbours (fluid velocity where the neighbour held fluid,
 // rigid-body velocity of its sphere or the wall velocity otherwise);
-// f = f^eq(rho, v) - 3 w_q / s+ (c c - I/3) : S, then collided.  Runs before
-// the flags are updated, so flags/owner still describe the old mapping.
+// f = f^eq(rho, v) - 3 w_q / s+ (c c - I/3) : S, then collided.  The mapping
+// before the re-mapping is evaluated from the positions it was made with
+// (xold), so the refill reads no flags and can share a kernel with the
+// re-mapping that rewrites them.
 // ---------------------------------------------------------------------------
 template <typename S, typename A>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_refill(S* __restrict__ state, const uint8_t* __restrict__ flags,
-                                                const uint16_t* __restrict__ owner,
-                                                const DevParticle* __restrict__ parts, int np, SweepParams p,
-                                                A ad, int* __restrict__ status) {
+__device__ void refill_cell(S* __restrict__ state, const DevParticle* __restrict__ parts, int np,
+                            const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
+                            const DevParticle& P, int* __restrict__ status) {
   using T = typename Store<S>::T;
-  const int pi = blockIdx.y;
-  const DevParticle& P = parts[pi];
-  if (P.fixed) return;
-  const int rb = p.box + 1;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= rb * rb * rb) return;
-  int x, y, z, wa = 0, ws = 0;
-  uint32_t c = 0;
-  if (!box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1) return;
-  const uint32_t N = ad.N;
-  if (!(flags[c] & kSolid) || owner[c] != pi) return;
-  if (cell_owner(x, y, z, parts, np, p) >= 0) return;   // still covered
+  int wa = 0, ws = 0;
   // density from old-fluid neighbours.  Each stage issues its loads for all
   // neighbours before the first use; a neighbour that does not count reads
   // the cell itself and is dropped afterwards.
@@ -566,17 +562,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     nok[q] = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws) == 1;
     nc[q] = nok[q] ? sc : c;
   }
-  uint8_t nfl[kQ];
-#pragma unroll
-  for (int q = 1; q < kQ; ++q) nfl[q] = flags[nc[q]];
   double rsum = 0.0;
   int cnt = 0;
 #pragma unroll
   for (int q = 1; q < kQ; ++q) {
-    const bool use = nok[q] && !(nfl[q] & kSolid);
+    const bool use = nok[q] && cell_owner<true>(x + cx_of(q), y + cy_of(q), z + cz_of(q), parts, np, p) < 0;
     double r = 0.0;
 #pragma unroll
-    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[(size_t)r2 * N + nc[q]]);
+    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[ad.pop(r2, nc[q])]);
     rsum = use ? rsum + (1.0 + r) : rsum;
     cnt += use ? 1 : 0;
   }
@@ -603,13 +596,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       int wa2 = 0, ws2 = 0;
       const int st = ad.locate(s[0], s[1], s[2], sc, wa2, ws2);
       const uint32_t src = st == 1 ? sc : c;
-      const bool solid = (flags[src] & kSolid) != 0;
-      const int ow = owner[src];
-      const DevParticle& Q = parts[ow < np ? ow : 0];   // a fluid cell's owner entry is not a sphere
+      const int ow = st == 1 ? cell_owner<true>(s[0], s[1], s[2], parts, np, p) : -1;
+      const DevParticle& Q = parts[ow >= 0 ? ow : 0];
       double j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
-        const double dq = (double)Store<S>::load(state[(size_t)q * N + src]);
+        const double dq = (double)Store<S>::load(state[ad.pop(q, src)]);
         j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
       }
       if (st == 0) {
@@ -617,7 +609,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       } else if (st < 0) {
         unstored = true;
         for (int b = 0; b < 3; ++b) V[b] = v[b];
-      } else if (!solid) {
+      } else if (ow < 0) {
         // post-collision momentum minus F/2 is the macroscopic velocity
         for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
       } else {
@@ -647,7 +639,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   SrBits sr(c, ~p.seed);
-  for (int q = 0; q < kQ; ++q) state[(size_t)q * N + c] = Store<S>::store_sr(d[q], sr.next());
+  for (int q = 0; q < kQ; ++q) state[ad.pop(q, c)] = Store<S>::store_sr(d[q], sr.next());
+}
+
+// Re-mapping of a moving sphere's region (its box around the old and the new
+// position) and refill of the cells it uncovered.  The two are independent
+// (the refill reads populations and the positions, the re-mapping writes
+// flags), so the first half of the workgroups re-maps and the second half
+// refills, one thread per cell each, and the kernel lasts as long as the
+// slower of the two instead of their sum.  A cell whose centre lies more
+// than 1.6 cells off the sphere's surface at both positions keeps its
+// flags: neither it nor any of its neighbours (at most sqrt 2 away)
+// changes side.
+template <typename S, typename A>
+__global__ __launch_bounds__(256) void k_refill_remap(
+    S* __restrict__ state, uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
+    const DevParticle* __restrict__ parts, int np, SweepParams p, A ad, int* __restrict__ status) {
+  const int pi = blockIdx.y;
+  const DevParticle& P = parts[pi];
+  if (P.fixed) return;
+  const int rb = p.box + 1;
+  const int half = (int)gridDim.x / 2;
+  const bool refill = (int)blockIdx.x >= half;
+  const int k = (refill ? (int)blockIdx.x - half : (int)blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= rb * rb * rb) return;
+  int x, y, z, wa = 0, ws = 0;
+  uint32_t c = 0;
+  if (!box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1) return;
+  double dn[3], dd[3];
+  sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, dn);
+  sphere_offset(P.xold, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, dd);
+  const double an = sqrt(dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2]);
+  const double ao = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  constexpr double kMargin = 1.6;
+  if ((an > P.r + kMargin && ao > P.r + kMargin) || (an < P.r - kMargin && ao < P.r - kMargin)) return;
+  if (!refill) map_cell<A>(x, y, z, c, flags, owner, parts, np, p, ad, status);
+  else if (cell_owner<true>(x, y, z, parts, np, p) == pi && cell_owner(x, y, z, parts, np, p) < 0)
+    refill_cell<S, A>(state, parts, np, p, ad, x, y, z, c, P, status);
 }
 
 }  // namespace vm

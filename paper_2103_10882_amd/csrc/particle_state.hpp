@@ -9,6 +9,7 @@ namespace vm {
 // ---------------------------------------------------------------------------
 struct DevParticle {
   double x[3], u[3], w[3];
+  double xold[3];              // position the mapping in place was made with (before the last update)
   double a[3], b[3];           // translational / angular acceleration of the previous step
   double F[3], T[3];           // raw hydrodynamic F^n, T^n of the last step
   double Fprev[3], Tprev[3];   // of the step before

@@ -1,7 +1,7 @@
 // Block-structured 2:1 refined grid (Sec. 4.1-4.2) with sub-cycled levels.
 //
-// Every level stores 16^3-cell blocks in slots, populations SoA
-// [q][slot][16][16][16] (post-collision deviations, storage type S), two
+// Every level stores 16^3-cell blocks in slots, populations blocked
+// [slot][q][16][16][16] (post-collision deviations, storage type S), two
 // buffers per level.  Level l holds its leaf blocks ("interior") and ghost
 // blocks: block positions of level l inside level-(l-1) leaves next to a
 // level-l leaf; their cells within two level-l cells of the level-l region
@@ -37,10 +37,6 @@ namespace vm {
 namespace {
 
 constexpr uint8_t kIface = 0x10;   // interior cell with a coalescence pull
-// workgroups per sphere of the finest level's link-cell pass: 256 / lanes
-// cells each, 8192 cells a round, so that a sphere's link cells (about
-// 4 pi r^2) fit one round up to r ~ 25
-constexpr int kRefineLinkGroups = 32 * kLinkLanes;
 // deepest hierarchy: the per-level seeds step by 8 per finest step, and the
 // migration kernel takes per-level tables by value
 constexpr int kMaxLevels = 8;
@@ -695,8 +691,8 @@ __device__ __forceinline__ int nbr_slot(const LevelArgs& a, const int* pos3, int
 // population q of local cell (x,y,z) pulled from x - c_q, via the neighbour
 // slot table nb[27]; returns false if the source block is not stored
 template <typename S, int Q, bool CHECK = true>
-__device__ __forceinline__ bool pull_block(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x,
-                                           int y, int z, typename Store<S>::T& out) {
+__device__ __forceinline__ bool pull_block(const S* __restrict__ src, const int* nbs, int slot, int x, int y, int z,
+                                           typename Store<S>::T& out) {
   constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
   int xs = x - cx, ys = y - cy, zs = z - cz;
   const int bx = xs < 0 ? -1 : (xs > 15 ? 1 : 0), by = ys < 0 ? -1 : (ys > 15 ? 1 : 0),
@@ -704,29 +700,29 @@ __device__ __forceinline__ bool pull_block(const S* __restrict__ src, uint32_t N
   const int s = (bx | by | bz) ? nbs[(bz + 1) * 9 + (by + 1) * 3 + (bx + 1)] : slot;
   if (CHECK && s < 0) return false;
   const uint32_t c = (uint32_t)s * kBlockCells + (uint32_t)(((zs & 15) * 16 + (ys & 15)) * 16 + (xs & 15));
-  out = Store<S>::load(src[(size_t)Q * N + c]);
+  out = Store<S>::load(src[bpop(Q, c)]);
   return true;
 }
 
 template <typename S, bool CHECK, int... Qs>
-__device__ __forceinline__ bool pull_cell(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x, int y,
-                                          int z, typename Store<S>::T (&d)[kQ], std::integer_sequence<int, Qs...>) {
-  return (pull_block<S, Qs, CHECK>(src, N, nbs, slot, x, y, z, d[Qs]) & ...);
+__device__ __forceinline__ bool pull_cell(const S* __restrict__ src, const int* nbs, int slot, int x, int y, int z,
+                                          typename Store<S>::T (&d)[kQ], std::integer_sequence<int, Qs...>) {
+  return (pull_block<S, Qs, CHECK>(src, nbs, slot, x, y, z, d[Qs]) & ...);
 }
 
 // the populations of mask `dirs` of a ghost cell; a source block that is not
 // stored gives 0.  All loads are issued before the first store.
 template <typename S, int Q>
-__device__ __forceinline__ void ghost_pull_one(const S* __restrict__ src, uint32_t N, const int* nbs, int slot,
-                                               int x, int y, int z, uint32_t dirs, typename Store<S>::T& d) {
-  if (!((dirs >> Q) & 1u) || !pull_block<S, Q>(src, N, nbs, slot, x, y, z, d)) d = typename Store<S>::T(0);
+__device__ __forceinline__ void ghost_pull_one(const S* __restrict__ src, const int* nbs, int slot, int x, int y,
+                                               int z, uint32_t dirs, typename Store<S>::T& d) {
+  if (!((dirs >> Q) & 1u) || !pull_block<S, Q>(src, nbs, slot, x, y, z, d)) d = typename Store<S>::T(0);
 }
 
 template <typename S, int... Qs>
-__device__ __forceinline__ void ghost_pull(const S* __restrict__ src, uint32_t N, const int* nbs, int slot, int x,
-                                           int y, int z, uint32_t dirs, typename Store<S>::T (&d)[kQ],
+__device__ __forceinline__ void ghost_pull(const S* __restrict__ src, const int* nbs, int slot, int x, int y, int z,
+                                           uint32_t dirs, typename Store<S>::T (&d)[kQ],
                                            std::integer_sequence<int, Qs...>) {
-  (ghost_pull_one<S, Qs>(src, N, nbs, slot, x, y, z, dirs, d[Qs]), ...);
+  (ghost_pull_one<S, Qs>(src, nbs, slot, x, y, z, dirs, d[Qs]), ...);
 }
 
 __device__ __forceinline__ void load_neighbours(const LevelArgs& a, int slot, int* nbs) {
@@ -749,12 +745,12 @@ __device__ __forceinline__ uint32_t xcd_contiguous(uint32_t lin, uint32_t G) {
 
 // plane z of one block; CHECK: test that the blocks a cell's pulls reach are
 // stored (needed only when a neighbour slot is missing)
-template <typename S, bool CHECK>
+template <typename S, bool CHECK, bool MRT>
 __device__ __forceinline__ void sweep_plane(const S* __restrict__ src, S* __restrict__ dst,
                                             const uint8_t* __restrict__ flags, int* __restrict__ status,
                                             const LevelArgs& a, const int* nbs, int slot, int z) {
   using T = typename Store<S>::T;
-  const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
+  const int x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15;
   // CHECK: the pulls of a cell reach the face and edge neighbour blocks on
   // its sides (D3Q19 has no body diagonals, so never the corner block); the
   // cell is tested once against those instead of per direction
@@ -768,7 +764,7 @@ __device__ __forceinline__ void sweep_plane(const S* __restrict__ src, S* __rest
     if constexpr (CHECK && sizeof(S) == 8) {
       // FP64 keeps the per-direction test: the per-cell one costs it
       // registers (occupancy 3 -> 2)
-      if (!pull_cell<S, true>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
+      if (!pull_cell<S, true>(src, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{})) {
         status[kStatusRange] = 6;
         return;
       }
@@ -780,26 +776,27 @@ __device__ __forceinline__ void sweep_plane(const S* __restrict__ src, S* __rest
           return;
         }
       }
-      pull_cell<S, false>(src, a.N, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
+      pull_cell<S, false>(src, nbs, slot, x, y, z, d, std::make_integer_sequence<int, kQ>{});
     }
-    const T drho = lbm_collide<T>(d, T(a.sp), T(a.sm), T(a.sb), T(a.F[0]), T(a.F[1]), T(a.F[2]));
+    const T drho = lbm_collide<T, MRT>(d, T(a.sp), T(a.sm), T(a.sb), T(a.F[0]), T(a.F[1]), T(a.F[2]));
     if (!(drho == drho)) status[kStatusUnstable] = 1;
     SrBits rb(c, a.seed);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * a.N + c], Store<S>::store_sr(d[q], rb.next()));
+    for (int q = 0; q < kQ; ++q) store_nt(&dst[bpop(q, c)], Store<S>::store_sr(d[q], rb.next()));
   }
 }
 
 // interior blocks of a level: pull + collide, cells with flags left out.
-// One workgroup per plane of a block (gridDim.y = 16), one thread per cell:
-// straight-line code needs 62 registers in FP16 and FP32 (124 in FP64)
-// against 109 (166) for a loop over planes, and holds twice the waves.
+// One workgroup per P planes of a block (gridDim.y = 16 / P), one thread per
+// cell: straight-line code needs 62 registers in FP16 and FP32 (124 in
+// FP64) against 109 (166) for a loop over planes, and holds twice the waves.
 // FP32 and FP16 storage number the work XCD-contiguously (3-4 % faster on the
 // 3-level workload); FP64 keeps launch order (3 % slower otherwise).
-template <typename S>
-__global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
-                                                     const uint8_t* __restrict__ flags, const int* __restrict__ list,
-                                                     int* __restrict__ status, LevelArgs a) {
+template <typename S, int P, bool MRT>
+__global__ __launch_bounds__(256 * P) void k_level_sweep(const S* __restrict__ src, S* __restrict__ dst,
+                                                         const uint8_t* __restrict__ flags,
+                                                         const int* __restrict__ list, int* __restrict__ status,
+                                                         LevelArgs a) {
   __shared__ int nbs[27];
   __shared__ int all_stored;
   const uint32_t lin = blockIdx.y * gridDim.x + blockIdx.x;
@@ -812,11 +809,25 @@ __global__ __launch_bounds__(256) void k_level_sweep(const S* __restrict__ src, 
     all_stored = ok;
   }
   __syncthreads();
-  const int z = (int)(item % gridDim.y);
+  const int z = (int)(item % gridDim.y) * P + (int)(threadIdx.x >> 8);
   // one test per workgroup instead of one per direction and cell
-  if (all_stored) sweep_plane<S, false>(src, dst, flags, status, a, nbs, slot, z);
-  else sweep_plane<S, true>(src, dst, flags, status, a, nbs, slot, z);
+  if (all_stored) sweep_plane<S, false, MRT>(src, dst, flags, status, a, nbs, slot, z);
+  else sweep_plane<S, true, MRT>(src, dst, flags, status, a, nbs, slot, z);
 }
+
+#ifndef VM_PLANES_F64
+#define VM_PLANES_F64 1
+#endif
+#ifndef VM_PLANES_F32
+#define VM_PLANES_F32 1
+#endif
+#ifndef VM_PLANES_F16
+#define VM_PLANES_F16 1
+#endif
+template <typename S> struct LevelPlanes;
+template <> struct LevelPlanes<double> { static constexpr int value = VM_PLANES_F64; };
+template <> struct LevelPlanes<float> { static constexpr int value = VM_PLANES_F32; };
+template <> struct LevelPlanes<__half> { static constexpr int value = VM_PLANES_F16; };
 
 // ghost cells (the band of each ghost block listed in band[band_off[g] ..
 // band_off[g+1]) as local cell indices): stream only; sources not stored at
@@ -847,10 +858,10 @@ __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src,
     const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)local;
     T d[kQ];
-    ghost_pull<S>(src, a.N, nbs, slot, x, y, z, m, d, std::make_integer_sequence<int, kQ>{});
+    ghost_pull<S>(src, nbs, slot, x, y, z, m, d, std::make_integer_sequence<int, kQ>{});
 #pragma unroll
     for (int q = 1; q < kQ; ++q)
-      if ((m >> q) & 1u) dst[(size_t)q * a.N + c] = Store<S>::store(d[q]);
+      if ((m >> q) & 1u) dst[bpop(q, c)] = Store<S>::store(d[q]);
   }
 }
 
@@ -860,8 +871,7 @@ __global__ __launch_bounds__(256) void k_ghost_stream(const S* __restrict__ src,
 template <typename S>
 __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S* __restrict__ fine,
                                                  const int* __restrict__ ex, const int* __restrict__ band_off,
-                                                 const uint16_t* __restrict__ band, const uint32_t* __restrict__ dirs,
-                                                 uint32_t Nc, uint32_t Nf) {
+                                                 const uint16_t* __restrict__ band, const uint32_t* __restrict__ dirs) {
   const int* e = ex + 5 * blockIdx.x;
   const int gs = e[0], ps = e[1], ox = e[2], oy = e[3], oz = e[4];
   const int b1 = band_off[blockIdx.x + 1];
@@ -876,10 +886,10 @@ __global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S
     S v[kQ];
 #pragma unroll
     for (int q = 1; q < kQ; ++q)
-      if ((m >> q) & 1u) v[q] = coarse[(size_t)q * Nc + cc];
+      if ((m >> q) & 1u) v[q] = coarse[bpop(q, cc)];
 #pragma unroll
     for (int q = 1; q < kQ; ++q)
-      if ((m >> q) & 1u) fine[(size_t)q * Nf + cf] = v[q];
+      if ((m >> q) & 1u) fine[bpop(q, cf)] = v[q];
   }
 }
 
@@ -891,7 +901,7 @@ constexpr int kIfaceCells = 16;
 template <typename S>
 __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __restrict__ dst,
                                                const S* __restrict__ fine, const IfaceEntry* __restrict__ tab,
-                                               int count, int* __restrict__ status, LevelArgs a, uint32_t Nf) {
+                                               int count, int* __restrict__ status, LevelArgs a) {
   using T = typename Store<S>::T;
   __shared__ double pre[kIfaceCells][kQ];
   const int e0 = blockIdx.x * kIfaceCells;
@@ -903,7 +913,7 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
     const int j = p / kQ, q = p - j * kQ;
     const IfaceEntry& e = tab[e0 + j];
     const float wq = e.weight[q];
-    const double sv = (double)Store<S>::load(src[(size_t)q * a.N + e.src[q]]);
+    const double sv = (double)Store<S>::load(src[bpop(q, e.src[q])]);
     double v = wq != 0.0f ? (double)wq * sv : 0.0;
     const unsigned mk = e.mask[q];
     const uint32_t c0 = (uint32_t)e.fine_slot * kBlockCells + (uint32_t)e.fine_local;
@@ -911,7 +921,7 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const uint32_t cf = (mk & (1u << m)) ? c0 + (uint32_t)(((m >> 2) * 16 + ((m >> 1) & 1)) * 16 + (m & 1)) : 0u;
-      ch[m] = Store<S>::load(fine[(size_t)q * Nf + cf]);
+      ch[m] = Store<S>::load(fine[bpop(q, cf)]);
     }
     if (mk) {
       double acc = 0.0;
@@ -932,7 +942,7 @@ __global__ __launch_bounds__(256) void k_iface(const S* __restrict__ src, S* __r
   const uint32_t c = (uint32_t)e.slot * kBlockCells + (uint32_t)e.local;
   SrBits rb(c, a.seed);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store_sr(d[q], rb.next());
+  for (int q = 0; q < kQ; ++q) dst[bpop(q, c)] = Store<S>::store_sr(d[q], rb.next());
 }
 
 // stored post-collision velocity of every interior cell of a level:
@@ -946,7 +956,7 @@ __global__ __launch_bounds__(256) void k_level_velocity(const S* __restrict__ sr
     double j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 1; q < kQ; ++q) {
-      const double d = (double)Store<S>::load(src[(size_t)q * a.N + c]);
+      const double d = (double)Store<S>::load(src[bpop(q, c)]);
       j[0] += cx_of(q) * d;
       j[1] += cy_of(q) * d;
       j[2] += cz_of(q) * d;
@@ -1040,7 +1050,7 @@ __global__ __launch_bounds__(256) void k_init_level(S* __restrict__ dst, const d
     const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
     SrBits rb(c, a.seed);
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * a.N + c] = Store<S>::store_sr(d[q], rb.next());
+    for (int q = 0; q < kQ; ++q) dst[bpop(q, c)] = Store<S>::store_sr(d[q], rb.next());
   }
 }
 
@@ -1067,13 +1077,12 @@ struct MigrateArgs {
   const void* old_pdf[kMaxLevels];
   const int* old_slot_of[kMaxLevels];
   int nb[kMaxLevels][3];
-  uint32_t oldN[kMaxLevels];
   uint32_t seed;
 };
 
 template <typename S>
 __global__ __launch_bounds__(256) void k_migrate(S* __restrict__ dst, const int* __restrict__ list,
-                                                 const int* __restrict__ pos, int l, uint32_t N, MigrateArgs m,
+                                                 const int* __restrict__ pos, int l, MigrateArgs m,
                                                  int* __restrict__ status) {
   const int slot = list[blockIdx.x];
   const int x = threadIdx.x & 15, y = threadIdx.x >> 4;
@@ -1094,7 +1103,7 @@ __global__ __launch_bounds__(256) void k_migrate(S* __restrict__ dst, const int*
       else {
         const uint32_t oc = (uint32_t)os * kBlockCells + (uint32_t)(((ck & 15) * 16 + (cj & 15)) * 16 + (ci & 15));
         const S* src = (const S*)m.old_pdf[lo];
-        for (int q = 0; q < kQ; ++q) v[q] = (double)Store<S>::load(src[(size_t)q * m.oldN[lo] + oc]);
+        for (int q = 0; q < kQ; ++q) v[q] = (double)Store<S>::load(src[bpop(q, oc)]);
       }
     } else {
       const int sh = lo - l, e = 1 << sh;
@@ -1106,14 +1115,14 @@ __global__ __launch_bounds__(256) void k_migrate(S* __restrict__ dst, const int*
             const int os = m.old_slot_of[lo][((long)(ck >> 4) * m.nb[lo][1] + (cj >> 4)) * m.nb[lo][0] + (ci >> 4)];
             if (os < 0) { ok = false; break; }
             const uint32_t oc = (uint32_t)os * kBlockCells + (uint32_t)(((ck & 15) * 16 + (cj & 15)) * 16 + (ci & 15));
-            for (int q = 0; q < kQ; ++q) v[q] += (double)Store<S>::load(src[(size_t)q * m.oldN[lo] + oc]);
+            for (int q = 0; q < kQ; ++q) v[q] += (double)Store<S>::load(src[bpop(q, oc)]);
           }
       const double inv = 1.0 / (double)(e * e * e);
       for (int q = 0; q < kQ; ++q) v[q] *= inv;
     }
     if (!ok) status[kStatusRange] = 8;
     SrBits rb(c, m.seed);
-    for (int q = 0; q < kQ; ++q) dst[(size_t)q * N + c] = Store<S>::store_sr((typename Store<S>::T)v[q], rb.next());
+    for (int q = 0; q < kQ; ++q) dst[bpop(q, c)] = Store<S>::store_sr((typename Store<S>::T)v[q], rb.next());
   }
 }
 
@@ -1226,10 +1235,6 @@ int mark_flags(vmlbm_ctx* c) {
                                                 c->parts(), np, finest_params(c), finest_addr(c),
                                                 (const int*)(c->ws + V.off_pos), c->status());
     HIP_TRY(c, hipGetLastError());
-    const LinkLists ll = c->links();
-    HIP_TRY(c, launch_link_lists<BAddr>((const uint8_t*)(c->ws + V.off_flags), (const uint16_t*)(c->ws + f.off_owner),
-                                        c->parts(), np, finest_params(c), finest_addr(c), ll.count, ll.links, ll.len,
-                                        c->stream));
   }
   return VMLBM_OK;
 }
@@ -1244,7 +1249,7 @@ int explode(vmlbm_ctx* c, int l) {
     k_explode<S><<<dim3(F.n_ghost, kBandSplit), 256, 0, c->stream>>>(
         (const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]), (const int*)(c->ws + F.off_explode),
         (const int*)(c->ws + F.off_band_off), (const uint16_t*)(c->ws + F.off_band),
-        (const uint32_t*)(c->ws + F.off_band_dirs), (uint32_t)C.cap * kBlockCells, (uint32_t)F.cap * kBlockCells);
+        (const uint32_t*)(c->ws + F.off_band_dirs));
     HIP_TRY(c, hipGetLastError());
     return VMLBM_OK;
   });
@@ -1274,18 +1279,25 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
     if (V.n_int) {
-      // one workgroup per plane of each block (measured on the 3-level
-      // workload against whole blocks and 2, 4 or 8 planes per workgroup)
-      const dim3 grid(V.n_int, kBlock);
-      k_level_sweep<S><<<grid, 256, 0, c->stream>>>((const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags),
-                                                    (const int*)(c->ws + V.off_int), c->status(), a);
+      // P planes of a block per workgroup, by storage format (measured on
+      // the 3-level workload)
+      constexpr int P = LevelPlanes<S>::value;
+      const dim3 grid(V.n_int, kBlock / P);
+      if (a.sb != a.sp)
+        k_level_sweep<S, P, true><<<grid, 256 * P, 0, c->stream>>>(
+            (const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags), (const int*)(c->ws + V.off_int),
+            c->status(), a);
+      else
+        k_level_sweep<S, P, false><<<grid, 256 * P, 0, c->stream>>>(
+            (const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags), (const int*)(c->ws + V.off_int),
+            c->status(), a);
       HIP_TRY(c, hipGetLastError());
     }
     if (V.n_iface) {
       Forest::Lev& F = f.lv[l + 1];
       k_iface<S><<<(V.n_iface + kIfaceCells - 1) / kIfaceCells, 256, 0, c->stream>>>(
           (const S*)src, (S*)dst, (const S*)(c->ws + F.off_pdf[F.cur]), (const IfaceEntry*)(c->ws + V.off_iface),
-          V.n_iface, c->status(), a, (uint32_t)F.cap * kBlockCells);
+          V.n_iface, c->status(), a);
       HIP_TRY(c, hipGetLastError());
     }
     if (V.n_ghost) {
@@ -1295,11 +1307,11 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
       HIP_TRY(c, hipGetLastError());
     }
     if (l == f.L && np) {
+      // link cells found per workgroup in its share of each sphere's box
       const SweepParams p = finest_params(c);
-      const LinkLists ll = c->links();
-      k_link_cells<S, BAddr><<<dim3(kRefineLinkGroups, np), dim3(256), 0, c->stream>>>(
+      k_link_cells<S, BAddr><<<dim3(link_chunks(p.box), np), dim3(256), 0, c->stream>>>(
           (const S*)src, (S*)dst, (const uint8_t*)(c->ws + V.off_flags), (const uint16_t*)(c->ws + f.off_owner),
-          c->parts(), ll.links, ll.len, c->slots(), c->status(), p, finest_addr(c));
+          c->parts(), c->slots(), c->status(), p, finest_addr(c));
       HIP_TRY(c, hipGetLastError());
     }
     return VMLBM_OK;
@@ -1310,40 +1322,29 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
   if (l == f.L) {
     if (np) {
       const SweepParams p = finest_params(c);
-      UpdateParams u{};
-      for (int i = 0; i < 3; ++i) u.g[i] = c->cfg.gravity[i];
-      u.step = (int)(c->fine_steps_done % std::max(c->cfg.history, 1));
-      u.hist_len = std::max(c->cfg.history, 1);
-      u.np = np;
       // After the second of two finest steps the coarser level's sweep
       // comes next and touches no particle data, so the particle update
-      // runs beside it on the side stream; the next finest step, the end
-      // of the coarse step and the layout check join it.
+      // (reduction, re-mapping and refill) runs beside it on the side
+      // stream; the next finest step, the end of the coarse step and the
+      // layout check join it.
       hipStream_t ps = c->stream;
       if (sub == 1 && f.L > 0) {
         HIP_TRY(c, hipEventRecord(c->ev_fork, c->stream));
         HIP_TRY(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
         ps = c->side;
       }
-      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, u, ps));
+      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p,
+                                      update_params(c, c->fine_steps_done), ps));
       if (c->moving) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;
           const int rb = p.box + 1;
-          dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
-          k_refill<S, BAddr><<<grid, block, 0, ps>>>((S*)(c->ws + V.off_pdf[V.cur]),
-                                                             (const uint8_t*)(c->ws + V.off_flags),
-                                                             (const uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
-                                                             finest_addr(c), c->status());
+          dim3 grid(2 * ((rb * rb * rb + 255) / 256), np), block(256);
+          k_refill_remap<S, BAddr><<<grid, block, 0, ps>>>((S*)(c->ws + V.off_pdf[V.cur]),
+                                                           (uint8_t*)(c->ws + V.off_flags),
+                                                           (uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
+                                                           finest_addr(c), c->status());
           HIP_TRY(c, hipGetLastError());
-          k_remap<BAddr><<<grid, block, 0, ps>>>((uint8_t*)(c->ws + V.off_flags),
-                                                 (uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
-                                                 finest_addr(c), c->status());
-          HIP_TRY(c, hipGetLastError());
-          const LinkLists ll = c->links();
-          HIP_TRY(c, launch_link_lists<BAddr>((const uint8_t*)(c->ws + V.off_flags),
-                                              (const uint16_t*)(c->ws + f.off_owner), c->parts(), np, p,
-                                              finest_addr(c), ll.count, ll.links, ll.len, ps));
           return VMLBM_OK;
         });
         if (rc) return rc;
@@ -1454,7 +1455,6 @@ int check_layout(vmlbm_ctx* c) {
     m.old_pdf[l] = c->ws + V.off_pdf[V.cur];
     m.old_slot_of[l] = (const int*)(c->ws + V.off_slot_of[V.tab]);
     for (int a = 0; a < 3; ++a) m.nb[l][a] = V.nb[a];
-    m.oldN[l] = (uint32_t)V.cap * kBlockCells;
   }
   std::vector<int8_t> old = f.leaf;
   f.leaf = nl;
@@ -1470,7 +1470,7 @@ int check_layout(vmlbm_ctx* c) {
       Forest::Lev& V = f.lv[l];
       if (!V.n_int) continue;
       k_migrate<S><<<V.n_int, 256, 0, c->stream>>>((S*)(c->ws + V.off_pdf[1 - V.cur]), (const int*)(c->ws + V.off_int),
-                                                   (const int*)(c->ws + V.off_pos), l, (uint32_t)V.cap * kBlockCells, m,
+                                                   (const int*)(c->ws + V.off_pos), l, m,
                                                    c->status());
       HIP_TRY(c, hipGetLastError());
     }
@@ -1538,7 +1538,8 @@ int refine_plan(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  c->slot_stride = (size_t)kRefineLinkGroups * 4 * kSlotWords;
+  // one force slot per workgroup of the link-cell pass (a box share each)
+  c->slot_stride = (size_t)link_chunks(box) * kSlotWords;
   const int np = (int)c->spheres.size();
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = (off + bytes + 255) & ~size_t(255); return o; };
@@ -1547,9 +1548,6 @@ int refine_plan(vmlbm_ctx* c) {
   c->off_slots = take(std::max<size_t>(np * c->slot_stride, 1) * sizeof(double));
   c->off_hist = take((size_t)std::max(c->cfg.history, 1) * std::max(np, 1) * kHistWords * sizeof(double));
   c->off_totals = take((size_t)kTotalsGroups * 8 * sizeof(double));
-  c->off_lcount = take((size_t)std::max(np, 1) * link_chunks(box) * sizeof(int));
-  c->off_links = take((size_t)std::max(np, 1) * box * box * box * sizeof(uint32_t));
-  c->off_llen = take((size_t)std::max(np, 1) * sizeof(int));
   for (int l = 0; l <= f.L; ++l) {
     Forest::Lev& V = f.lv[l];
     V.cap = (int)std::max<long>(cap[l], (long)(V.pos.size() / 3));
@@ -1595,6 +1593,7 @@ int refine_init(vmlbm_ctx* c, double rho, const double* u0) {
     memset(&P, 0, sizeof(P));
     for (int a = 0; a < 3; ++a) {
       P.x[a] = s.x[a];
+      P.xold[a] = s.x[a];
       P.u[a] = s.fixed ? 0.0 : s.u[a];
       P.w[a] = s.fixed == 1 ? 0.0 : s.w[a];
     }
@@ -1681,19 +1680,18 @@ static int read_level_raw(vmlbm_ctx* c, int level, std::vector<double>& out, std
   const size_t cells = (size_t)V.n_int * kBlockCells;
   out.assign(kQ * cells, 0.0);
   fl.assign(cells, 0);
-  std::vector<char> raw(cells * S);
-  for (int q = 0; q < kQ; ++q) {
-    // interior slots are 0..n_int-1, contiguous at the front of the pool
-    HIP_TRY(c, hipMemcpy(raw.data(), c->ws + V.off_pdf[V.cur] + ((size_t)q * V.cap * kBlockCells) * S, cells * S,
-                         hipMemcpyDeviceToHost));
+  std::vector<char> raw(kQ * cells * S);
+  // interior slots are 0..n_int-1, contiguous at the front of the pool
+  HIP_TRY(c, hipMemcpy(raw.data(), c->ws + V.off_pdf[V.cur], kQ * cells * S, hipMemcpyDeviceToHost));
+  for (int q = 0; q < kQ; ++q)
     for (size_t i = 0; i < cells; ++i) {
+      const size_t k = bpop(q, (uint32_t)i);
       double d;
-      if (c->cfg.storage == VMLBM_F64) d = ((const double*)raw.data())[i];
-      else if (c->cfg.storage == VMLBM_F32) d = ((const float*)raw.data())[i];
-      else d = __half2float(((const __half*)raw.data())[i]);
+      if (c->cfg.storage == VMLBM_F64) d = ((const double*)raw.data())[k];
+      else if (c->cfg.storage == VMLBM_F32) d = ((const float*)raw.data())[k];
+      else d = __half2float(((const __half*)raw.data())[k]);
       out[q * cells + i] = w_of(q) + d;
     }
-  }
   HIP_TRY(c, hipMemcpy(fl.data(), c->ws + V.off_flags, cells, hipMemcpyDeviceToHost));
   return VMLBM_OK;
 }
@@ -1718,17 +1716,16 @@ int refine_write_populations(vmlbm_ctx* c, int level, const double* in) {
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   const size_t S = storage_bytes(c->cfg.storage);
   const size_t cells = (size_t)V.n_int * kBlockCells;
-  std::vector<char> raw(cells * S);
-  for (int q = 0; q < kQ; ++q) {
+  std::vector<char> raw(kQ * cells * S);
+  for (int q = 0; q < kQ; ++q)
     for (size_t i = 0; i < cells; ++i) {
+      const size_t k = bpop(q, (uint32_t)i);
       const double d = in[q * cells + i] - w_of(q);
-      if (c->cfg.storage == VMLBM_F64) ((double*)raw.data())[i] = d;
-      else if (c->cfg.storage == VMLBM_F32) ((float*)raw.data())[i] = (float)d;
-      else ((uint16_t*)raw.data())[i] = half_bits_rne(d);
+      if (c->cfg.storage == VMLBM_F64) ((double*)raw.data())[k] = d;
+      else if (c->cfg.storage == VMLBM_F32) ((float*)raw.data())[k] = (float)d;
+      else ((uint16_t*)raw.data())[k] = half_bits_rne(d);
     }
-    HIP_TRY(c, hipMemcpy(c->ws + V.off_pdf[V.cur] + ((size_t)q * V.cap * kBlockCells) * S, raw.data(), cells * S,
-                         hipMemcpyHostToDevice));
-  }
+  HIP_TRY(c, hipMemcpy(c->ws + V.off_pdf[V.cur], raw.data(), kQ * cells * S, hipMemcpyHostToDevice));
   return VMLBM_OK;
 }
 

@@ -57,14 +57,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // Addressing of a lattice of one level: locate() maps (possibly out-of-range)
-// cell coordinates to a cell index; populations of cell c, direction q live
-// at q * N + c.
+// cell coordinates to a cell index c; pop(q, c) is the element of
+// population q of cell c.
 //
-// Uniform grid: cells [z][y][x]; periodic axes wrap, other axes end in walls.
+// Uniform grid: cells [z][y][x], populations SoA [q][z][y][x]; periodic axes
+// wrap, other axes end in walls.
 struct UAddr {
   int n[3];
   int per[3];
   uint32_t N;
+  __device__ __forceinline__ size_t pop(int q, uint32_t c) const { return (size_t)q * N + c; }
   // 1: stored cell c; 0: outside through the wall (axis wa, side ws)
   __device__ __forceinline__ int locate(int x, int y, int z, uint32_t& c, int& wa, int& ws) const {
     int s[3] = {x, y, z};
@@ -83,13 +85,20 @@ struct UAddr {
 // One level of the block-structured grid: 16^3-cell blocks in slots
 // (cell index = slot * 4096 + local), periodic; a dense table gives the slot
 // of every block position of the level (negative: not stored at this level).
+// Populations are blocked, [slot][q][16][16][16]: the 19 populations of a
+// block are one contiguous range, so a sweep of a block and its neighbours
+// touches a few contiguous regions instead of 19 widely separated arrays.
 constexpr int kBlock = 16;
 constexpr int kBlockCells = kBlock * kBlock * kBlock;
+__host__ __device__ __forceinline__ size_t bpop(int q, uint32_t c) {
+  return (size_t)(c >> 12) * (kQ * kBlockCells) + (size_t)q * kBlockCells + (c & (kBlockCells - 1));
+}
 struct BAddr {
   int n[3];            // cells of the level per axis
   int nb[3];           // block positions of the level per axis
   const int* slot_of;  // [nb2][nb1][nb0]
-  uint32_t N;          // population stride: slot capacity * 4096
+  uint32_t N;          // cells of the slot pool: slot capacity * 4096
+  __device__ __forceinline__ size_t pop(int q, uint32_t c) const { return bpop(q, c); }
   // 1: stored cell c; -1: not stored at this level (c unchanged).  Written
   // with bit masks rather than a branch on the loaded slot, so that callers
   // can issue the lookups of several cells before waiting for any.

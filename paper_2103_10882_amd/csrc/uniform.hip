@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, ui
 
 // fixed-order partial sums over fluid cells: count, sum of deviations and
 // their first moment; grid-stride over the cell range (or the listed 16^3
-// slots of a block level)
+// slots of a block level, whose populations are blocked)
 template <typename S>
 __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ pdf, const uint8_t* __restrict__ flags,
                                                 uint32_t N, uint32_t cells, const int* __restrict__ slots,
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ pdf, const
     if (flags && (flags[c] & kSolid)) continue;
     v[0] += 1.0;
     for (int q = 0; q < kQ; ++q) {
-      const double d = (double)Store<S>::load(pdf[(size_t)q * N + c]);
+      const double d = (double)Store<S>::load(pdf[slots ? bpop(q, c) : (size_t)q * N + c]);
       v[1] += d;
       v[2] += cx_of(q) * d;
       v[3] += cy_of(q) * d;
@@ -202,6 +202,21 @@ __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ pdf, const
   __syncthreads();
   if (threadIdx.x == 0)
     for (int k = 0; k < 5; ++k) part[8 * blockIdx.x + k] = red[k][0] + red[k][1] + red[k][2] + red[k][3];
+}
+
+// plain copy, one 16-byte load and one streaming 16-byte store per thread
+typedef float vec4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const vec4f* __restrict__ src, vec4f* __restrict__ dst,
+                                                     size_t n) {
+  const size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(src[i], &dst[i]);
+}
+
+// one workgroup per sphere: force/torque reduction and particle update
+__global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__ parts, const double* __restrict__ slots,
+                                                       double* __restrict__ hist, int* __restrict__ status,
+                                                       SweepParams p, UpdateParams u) {
+  reduce_update(parts, slots, hist, status, p, u, blockIdx.x);
 }
 
 }  // namespace
@@ -309,6 +324,18 @@ hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double
   return hipGetLastError();
 }
 
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  if (n) k_stream_copy<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>((const vec4f*)src, (vec4f*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_update(DevParticle* parts, int np, const double* slots, double* hist, int* status,
+                                const SweepParams& p, const UpdateParams& u, hipStream_t st) {
+  k_reduce_update<<<dim3(np), dim3(256), 0, st>>>(parts, slots, hist, status, p, u);
+  return hipGetLastError();
+}
+
 hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
                           const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st) {
   dim3 grid((p.N + 255) / 256), block(256);
@@ -322,12 +349,9 @@ template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
                                const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st) {
   const int rb = p.box + 1;
-  dim3 grid((rb * rb * rb + 255) / 256, np), block(256);
-  k_refill<S, UAddr><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p, uaddr(p), status);
+  dim3 grid(2 * ((rb * rb * rb + 255) / 256), np), block(256);
+  k_refill_remap<S, UAddr><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p, uaddr(p), status);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  k_remap<UAddr><<<grid, block, 0, st>>>(flags, owner, parts, np, p, uaddr(p), status);
-  e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_link_lists<UAddr>(flags, owner, parts, np, p, uaddr(p), ll.count, ll.links, ll.len, st);
 }
@@ -339,7 +363,7 @@ template hipError_t launch_boundary<double>(const void*, void*, const uint8_t*, 
 template hipError_t launch_interior<float>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<float>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
+                                           int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
 template hipError_t launch_interior<__half>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<__half>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,

@@ -19,14 +19,13 @@ struct SweepParams {
   double F[3];            // fluid body force
   uint32_t N;             // cells
   int box;                // edge of a sphere's box (cells); holds all its link cells
-  size_t slot_stride;     // doubles per sphere in the force-slot array (kSlotWords per wave)
+  size_t slot_stride;     // doubles per sphere in the force-slot array (kSlotWords per workgroup)
   uint32_t seed;          // stochastic-rounding stream of this sweep
 };
 
-// Workgroups per sphere of the link-cell pass; each of their waves owns one
-// force/torque slot of kSlotWords doubles: the deviation parts of force and
-// torque, then the integer sums K and L x K of the weight constants (see
-// boundary_cell).
+// Workgroups per sphere of the link-cell pass; each owns one force/torque
+// slot of kSlotWords doubles: the deviation parts of force and torque, then
+// the integer sums K and L x K of the weight constants (see boundary_cell).
 constexpr int kLinkGroups = 32;
 constexpr int kSlotWords = 12;
 inline int link_chunks(int box) { return (box * box * box + 255) / 256; }
@@ -66,7 +65,11 @@ hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* pa
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
                                const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st);
-hipError_t launch_reduce_update(DevParticle* parts, int np, double* slots, double* hist, int* status,
+// plain device copy of bytes (a multiple of 16): the bandwidth reference
+hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// per-sphere force/torque reduction and particle update (Algorithm 1)
+hipError_t launch_reduce_update(DevParticle* parts, int np, const double* slots, double* hist, int* status,
                                 const SweepParams& p, const UpdateParams& u, hipStream_t st);
+
 
 }  // namespace vm
