@@ -9,14 +9,20 @@ per-sphere force/torque reduction and particle update.
 
 For each storage format: W warm-up steps, then K timed steps between HIP
 events on the library's stream (MLUPS over all 512^3 cells), then untimed
-steps up to 1000 to measure the drag error against FP64 (mean F_z over steps
-800-999, max over spheres).  `value` is the MLUPS of the fastest format whose
-drag error is below 1e-3.
+steps up to 1000 to measure the drag against the library's FP64 run (mean
+F_z over steps 800-999, max over spheres).  The drag error against the FP64
+oracle is measured on a reduced instance of the same workload (128^3, one
+fixed r = 20 sphere, 1000 steps), whose oracle run is stored in
+tests/golden/reference_runs.json.  `value` is the MLUPS of the fastest
+format whose drag error against the oracle is below 1e-3.
 
 Also reported: the roofline of the interior sweep kernel (algorithmic bytes
 per launch / event-timed launch duration vs 8 TB/s), the moving-sphere
-workload (256^3, rising light sphere, FP64 vs FP32 trajectory error), and the
-CPU oracle timed on a bounded sample on the host cores.
+workload (256^3 throughput; trajectory error of each format against the
+stored oracle run of a reduced 64 x 64 x 128 instance), the refined
+workload with its roofline (all levels' cell updates x bytes per update per
+coarse step), the adjoint cost, and the CPU oracle timed on a bounded
+sample on the host cores.
 """
 import argparse
 import json
@@ -35,6 +41,7 @@ BYTES = {"f64": 8, "f32": 4, "f16": 2}
 SWEEP_SOURCES = ["paper_2103_10882_amd/csrc/common.hpp", "paper_2103_10882_amd/csrc/stencil.hpp",
                  "paper_2103_10882_amd/csrc/uniform.hpp", "paper_2103_10882_amd/csrc/uniform.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_precision512.md")
+GOLDEN_FILE = os.path.join(ROOT, "tests", "golden", "reference_runs.json")
 COPY_BYTES = 1 << 30
 
 
@@ -105,28 +112,74 @@ def run_mrt(pkg, w, storages, warmup, steps, bulk_factor=100.0):
     return out
 
 
+def golden():
+    with open(GOLDEN_FILE) as f:
+        return json.load(f)
+
+
+def drag_vs_oracle(pkg, storages):
+    """Drag error of each storage format against the stored FP64 oracle run
+    of the reduced precision-sweep instance (128^3, one fixed r = 20 sphere,
+    1000 steps): |<F_z> - <F_z>_oracle| / |<F_z>_oracle| over steps 800-999."""
+    g = golden()["drag128"]
+    lo, hi = g["window"]
+    out = {"workload": "128^3 periodic, one fixed r=20 sphere, omega 1.6, F 1e-5 z; mean F_z over steps %d-%d" %
+           (lo, hi - 1), "oracle_fz_mean": g["Fz_mean"]}
+    for st in storages:
+        sim = pkg.Sim(g["config"], g["spheres"], storage=st, history=hi - lo)
+        sim.init()
+        sim.step(g["steps"])
+        sim.sync()
+        fz = float(sim.history(0, hi - lo)[:, 2].mean())
+        sim.close()
+        out[st] = {"fz_mean": fz, "drag_err": abs(fz - g["Fz_mean"]) / abs(g["Fz_mean"])}
+    return out
+
+
+def trajectory_vs_oracle(pkg, storages):
+    """Trajectory error of each storage format against the stored FP64
+    oracle run of the reduced rising-sphere instance (64 x 64 x 128 between
+    walls, r = 8, density ratio 0.5, C_v 0.5, Ga 150, 1000 steps): the
+    error measures of Sec. 3.4.1 on u_z,n = u_z / u_g sampled every step."""
+    import numpy as np
+    g = golden()["rising64"]
+    n = g["steps"]
+    uo = np.array(g["uz"]) / 0.01
+    out = {"workload": "64x64x128, walls at z=0,128; r=8, density ratio 0.5, C_v 0.5, Ga 150; %d steps" % n}
+    for st in storages:
+        sim = pkg.Sim(g["config"], g["spheres"], storage=st, history=n)
+        sim.init()
+        sim.step(n)
+        sim.sync()
+        h = sim.history(0, n)
+        sim.close()
+        ug = h[:, 11] / 0.01
+        out[st] = {"eps_sq": float(np.mean((ug - uo) ** 2)),
+                   "eps_rel": float(np.mean((ug[uo != 0] - uo[uo != 0]) / uo[uo != 0])),
+                   "eps_term_rel": float((ug[-1] - uo[-1]) / uo[-1]),
+                   "z_err": float(np.abs(h[:, 8] - np.array(g["z"])).max())}
+    return out
+
+
 def run_rising(pkg, steps):
-    """Moving light sphere between walls: FP64 vs FP32 trajectory."""
+    """Moving light sphere between walls at full size: throughput of FP64
+    and FP32 (their trajectory errors are measured against the oracle on
+    the reduced instance, trajectory_vs_oracle)."""
     import numpy as np
     import synth
     w = synth.rising()
     out = {}
-    traj = {}
     for st in ("f64", "f32"):
         sim = pkg.Sim(w["config"], w["spheres"], storage=st, history=steps)
         sim.init()
         t = timed_steps(sim, steps)
         N = np.prod(w["config"]["n"])
-        traj[st] = sim.history(0, steps)
         out[st] = {"mlups": float(N * steps / t / 1e6)}
+        if st == "f64":
+            out["uz_n_final_f64"] = float(sim.history(0, 1)[0, 11] / 0.01)
         sim.close()
         del sim
-    ug = 0.01
-    uz64, uz32 = traj["f64"][:, 11] / ug, traj["f32"][:, 11] / ug
     out["steps"] = steps
-    out["uz_n_final_f64"] = float(uz64[-1])
-    out["eps_sq_f32"] = float(np.mean((uz32 - uz64) ** 2))
-    out["z_err_f32"] = float(np.abs(traj["f32"][:, 8] - traj["f64"][:, 8]).max())
     return out
 
 
@@ -149,8 +202,15 @@ def run_refined(pkg, coarse_steps=500):
         t = timed_steps(sim, coarse_steps)
         cu1, _ = sim.stats()
         h = sim.history(0, 4 * coarse_steps)
+        upd = (cu1 - cu0) / coarse_steps
+        # all levels' cell updates per coarse step (sum_l 2^l N_l) x bytes per
+        # update (19 loads, 19 stores, the flag byte)
+        gbs = upd * (38 * BYTES[st] + 1) / (t / coarse_steps) / 1e9
         out[st] = {"mlups": (cu1 - cu0) / t / 1e6, "ms_per_coarse_step": 1e3 * t / coarse_steps,
-                   "cell_updates_per_coarse_step": (cu1 - cu0) / coarse_steps, "blocks_at_start": blocks,
+                   "cell_updates_per_coarse_step": upd, "blocks_at_start": blocks,
+                   "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_GBS, "unit": "GB/s",
+                                "frac": round(gbs / PEAK_GBS, 4),
+                                "bytes_per_coarse_step": upd * (38 * BYTES[st] + 1)},
                    "refinements": sim.refinements(), "z_rise": float(h[-1, 8] - w["spheres"][0]["x"][2]),
                    "uz_final": float(h[-1, 11])}
         sim.close()
@@ -490,29 +550,33 @@ def measured_traffic(storage):
 
 
 def copy_reference():
-    """A plain device copy of COPY_BYTES, five times: the reference whose
-    FETCH_SIZE / WRITE_SIZE readings scale the sweep's counters."""
+    """The library's plain device copy of COPY_BYTES, five times: the
+    reference whose FETCH_SIZE / WRITE_SIZE readings scale the sweep's
+    counters."""
     import torch
+    import paper_2103_10882_amd as pkg
     n = COPY_BYTES // 4
     x = torch.ones(n, device="cuda", dtype=torch.float32)
     y = torch.empty_like(x)
     for _ in range(5):
-        y.copy_(x)
+        pkg.stream_copy(y, x)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 5}), flush=True)
 
 
 def stream_reference(nbytes=4 << 30, reps=10):
-    """What PyTorch's own streaming kernels reach on this GPU: read (sum),
-    write (fill) and copy of nbytes, GB/s of bytes moved.  A 1:1 read/write
-    stream such as the interior sweep is bounded by the copy figure."""
+    """Streaming rates on this GPU, GB/s of bytes moved: the library's plain
+    16-byte-per-lane copy (vmlbm_stream_copy), and PyTorch's read (sum) and
+    write (fill) of nbytes.  A 1:1 read/write stream such as the interior
+    sweep is bounded by the copy figure."""
     import torch
+    import paper_2103_10882_amd as pkg
     n = nbytes // 4
     x = torch.ones(n, device="cuda", dtype=torch.float32)
     y = torch.empty_like(x)
     out = {}
     for name, fn, moved in (("read", lambda: x.sum(), nbytes), ("write", lambda: y.fill_(1.5), nbytes),
-                            ("copy", lambda: y.copy_(x), 2 * nbytes)):
+                            ("copy", lambda: pkg.stream_copy(y, x), 2 * nbytes)):
         fn()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -630,11 +694,10 @@ def main():
         log(f"  {res[st]['mlups']:.0f} MLUPS, sweep {res[st]['sweep_ms']:.3f} ms, {res[st]['sweep_gbs']:.0f} GB/s")
     ref = res.get("f64")
     for st, r in res.items():
-        if ref is None:
-            r["drag_err"] = None
-            continue
-        r["drag_err"] = max(abs(a - b) / abs(b) for a, b in zip(r["drag"], ref["drag"]))
-    ok = [st for st, r in res.items() if r["drag_err"] is not None and r["drag_err"] < 1e-3]
+        r["drag_err_vs_fp64"] = None if ref is None else max(abs(a - b) / abs(b) for a, b in zip(r["drag"], ref["drag"]))
+    log("drag against the stored FP64 oracle run (128^3)")
+    dvo = drag_vs_oracle(pkg, list(res))
+    ok = [st for st in res if dvo[st]["drag_err"] < 1e-3]
     best = max(ok, key=lambda s: res[s]["mlups"]) if ok else max(res, key=lambda s: res[s]["mlups"])
     b = res[best]
     traffic = measured_traffic(best) if args.n == 512 else None
@@ -676,14 +739,18 @@ def main():
         "precision_sweep": {st: {"mlups": round(r["mlups"], 1), "mlups_fluid": round(r["mlups_fluid"], 1),
                                  "sweep_gbs": round(r["sweep_gbs"], 1),
                                  "hbm_frac": round(r["sweep_gbs"] / PEAK_GBS, 4),
-                                 "drag_err": r["drag_err"], "drag_fz_mean": r["drag"][0]}
+                                 "drag_err_vs_oracle": dvo[st]["drag_err"],
+                                 "drag_err_vs_fp64_512": r["drag_err_vs_fp64"], "drag_fz_mean": r["drag"][0]}
                             for st, r in res.items()},
+        "drag_vs_oracle": dvo,
     }
     if not args.no_extra:
         log("MRT, bulk factor 100, on the precision workload")
         line["mrt_bulk100"] = run_mrt(pkg, w, ["f32", "f16"], args.warmup, args.steps)
         log("rising sphere 256^3")
         line["rising"] = run_rising(pkg, 2000)
+        log("trajectories against the stored FP64 oracle run (64x64x128)")
+        line["trajectory_vs_oracle"] = trajectory_vs_oracle(pkg, ["f64", "f32", "f16"])
         log("refined 128x128x512, 3 levels")
         line["refined"] = run_refined(pkg)
         log("adjoint 128^3")

@@ -200,3 +200,46 @@ def test_refined_full_comoving_and_rise(env):
     say(f"  u_z after 80 finest steps: f64 {uz['f64'][-1]:.6e} f32 {uz['f32'][-1]:.6e}")
     assert uz["f64"][-1] > 0
     assert np.abs(uz["f32"] - uz["f64"]).max() <= 1e-4 * np.abs(uz["f64"]).max()
+
+
+def test_rising256_parity_100_steps(env):
+    """The rising-sphere workload at full size (256^3, no-slip walls at z = 0
+    and 256, density ratio 0.5, r = 12, C_v = 0.5, Ga = 150, from rest),
+    FP64, against the oracle for 100 steps: force and torque every step
+    within 1e-10 (scale: the net weight, as the force starts from zero),
+    the owner map every 10 steps, sphere state and populations at the end."""
+    import torch
+    pkg, oracle = env
+    w = synth.rising()
+    cfg, sph = w["config"], w["spheres"]
+    s = sph[0]
+    fscale = abs((s["density_ratio"] - 1.0) * cfg["gravity"][2] * 4.0 / 3.0 * np.pi * s["radius"] ** 3)
+    say("case rising256 f64, 100 steps against the oracle")
+    sim = pkg.Sim(cfg, sph, storage="f64", history=4)
+    sim.init()
+    ref = oracle.Uniform(cfg, sph)
+    ref.init()
+    worst = 0.0
+    for k in range(1, 101):
+        sim.step(1)
+        ref.step(1)
+        Fg, Tg = sim.force_torque(0)
+        Fo, To = ref.force_torque(0)
+        fs = max(np.abs(Fo).max(), fscale)
+        e = max(np.abs(Fg - Fo).max() / fs, np.abs(Tg - To).max() / max(np.abs(To).max(), s["radius"] * fs))
+        assert e <= 1e-10, (k, Fg, Fo, Tg, To)
+        worst = max(worst, e)
+        if k % 10 == 0:
+            flips = int((sim.owner() != ref.owner()).sum())
+            assert flips == 0, f"step {k}: {flips} mapping differences"
+            say(f"  step {k}: worst F/T error so far {worst:.2e}")
+    xg, ug, wg = sim.particle(0)
+    xo, uo, wo = ref.particle(0)
+    assert np.abs(xg - xo).max() < 1e-12 and np.abs(ug - uo).max() < 1e-14
+    fg = sim.populations()
+    rel = np.abs(fg - ref.post_collision()).max() / np.abs(fg).max()
+    say(f"  u_z {ug[2]:.6e} vs {uo[2]:.6e}; population rel err {rel:.2e}")
+    assert rel <= 1e-12
+    sim.close()
+    del sim, ref, fg
+    torch.cuda.empty_cache()
