@@ -200,6 +200,21 @@ int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
  * 8^-l in coarse units).  Deterministic device reduction; synchronises. */
 int vmlbm_totals(vmlbm_ctx* ctx, double* mass, double mom[3]);
 
+/* vmlbm_totals for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * sums, bit for bit, with the per-workgroup partials in a file-scope device
+ * array of 1024 x 8 doubles (64 KiB) instead of the workspace, read back
+ * into a stack buffer; no allocation routine is called.  Each GPU the
+ * library runs on holds its own copy of the array until the process ends;
+ * its address is looked up when a workspace is bound on that GPU.  The
+ * array does not grow with the grid (the reduction strides over the
+ * cells), so no grid is too large for it.  All calls on one GPU share the
+ * array: calls that overlap on one GPU (on other host threads or streams)
+ * race.  Every partial is written before it is read, so nothing needs
+ * clearing between calls.  Synchronises the context's stream;
+ * VMLBM_ESTATE if no workspace is bound. */
+int vmlbm_totals_static(vmlbm_ctx* ctx, double* mass, double mom[3]);
+
 /* Uniform grid: post-collision populations of the cells of a box (periodic
  * wrap), FP64 host array [19][size2][size1][size0]; solid cells read 0. */
 int vmlbm_read_box(vmlbm_ctx* ctx, const int lo[3], const int size[3], double* out);

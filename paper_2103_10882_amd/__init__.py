@@ -27,7 +27,7 @@ EXPORTS = [
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
     "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
-    "vmlbm_stream_copy",
+    "vmlbm_stream_copy", "vmlbm_totals_static",
 ]
 
 
@@ -89,6 +89,7 @@ def lib():
             "vmlbm_sweep_time": [vp, vp, vp],
             "vmlbm_cell_counts": [vp, ctypes.c_int, vp, vp],
             "vmlbm_totals": [vp, vp, vp],
+            "vmlbm_totals_static": [vp, vp, vp],
             "vmlbm_read_box": [vp, vp, vp, vp],
             "vmlbm_level_blocks": [vp, ctypes.c_int, vp, vp],
             "vmlbm_refinements": [vp, vp],
@@ -285,6 +286,13 @@ class Sim:
         s, n = ctypes.c_double(), ctypes.c_longlong()
         self._check(self.L.vmlbm_sweep_time(self.h, ctypes.byref(s), ctypes.byref(n)), "sweep_time")
         return s.value, n.value
+
+    def totals_static(self):
+        """totals() through the entry point that allocates nothing."""
+        m = np.zeros(1)
+        j = np.zeros(3)
+        self._check(self.L.vmlbm_totals_static(self.h, _ptr(m), _ptr(j)), "totals_static")
+        return float(m[0]), j
 
     def totals(self):
         m = np.zeros(1)

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,35 @@
 using namespace vm;
 
 namespace vm {
+
+// Scratch for callers that cannot allocate (vmlbm_totals_static): the
+// per-workgroup partial sums of the totals reduction live in this
+// file-scope device array instead of the context's workspace.  In host code
+// its name is not a device address; each device's copy is looked up once,
+// with that device current, when a workspace is bound on it (scratch_on).
+constexpr int kStaticScratchDoubles = kTotalsGroups * 8;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
+
+// this device's copy of the scratch array (the current device)
+static hipError_t scratch_on(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 int fail(vmlbm_ctx* c, int code, const char* fmt, ...) {
   char buf[512];
@@ -311,6 +341,7 @@ int vmlbm_bind_workspace(vmlbm_ctx* c, void* dev_ptr, size_t bytes) {
   if (bytes < need) return fail(c, VMLBM_ENOMEM, "workspace %zu < required %zu bytes", bytes, need);
   c->ws = (char*)dev_ptr;
   c->ws_bytes = bytes;
+  HIP_TRY(c, scratch_on(&c->scratch));
   c->use_flags = !c->spheres.empty() || c->wall_axis >= 0;
   if (!c->side) {
     HIP_TRY(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
@@ -612,17 +643,15 @@ int vmlbm_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* inte
   return VMLBM_OK;
 }
 
-int vmlbm_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
-  int rc = check_ready(c);
-  if (rc) return rc;
-  if (c->cfg.block > 0) return refine_totals(c, mass, mom);
+// totals with device partials `part` and a host buffer `h`, both of
+// kTotalsGroups x 8 doubles
+static int totals_with(vmlbm_ctx* c, double* part, double* h, double* mass, double mom[3]) {
+  if (c->cfg.block > 0) return refine_totals(c, part, h, mass, mom);
   const uint32_t N = (uint32_t)((size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2]);
-  double* part = (double*)(c->ws + c->off_totals);
   HIP_TRY(c, launch_totals(c->cfg.storage, c->ws + c->off_pdf[c->cur], c->use_flags ? c->flags() : nullptr, N, N,
                            nullptr, 0, part, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::vector<double> h((size_t)kTotalsGroups * 8);
-  HIP_TRY(c, hipMemcpy(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(h, part, (size_t)kTotalsGroups * 8 * sizeof(double), hipMemcpyDeviceToHost));
   long double n = 0, m = 0, j[3] = {0, 0, 0};
   for (int g = 0; g < kTotalsGroups; ++g) {
     n += h[8 * g]; m += h[8 * g + 1];
@@ -631,6 +660,22 @@ int vmlbm_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
   if (mass) *mass = (double)(n + m);
   if (mom) for (int a = 0; a < 3; ++a) mom[a] = (double)j[a];
   return VMLBM_OK;
+}
+
+int vmlbm_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  std::vector<double> h((size_t)kTotalsGroups * 8);
+  return totals_with(c, (double*)(c->ws + c->off_totals), h.data(), mass, mom);
+}
+
+int vmlbm_totals_static(vmlbm_ctx* c, double* mass, double mom[3]) {
+  int rc = check_ready(c);
+  if (rc) return rc;
+  if (!c->scratch) return fail(c, VMLBM_ESTATE, "no scratch array on this device");
+  // the partials come back into a stack buffer: no heap use on this path
+  double h[kStaticScratchDoubles];
+  return totals_with(c, c->scratch, h, mass, mom);
 }
 
 int vmlbm_read_box(vmlbm_ctx* c, const int lo[3], const int size[3], double* out) {

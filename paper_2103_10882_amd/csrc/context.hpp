@@ -25,6 +25,7 @@ struct vmlbm_ctx {
   hipStream_t side = nullptr;              // boundary kernels, forked from and joined to `stream`
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   char* ws = nullptr;
+  double* scratch = nullptr;   // this device's file-scope scratch array (api.hip), set at binding
   size_t ws_bytes = 0;
   size_t ws_needed = 0;
   bool initialized = false;
@@ -109,7 +110,7 @@ int uniform_step(vmlbm_ctx* c, int nsteps);
 constexpr int kTotalsGroups = 1024;
 hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uint32_t N, uint32_t cells,
                          const int* slot_list, int nslots, double* partials, hipStream_t st);
-int refine_totals(vmlbm_ctx* c, double* mass, double mom[3]);
+int refine_totals(vmlbm_ctx* c, double* part, double* h, double* mass, double mom[3]);
 
 // adjoint (adjoint.hip)
 void adjoint_plan(vmlbm_ctx* c, const Take& take);

@@ -1761,12 +1761,12 @@ int refine_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* int
 
 void refine_destroy(vmlbm_ctx*) {}
 
-// volume-weighted totals over the interior fluid cells of every level
-int refine_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
+// volume-weighted totals over the interior fluid cells of every level;
+// part: device partials (kTotalsGroups x 8 doubles), h: host buffer of the
+// same size
+int refine_totals(vmlbm_ctx* c, double* part, double* h, double* mass, double mom[3]) {
   Forest& f = *c->forest;
   long double m = 0, j[3] = {0, 0, 0};
-  double* part = (double*)(c->ws + c->off_totals);
-  std::vector<double> h((size_t)kTotalsGroups * 8);
   for (int l = 0; l <= f.L; ++l) {
     Forest::Lev& V = f.lv[l];
     if (!V.n_int) continue;
@@ -1774,7 +1774,7 @@ int refine_totals(vmlbm_ctx* c, double* mass, double mom[3]) {
                              (uint32_t)V.cap * kBlockCells, 0, (const int*)(c->ws + V.off_int), V.n_int, part,
                              c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    HIP_TRY(c, hipMemcpy(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIP_TRY(c, hipMemcpy(h, part, (size_t)kTotalsGroups * 8 * sizeof(double), hipMemcpyDeviceToHost));
     long double n = 0, ml = 0, jl[3] = {0, 0, 0};
     for (int g = 0; g < kTotalsGroups; ++g) {
       n += h[8 * g]; ml += h[8 * g + 1];
