@@ -23,7 +23,8 @@
 //    as on the uniform grid (Eqs. 10-12, Algorithm 1, Sec. 2.3);
 //  * refinement criterion (Sec. 4.2.1): blocks near the particle are on the
 //    finest level, others take the level of the static refine regions;
-//    2:1 balance by refining; checked every check_every coarse steps,
+//    2:1 balance by splitting, one level at a time; checked every
+//    check_every coarse steps,
 //    data moved by copying a cell to its 8 children or averaging them.
 // Domains are periodic in all directions.
 #include <cmath>
@@ -127,6 +128,9 @@ struct RForest {
 
   // leaf level of every finest block position from target levels, refined
   // until leaves that touch (face, edge or corner) differ by at most one level
+  // (Sec. 4.1).  Reading: a leaf that touches one more than a level deeper is
+  // split once, and the check repeats, so no block is finer than the targets
+  // and the 2:1 rule need.
   std::vector<int> balance(std::vector<int> t) const {
     const long NB = (long)nb[0] * nb[1] * nb[2];
     std::vector<int> lf(NB);
@@ -166,8 +170,8 @@ struct RForest {
                   if (a >= 0 && a < s && bb >= 0 && bb < s && c >= 0 && c < s) continue;
                   mx = std::max(mx, lf[bpos(wrap(ni + a, nb[0]), wrap(nj + bb, nb[1]), wrap(nk + c, nb[2]))]);
                 }
-            if (mx > l + 1 && t[bpos(i, j, k)] < mx - 1) {
-              t[bpos(i, j, k)] = mx - 1;
+            if (mx > l + 1 && t[bpos(i, j, k)] < l + 1) {
+              t[bpos(i, j, k)] = l + 1;
               changed = true;
             }
           }

@@ -146,21 +146,66 @@ def octree_ok(leaf, L):
     return True
 
 
+def no_mergeable_node(leaf, L, target):
+    """Minimality of a balanced layout: no eight sibling leaves of level l
+    could be merged into their parent.  A merge is possible when no position
+    of the parent targets level l, the siblings are all leaves of level l,
+    and no leaf touching the parent (face, edge or corner, periodic) lies
+    deeper than l."""
+    nz, ny, nx = leaf.shape
+    for l in range(1, L + 1):
+        s = 2 ** (L - l + 1)   # parent edge in finest positions
+        for k in range(0, nz, s):
+            for j in range(0, ny, s):
+                for i in range(0, nx, s):
+                    node = leaf[k:k + s, j:j + s, i:i + s]
+                    if not (node == l).all() or target[k:k + s, j:j + s, i:i + s].max() >= l:
+                        continue
+                    shell = np.take(np.take(np.take(leaf, range(k - 1, k + s + 1), axis=0, mode="wrap"),
+                                            range(j - 1, j + s + 1), axis=1, mode="wrap"),
+                                    range(i - 1, i + s + 1), axis=2, mode="wrap")
+                    if shell.max() <= l:
+                        return False
+    return True
+
+
+def region_targets(regs, n0, block, L):
+    """Target level per finest block position from static regions [lo, hi)
+    in coarse cells (blocks intersecting the box)."""
+    nb = [n // block * 2 ** L for n in n0]
+    t = np.zeros(nb[::-1], dtype=int)
+    sc = 2 ** L / block
+    for lo, hi, lev in regs:
+        a = [int(np.floor(lo[d] * sc)) for d in range(3)]
+        b = [int(np.ceil(hi[d] * sc)) for d in range(3)]
+        t[a[2]:b[2], a[1]:b[1], a[0]:b[0]] = np.maximum(t[a[2]:b[2], a[1]:b[1], a[0]:b[0]], lev)
+    return t
+
+
 def test_balance_random_targets(ora):
+    """Layouts from random static regions on 4 levels, one of them on the
+    finest level, so that balance must reach across three levels: every
+    target met, 2:1 between touching leaves, whole octree nodes, and nothing
+    finer than needed (no mergeable siblings), all checked by brute force
+    over the finest block positions."""
     rng = np.random.default_rng(3)
-    for trial in range(4):
-        c = cfg_of((16, 16, 16), 4, 8)
+    n0 = (16, 16, 16)
+    for trial in range(6):
+        c = cfg_of(n0, 4, 8)
         regs = []
-        for _ in range(3):
+        for r in range(3):
             lo = rng.integers(0, 14, 3)
             hi = lo + rng.integers(1, 3, 3)
-            regs.append((tuple(lo), tuple(hi), int(rng.integers(1, 4))))
+            regs.append((tuple(int(v) for v in lo), tuple(int(v) for v in hi), 3 if r == 0 else int(rng.integers(1, 3))))
         R = ora.Refined(c, regions=regs)
         R.init()
         leaf = R.leaf()
-        assert leaf.max() == max(r[2] for r in regs)
+        t = region_targets(regs, n0, 8, 3)
+        assert leaf.max() == 3
+        assert (leaf >= t).all()
         assert two_to_one_ok(leaf)
         assert octree_ok(leaf, 3)
+        assert no_mergeable_node(leaf, 3, t)
 
 
 def test_comoving_sphere_across_rerefinement(ora):
