@@ -54,7 +54,7 @@ typedef struct {
                                  refined grid: COARSEST-level cells */
   int block;                  /* 0 = one uniform grid; else cells per block edge
                                  (16) of the block-structured grid (Sec. 4.1) */
-  int levels;                 /* refinement levels, 1..8 (block > 0) */
+  int levels;                 /* refinement levels, 1..9 (block > 0) */
   int periodic[3];            /* 1 periodic, 0 halfway no-slip walls at both ends */
   double wall_velocity[2][3]; /* velocity of the low/high wall of the first
                                  non-periodic axis (other walls rest) */

@@ -75,7 +75,7 @@ using Take = std::function<size_t(size_t)>;
 // uses level_seed(finest steps done, l); initial states and data migrated
 // between levels use their own streams.
 inline uint32_t step_seed(long long n) { return (uint32_t)n; }
-inline uint32_t level_seed(long long fine_steps, int l) { return (uint32_t)(fine_steps * 8 + l); }
+inline uint32_t level_seed(long long fine_steps, int l) { return (uint32_t)(fine_steps * 16 + l); }
 constexpr uint32_t kInitSeed = 0xa511e9b3u;
 constexpr uint32_t kMigrateSeed = 0x63d83595u;
 

@@ -37,9 +37,12 @@ namespace vm {
 namespace {
 
 constexpr uint8_t kIface = 0x10;   // interior cell with a coalescence pull
-// deepest hierarchy: the per-level seeds step by 8 per finest step, and the
-// migration kernel takes per-level tables by value
-constexpr int kMaxLevels = 8;
+// deepest hierarchy, that of the paper's deepest setups (9 levels): the
+// per-level seeds step by 16 per finest step, and the migration kernel takes
+// per-level tables by value.  The layout is dense over finest block
+// positions (at most 2^26 of them), which bounds the coarse domain that deep
+// hierarchies can take: one coarse block at 9 levels.
+constexpr int kMaxLevels = 9;
 
 struct IfaceEntry {
   int slot, local;      // the coarse cell
@@ -206,7 +209,9 @@ std::vector<int8_t> balance_layout(const Forest& f, std::vector<int8_t> t) {
   // pyramid of maxima: level-l node (edge 2^(L-l) positions)
   auto node_dims = [&](int l, int d[3]) { for (int a = 0; a < 3; ++a) d[a] = f.nbL[a] >> (L - l); };
   std::vector<std::vector<int8_t>> mx(L + 1);
-  for (int iter = 0; iter < 64; ++iter) {
+  // each pass splits violating leaves by one level: at most L passes per
+  // level of difference, so L * L passes suffice
+  for (int iter = 0; iter <= L * L + 64; ++iter) {
     mx[L] = t;
     for (int l = L - 1; l >= 0; --l) {
       int d[3], e[3];
@@ -251,12 +256,13 @@ std::vector<int8_t> balance_layout(const Forest& f, std::vector<int8_t> t) {
                 m = std::max(m, (int)lf[f.lpos(f.wrap(i + a, f.nbL[0]), f.wrap(j + b, f.nbL[1]),
                                                f.wrap(k + c, f.nbL[2]))]);
               }
+          // split once; the next pass checks the children
           if (m > l + 1)
             for (int c = 0; c < S; ++c)
               for (int b = 0; b < S; ++b)
                 for (int a = 0; a < S; ++a) {
                   int8_t& tv = t[f.lpos(i + a, j + b, k + c)];
-                  if (tv < m - 1) { tv = (int8_t)(m - 1); changed = true; }
+                  if (tv < l + 1) { tv = (int8_t)(l + 1); changed = true; }
                 }
         }
     if (!changed) return lf;
@@ -403,11 +409,21 @@ void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<
     }
     f.leaf = keep;
   }
+  // Spheres: the layout around one sphere repeats under shifts by a whole
+  // coarse node, so the offsets of its widest block range within a node
+  // (the same along all axes: the extents are per axis) cover every place.
+  // Per offset, with B_l the region of leaves at level >= l (in level-l
+  // blocks), e_l its per-axis extents and |.| exact counts:
+  //   slots at level l (leaves and ghost blocks) <= prod(e_l + 2) - |B_{l+1}|,
+  //   coalescence cells of level l <= prod(16 e'_l + 4) - 4096 |B_{l+1}|,
+  // where e'_l are the extents of B_{l+1} in level-l blocks: ghost blocks lie
+  // in the one-block shell around B_l, coalescence cells within two cells
+  // of B_{l+1}.  The offsets run on host threads.
   const int node = 1 << L;   // coarse node edge in finest blocks
   for (const auto& s : c->spheres) {
     const int w = (int)std::ceil(2.0 * (s.radius + b) / b) + 1;   // widest block range
-    std::vector<std::array<int, 3>> ext(L + 1, {0, 0, 0}), iext(L + 1, {0, 0, 0});
-    for (int o = 0; o < node; ++o) {
+    std::vector<std::vector<long>> oc(node, std::vector<long>(L + 1, 0)), oi(node, std::vector<long>(L + 1, 0));
+    auto one_offset = [&](int o) {
       std::vector<int8_t> t(f.base.size(), 0);
       int lo[3];
       for (int a = 0; a < 3; ++a) lo[a] = (f.nbL[a] / 2 / node) * node + o;
@@ -417,8 +433,17 @@ void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<
             t[f.lpos(f.wrap(lo[0] + i, f.nbL[0]), f.wrap(lo[1] + j, f.nbL[1]), f.wrap(lo[2] + k, f.nbL[2]))] =
                 (int8_t)L;
       const std::vector<int8_t> lf = balance_layout(f, t);
+      // finest positions per leaf level
+      std::vector<long> at(L + 2, 0);
+      for (int8_t v : lf) at[v] += 1;
+      // |B_m| in level-l blocks = (finest positions with leaf >= m) / 8^(L-l)
+      auto count_ge = [&](int m, int l) {
+        long n = 0;
+        for (int v = m; v <= L; ++v) n += at[v];
+        return n >> (3 * (L - l));
+      };
       for (int l = 1; l <= L; ++l) {
-        // projections of {leaf >= l} onto the axes, in level-l and level-(l-1) blocks
+        // projections of B_l onto the axes, in level-l and level-(l-1) blocks
         const int sh = L - l;
         std::vector<std::vector<char>> pl(3), pc(3);
         for (int a = 0; a < 3; ++a) {
@@ -435,21 +460,29 @@ void plan_capacity(vmlbm_ctx* c, Forest& f, std::vector<long>& cap, std::vector<
                   pc[a][q[a] >> (sh + 1)] = 1;
                 }
               }
+        long box = 1, cbox = 1;
         for (int a = 0; a < 3; ++a) {
-          ext[l][a] = std::max(ext[l][a], (int)std::count(pl[a].begin(), pl[a].end(), 1));
-          iext[l - 1][a] = std::max(iext[l - 1][a], (int)std::count(pc[a].begin(), pc[a].end(), 1));
+          const long e = std::count(pl[a].begin(), pl[a].end(), 1);
+          const long ep = std::count(pc[a].begin(), pc[a].end(), 1);
+          box *= std::min<long>(f.lv[l].nb[a], e + 2);
+          cbox *= std::min<long>(f.lv[l - 1].n[a], 16 * ep + 4);
         }
+        oc[o][l] = box - (l < L ? count_ge(l + 1, l) : 0);
+        oi[o][l - 1] = cbox - 4096 * count_ge(l, l - 1);
       }
-    }
-    for (int l = 1; l <= L; ++l) {
-      long n = 1;
-      for (int a = 0; a < 3; ++a) n *= std::min(f.lv[l].nb[a], ext[l][a] + 2);
-      cap[l] += n;
-    }
-    for (int l = 0; l < L; ++l) {
-      long n = 1;
-      for (int a = 0; a < 3; ++a) n *= std::min(f.lv[l].nb[a], iext[l][a] + 2);
-      icap[l] += n * kBlockCells;
+    };
+    const int nt = (int)std::max(1u, std::min<unsigned>(16, std::thread::hardware_concurrency()));
+    std::vector<std::thread> pool;
+    for (int t0 = 0; t0 < nt; ++t0)
+      pool.emplace_back([&, t0]() {
+        for (int o = t0; o < node; o += nt) one_offset(o);
+      });
+    for (auto& th : pool) th.join();
+    for (int l = 0; l <= L; ++l) {
+      long mc = 0, mi = 0;
+      for (int o = 0; o < node; ++o) { mc = std::max(mc, oc[o][l]); mi = std::max(mi, oi[o][l]); }
+      cap[l] += mc;
+      icap[l] += mi;
     }
   }
   for (int l = 0; l <= L; ++l) {

@@ -64,10 +64,11 @@ def test_host_only_calls(pkg):
 
 
 def test_level_count_limits(pkg):
-    """1..8 levels for a block grid; 9 is refused at creation."""
+    """1..9 levels for a block grid (the paper's deepest setups use 9); 10
+    is refused at creation."""
     L = pkg.lib()
     h = ctypes.c_void_p()
-    for levels, rc in ((8, 0), (9, -1), (0, -1)):
+    for levels, rc in ((8, 0), (9, 0), (10, -1), (0, -1)):
         cfg = synth.base_config((16, 16, 16))
         cfg["levels"], cfg["block"] = levels, 16
         c = pkg.make_config(cfg, "f32")

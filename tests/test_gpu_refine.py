@@ -227,6 +227,73 @@ def test_static_four_levels(env):
     assert rel <= 1e-12
 
 
+def test_five_levels_static_oracle(env):
+    """Five levels against the oracle on the smallest domain, one coarse
+    16^3 block (finest level 256^3; the oracle's dense per-level arrays
+    take about 8 GB): static nesting down to level 4 around one spot, a
+    rough start and a body force, every level's populations after two coarse
+    steps (32 finest steps) within 1e-12."""
+    pkg, oracle = env
+    n0 = (16, 16, 16)
+    c = cfg_of(n0, 5, omega=1.8, F=(2e-7, -1e-7, 3e-7))
+    regions = [((7, 7, 7), (9, 9, 9), 4)]
+    u0 = synth.velocity_perturbation(n0, seed=21, amplitude=0.01)
+    say("case refined16^3 L5 static f64 against the oracle")
+    sim = pkg.Sim(c, [], storage="f64", regions=regions, check_every=0)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, regions=regions)
+    ref.init(1.0, u0)
+    assert ref.leaf().max() == 4
+    for k in range(2):
+        sim.step(1)
+        ref.step(1)
+    sim.sync()
+    rel = compare_levels(sim, ref, 5)
+    say(f"  blocks per level {[int(sim.level_blocks(l).shape[0]) for l in range(5)]}; population rel err {rel:.2e}")
+    assert rel <= 1e-12
+    sim.close()
+
+
+def test_five_levels_moving_sphere_oracle(env):
+    """Five levels against the oracle with a heavy sphere moving on level 4
+    (one coarse 16^3 block, finest 256^3): the particle criterion holds the
+    finest level around it and the layout changes once its grown box crosses
+    a finest-block face; force and torque every finest step, layouts,
+    particle state and every level's populations after three coarse steps."""
+    pkg, oracle = env
+    n0 = (16, 16, 16)
+    c = cfg_of(n0, 5, omega=1.7)
+    # the grown box's lower face crosses z = 128, the boundary between two
+    # pairs of sibling finest blocks, during the run
+    s = synth.sphere((128.3, 127.8, 147.8), 5.5, density_ratio=1e3, cv=0.5, fixed=False, u=(0.0, 0.0, 0.05))
+    u0 = synth.velocity_perturbation(n0, seed=22, amplitude=0.005)
+    say("case refined16^3 L5 moving sphere f64 against the oracle")
+    sim = pkg.Sim(c, [s], storage="f64", history=64, check_every=1)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, spheres=[s], check_every=1)
+    ref.init(1.0, u0)
+    for k in range(1, 4):
+        sim.step(1)
+        ref.step(1)
+        hg = sim.history(0, 16)
+        Fo, To = ref.force_torque(0)
+        Fg, Tg = hg[-1, 0:3], hg[-1, 3:6]
+        assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), 5.5 * np.abs(Fo).max()), (k, Tg, To)
+    sim.sync()
+    nref = sim.refinements()
+    _, _, nref_o = ref.counters()
+    say(f"  refinements gpu {nref} oracle {nref_o}; blocks {[int(sim.level_blocks(l).shape[0]) for l in range(5)]}")
+    assert nref == nref_o and nref >= 1
+    xg, ug, wg = sim.particle(0)
+    xo, uo, wo = ref.particle(0)
+    assert np.abs(xg - xo).max() < 1e-11 and np.abs(ug - uo).max() < 1e-12
+    rel = compare_levels(sim, ref, 5)
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-12
+    sim.close()
+
+
 def write_from_oracle(sim, ref, levels):
     """Copy the oracle's interior populations of every level into the GPU
     grid, block by block in the GPU's slot order (same layout on both)."""
@@ -391,6 +458,42 @@ def test_deep_hierarchy_comoving_sphere(env):
         fluid = np.abs(f).sum(axis=0) > 0
         if fluid.sum() == 0:
             continue
+        err = np.abs(f[:, fluid] - feq[:, None]).max()
+        say(f"  level {l}: {int(fluid.sum())} fluid cells, max |f - f^eq| {err:.2e}")
+        assert err < 1e-14
+    _, u, _ = sim.particle(0)
+    assert np.abs(u - U).max() < 1e-14
+    sim.close()
+
+
+def test_nine_levels_comoving_sphere(env):
+    """Nine levels, the depth of the paper's Table 3 setups, on one coarse
+    16^3 block (finest level 4096^3 cells, of which only the blocks around
+    the sphere are stored): a heavy sphere moving with a uniform flow crosses
+    finest blocks over two coarse steps (512 finest steps), re-refining on
+    the way; every interior cell of every level stays at f^eq(1, U)."""
+    pkg, oracle = env
+    n0 = (16, 16, 16)
+    U = np.array([0.012, -0.008, 0.015])
+    c = cfg_of(n0, 9, omega=1.6)
+    # the grown box's lower z face crosses 2048, between two pairs of
+    # sibling finest blocks, during the run
+    s = synth.sphere((2050.3, 2045.8, 2064.0), 4.5, density_ratio=1e9, cv=0.0, fixed=False, u=tuple(U))
+    u0 = np.broadcast_to(U[:, None, None, None], (3,) + n0[::-1]).copy()
+    say("case deep hierarchy co-moving sphere, 9 levels, f64")
+    sim = pkg.Sim(c, [s], storage="f64", check_every=1)
+    sim.init(1.0, u0)
+    sim.step(2)
+    sim.sync()
+    blocks = [int(sim.level_blocks(l).shape[0]) for l in range(9)]
+    say(f"  refinements {sim.refinements()}, blocks {blocks}")
+    assert sim.refinements() >= 1 and blocks[8] > 0
+    feq = oracle.equilibrium(1.0, U)
+    for l in range(9):
+        if blocks[l] == 0:
+            continue
+        f = sim.populations(l)
+        fluid = np.abs(f).sum(axis=0) > 0
         err = np.abs(f[:, fluid] - feq[:, None]).max()
         say(f"  level {l}: {int(fluid.sum())} fluid cells, max |f - f^eq| {err:.2e}")
         assert err < 1e-14
