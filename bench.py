@@ -211,7 +211,8 @@ def run_refined(pkg, coarse_steps=500):
                    "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_GBS, "unit": "GB/s",
                                 "frac": round(gbs / PEAK_GBS, 4),
                                 "bytes_per_coarse_step": upd * (38 * BYTES[st] + 1)},
-                   "refinements": sim.refinements(), "z_rise": float(h[-1, 8] - w["spheres"][0]["x"][2]),
+                   "refinements": sim.refinements(), "prebuilt_layouts": sim.prebuilt_layouts(),
+                   "z_rise": float(h[-1, 8] - w["spheres"][0]["x"][2]),
                    "uz_final": float(h[-1, 11])}
         sim.close()
         del sim

@@ -230,6 +230,12 @@ int vmlbm_level_blocks(vmlbm_ctx* ctx, int level, int* count, int* origin);
 /* Number of re-refinements performed so far (Sec. 4.2). */
 int vmlbm_refinements(vmlbm_ctx* ctx, int* count);
 
+/* Of those, the number whose host tables were built ahead on a host thread
+ * (the block ranges of the next layout change predicted from the spheres'
+ * velocities while the device stepped) rather than at the layout check.
+ * The tables are the same either way; this counts where the build ran. */
+int vmlbm_prebuilt_layouts(vmlbm_ctx* ctx, int* count);
+
 /* Set the differentiable parameters: body force magnitude along +z and
  * omega (Lambda held fixed, so s- follows omega).  Checkpoints of an earlier
  * vmlbm_forward_ckpt no longer count: vmlbm_adjoint then needs a new forward

@@ -25,7 +25,8 @@ EXPORTS = [
     "vmlbm_set_sphere_motion",
     "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
-    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks", "vmlbm_refinements",
+    "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks",
+    "vmlbm_refinements", "vmlbm_prebuilt_layouts",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
     "vmlbm_stream_copy", "vmlbm_totals_static",
 ]
@@ -93,6 +94,7 @@ def lib():
             "vmlbm_read_box": [vp, vp, vp, vp],
             "vmlbm_level_blocks": [vp, ctypes.c_int, vp, vp],
             "vmlbm_refinements": [vp, vp],
+            "vmlbm_prebuilt_layouts": [vp, vp],
             "vmlbm_set_params": [vp, ctypes.c_double, ctypes.c_double],
             "vmlbm_forward_ckpt": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
             "vmlbm_adjoint": [vp, ctypes.c_double, vp],
@@ -322,6 +324,11 @@ class Sim:
     def refinements(self):
         c = ctypes.c_int()
         self._check(self.L.vmlbm_refinements(self.h, ctypes.byref(c)), "refinements")
+        return c.value
+
+    def prebuilt_layouts(self):
+        c = ctypes.c_int()
+        self._check(self.L.vmlbm_prebuilt_layouts(self.h, ctypes.byref(c)), "prebuilt_layouts")
         return c.value
 
     # --- differentiation ------------------------------------------------------

@@ -283,8 +283,12 @@ def test_five_levels_moving_sphere_oracle(env):
     sim.sync()
     nref = sim.refinements()
     _, _, nref_o = ref.counters()
-    say(f"  refinements gpu {nref} oracle {nref_o}; blocks {[int(sim.level_blocks(l).shape[0]) for l in range(5)]}")
+    say(f"  refinements gpu {nref} oracle {nref_o} (tables built ahead: {sim.prebuilt_layouts()}); "
+        f"blocks {[int(sim.level_blocks(l).shape[0]) for l in range(5)]}")
     assert nref == nref_o and nref >= 1
+    # the change is the one predicted from the sphere's velocity after the
+    # first check, so its tables come from the host thread
+    assert sim.prebuilt_layouts() >= 1
     xg, ug, wg = sim.particle(0)
     xo, uo, wo = ref.particle(0)
     assert np.abs(xg - xo).max() < 1e-11 and np.abs(ug - uo).max() < 1e-12
