@@ -979,13 +979,19 @@ __device__ __forceinline__ void iface_role(const S* __restrict__ src, S* __restr
   for (int q = 0; q < kQ; ++q) dst[bpop(q, c)] = Store<S>::store_sr(d[q], rb.next());
 }
 
-// The work of one level's sweep as one launch: interior planes, then the
-// coalescence cells (kIfaceCells per workgroup), then the ghost bands
-// (kBandSplit workgroups per ghost block).  The three write disjoint cells
-// of the new state and read the current one (the coalescence cells also
-// the finer level's), so they need no order among themselves.
+// The work of one level's sweep as one launch: the ghost bands (kBandSplit
+// workgroups per ghost block), the coalescence cells (kIfaceCells per
+// workgroup), then the interior planes.  The three write disjoint cells of
+// the new state and read the current one (the coalescence cells also the
+// finer level's), so they need no order among themselves; the short,
+// latency-bound ghost and coalescence workgroups go first so that they run
+// beside the bulk rather than after it.  The interior part starts at a
+// multiple of 8 workgroups (n_lead, the others' count rounded up), so that
+// its numbering keeps the launch order's round-robin over the 8 XCDs.
 struct LevelRoles {
   uint32_t n_sweep;                 // interior workgroups (16 per block)
+  uint32_t n_lead;                  // workgroups before the interior ones
+  int n_ghost_wg;                   // ghost workgroups
   int n_iface_wg, n_iface;          // coalescence workgroups and cells
   const void* fine;                 // level l+1 current state
   const IfaceEntry* iface;
@@ -1002,21 +1008,20 @@ struct LevelRoles {
 // scalar registers of a wave above the 8-wave budget; 6 % on the 3-level
 // workload); FP32 measured no better for it (2 scalar registers spilled)
 template <typename S, bool MRT>
-__global__ __launch_bounds__(256, sizeof(S) == 2 ? VM_LEVEL_WAVES : 1) void k_level(const S* __restrict__ src, S* __restrict__ dst,
-                                               const uint8_t* __restrict__ flags, const int* __restrict__ list,
-                                               int* __restrict__ status, LevelArgs a, LevelRoles r) {
+__global__ __launch_bounds__(256, sizeof(S) == 2 ? VM_LEVEL_WAVES : 1) void k_level(
+    const S* __restrict__ src, S* __restrict__ dst, const uint8_t* __restrict__ flags,
+    const int* __restrict__ list, int* __restrict__ status, LevelArgs a, LevelRoles r) {
   uint32_t b = blockIdx.x;
-  if (b < r.n_sweep) {
-    sweep_role<S, MRT>(src, dst, flags, list, status, a, b, r.n_sweep);
+  if (b >= r.n_lead) {
+    sweep_role<S, MRT>(src, dst, flags, list, status, a, b - r.n_lead, r.n_sweep);
     return;
   }
-  b -= r.n_sweep;
-  if ((int)b < r.n_iface_wg) {
-    iface_role<S>(src, dst, (const S*)r.fine, r.iface, r.n_iface, status, a, (int)b);
+  if ((int)b < r.n_ghost_wg) {
+    ghost_role<S>(src, dst, r.ghost, r.band_off, r.band, r.dirs, a, (int)(b / kBandSplit), (int)(b % kBandSplit));
     return;
   }
-  b -= (uint32_t)r.n_iface_wg;
-  ghost_role<S>(src, dst, r.ghost, r.band_off, r.band, r.dirs, a, (int)(b / kBandSplit), (int)(b % kBandSplit));
+  b -= (uint32_t)r.n_ghost_wg;
+  if ((int)b < r.n_iface_wg) iface_role<S>(src, dst, (const S*)r.fine, r.iface, r.n_iface, status, a, (int)b);
 }
 
 // stored post-collision velocity of every interior cell of a level:
@@ -1351,12 +1356,13 @@ int launch_level(vmlbm_ctx* c, int l, int sub, const LevelArgs& a) {
     r.fine = c->ws + f.lv[l + 1].off_pdf[f.lv[l + 1].cur];
     r.iface = (const IfaceEntry*)(c->ws + V.off_iface);
   }
-  const int n_ghost_wg = V.n_ghost * kBandSplit;
+  r.n_ghost_wg = V.n_ghost * kBandSplit;
   r.ghost = (const int*)(c->ws + V.off_ghost);
   r.band_off = (const int*)(c->ws + V.off_band_off);
   r.band = (const uint16_t*)(c->ws + V.off_band);
   r.dirs = (const uint32_t*)(c->ws + V.off_band_dirs) + 1 + sub;
-  const uint32_t grid = r.n_sweep + (uint32_t)r.n_iface_wg + (uint32_t)n_ghost_wg;
+  r.n_lead = ((uint32_t)(r.n_ghost_wg + r.n_iface_wg) + 7u) & ~7u;
+  const uint32_t grid = r.n_lead + r.n_sweep;
   if (!grid) return VMLBM_OK;
   const void* src = c->ws + V.off_pdf[V.cur];
   void* dst = c->ws + V.off_pdf[1 - V.cur];
