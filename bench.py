@@ -593,6 +593,34 @@ def stream_reference(nbytes=4 << 30, reps=10):
     return out
 
 
+def pull_reference(n, storages, reps=5):
+    """GB/s of the interior sweep's access pattern without its arithmetic
+    (vmlbm_stream_pull: 19 pulled loads and 19 streaming stores per cell of
+    a periodic n^3 box), per storage format: the rate a sweep with no
+    arithmetic and no flags would reach."""
+    import torch
+    import paper_2103_10882_amd as pkg
+    out = {}
+    for st in storages:
+        dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[st]
+        cells = n ** 3
+        x = torch.zeros(19 * cells, device="cuda", dtype=dt)
+        y = torch.empty_like(x)
+        pkg.stream_pull(y, x, (n, n, n), st)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            pkg.stream_pull(y, x, (n, n, n), st)
+        e1.record()
+        torch.cuda.synchronize()
+        out[st] = round(2 * 19 * cells * x.element_size() * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+        del x, y
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle on a bounded sample of the headline workload: a 128^3
     periodic box holding one of its fixed r=20 spheres, same omega and body
@@ -685,6 +713,8 @@ def main():
     log("stream reference")
     sref = stream_reference()
     log(f"  {sref}")
+    pref = pull_reference(args.n, args.storages.split(","))
+    log(f"  sweep access pattern without arithmetic: {pref}")
     w = synth.precision(n=args.n)
     drag_window = 200
     drag_steps = max(args.drag_steps, args.warmup + args.steps + drag_window)
@@ -734,6 +764,8 @@ def main():
             "traffic_over_algorithmic": None if traffic is None else round(traffic / b["sweep_bytes"], 3),
             "stream_reference_gbs": sref,
             "frac_of_copy": round(b["sweep_gbs"] / sref["copy_gbs"], 3),
+            "pull_pattern_gbs": pref,
+            "frac_of_pull_pattern": round(b["sweep_gbs"] / pref[best], 3),
             "bytes_per_launch": b["sweep_bytes"],
             "launch_ms": round(b["sweep_ms"], 4),
         },

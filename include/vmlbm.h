@@ -195,6 +195,18 @@ int vmlbm_sweep_time(vmlbm_ctx* ctx, double* seconds, long long* launches);
  * reaches.  VMLBM_EINVAL for a size that is not a multiple of 16. */
 int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
+/* Bandwidth reference, not part of the method: the memory access pattern of
+ * the interior stream-collide sweep (Sec. 2.1, the pull form of Eq. 1)
+ * without its arithmetic.  src and dst hold 19 populations of a periodic
+ * n[0] x n[1] x n[2] box in the sweep's layout (cell index x fastest,
+ * population q at offset q * n[0] n[1] n[2]) in storage format `storage`
+ * (VMLBM_F64, VMLBM_F32 or VMLBM_F16); every cell gets
+ * dst[q][x] = src[q][x - c_q], with streaming stores, enqueued on `stream`.
+ * Device pointers, not overlapping, each 19 n[0] n[1] n[2] elements.
+ * VMLBM_EINVAL for null pointers or a bad storage, VMLBM_ERANGE for
+ * n[1] or n[2] outside 1..65535 or n[0] < 1. */
+int vmlbm_stream_pull(void* dst, const void* src, int storage, const int n[3], void* stream);
+
 /* Totals of the post-collision state over fluid cells: mass sum f~ and
  * momentum sum c f~ (refined grid: every level weighted by its cell volume
  * 8^-l in coarse units).  Deterministic device reduction; synchronises. */

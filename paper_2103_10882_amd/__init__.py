@@ -28,7 +28,7 @@ EXPORTS = [
     "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks",
     "vmlbm_refinements", "vmlbm_prebuilt_layouts",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
-    "vmlbm_stream_copy", "vmlbm_totals_static",
+    "vmlbm_stream_copy", "vmlbm_stream_pull", "vmlbm_totals_static",
 ]
 
 
@@ -100,6 +100,7 @@ def lib():
             "vmlbm_adjoint": [vp, ctypes.c_double, vp],
             "vmlbm_destroy": [vp],
             "vmlbm_stream_copy": [vp, vp, ctypes.c_size_t, vp],
+            "vmlbm_stream_pull": [vp, vp, ctypes.c_int, vp, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -405,3 +406,19 @@ def stream_copy(dst, src):
                                  ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     if rc != 0:
         raise VmlbmError(rc, "stream_copy")
+
+
+def stream_pull(dst, src, n, storage):
+    """The interior sweep's access pattern without arithmetic on a periodic
+    n = (nx, ny, nz) box: dst[q][x] = src[q][x - c_q] (torch tensors of 19
+    nx ny nz elements of the storage format) on torch's current stream."""
+    import torch
+    code = {"f64": 0, "f32": 1, "f16": 2}[storage]
+    cells = 19 * n[0] * n[1] * n[2]
+    assert src.numel() == cells and dst.numel() == cells
+    assert src.element_size() == dst.element_size() == (8, 4, 2)[code]
+    nn = (ctypes.c_int * 3)(*n)
+    rc = lib().vmlbm_stream_pull(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), code, nn,
+                                 ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise VmlbmError(rc, "stream_pull")

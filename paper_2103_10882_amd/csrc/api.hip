@@ -621,6 +621,12 @@ int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
   return launch_stream_copy(dst, src, bytes, (hipStream_t)stream) == hipSuccess ? VMLBM_OK : VMLBM_EDEVICE;
 }
 
+int vmlbm_stream_pull(void* dst, const void* src, int storage, const int n[3], void* stream) {
+  if (!dst || !src || !n || storage < VMLBM_F64 || storage > VMLBM_F16) return VMLBM_EINVAL;
+  if (n[0] < 1 || n[1] < 1 || n[2] < 1 || n[1] > 65535 || n[2] > 65535) return VMLBM_ERANGE;
+  return launch_stream_pull(dst, src, storage, n, (hipStream_t)stream) == hipSuccess ? VMLBM_OK : VMLBM_EDEVICE;
+}
+
 int vmlbm_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* interior) {
   int rc = check_ready(c);
   if (rc) return rc;

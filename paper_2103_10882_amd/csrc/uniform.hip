@@ -212,6 +212,30 @@ __global__ __launch_bounds__(256) void k_stream_copy(const vec4f* __restrict__ s
   if (i < n) __builtin_nontemporal_store(src[i], &dst[i]);
 }
 
+// Bandwidth reference with the interior sweep's memory access pattern and
+// no arithmetic: per cell of a periodic box (x fastest, population q at
+// q * N), population q pulled from the neighbour at x - c_q and stored, one
+// thread per cell, streaming stores.
+template <typename S>
+__global__ __launch_bounds__(256) void k_stream_pull(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
+                                                     int nz) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+  if (x >= nx) return;
+  const size_t N = (size_t)nx * ny * nz;
+  S d[kQ];
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    int xs = x - cx_of(q), ys = y - cy_of(q), zs = z - cz_of(q);
+    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+    ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+    zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
+    d[q] = src[(size_t)q * N + ((size_t)zs * ny + ys) * nx + xs];
+  }
+  const size_t c = ((size_t)z * ny + y) * nx + x;
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], d[q]);
+}
+
 // one workgroup per sphere: force/torque reduction and particle update
 __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__ parts, const double* __restrict__ slots,
                                                        double* __restrict__ hist, int* __restrict__ status,
@@ -327,6 +351,17 @@ hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
   const size_t n = bytes / 16;
   if (n) k_stream_copy<<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st>>>((const vec4f*)src, (vec4f*)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_pull(void* dst, const void* src, int storage, const int n[3], hipStream_t st) {
+  const dim3 grid((unsigned)((n[0] + 255) / 256), (unsigned)n[1], (unsigned)n[2]);
+  if (storage == 0)
+    k_stream_pull<double><<<grid, 256, 0, st>>>((const double*)src, (double*)dst, n[0], n[1], n[2]);
+  else if (storage == 1)
+    k_stream_pull<float><<<grid, 256, 0, st>>>((const float*)src, (float*)dst, n[0], n[1], n[2]);
+  else
+    k_stream_pull<__half><<<grid, 256, 0, st>>>((const __half*)src, (__half*)dst, n[0], n[1], n[2]);
   return hipGetLastError();
 }
 

@@ -67,6 +67,10 @@ hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, con
                                const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st);
 // plain device copy of bytes (a multiple of 16): the bandwidth reference
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// the interior sweep's access pattern without arithmetic (a bandwidth
+// reference): dst[q][c] = src[q][c - c_q] on a periodic n[0] x n[1] x n[2]
+// box of storage format `storage`
+hipError_t launch_stream_pull(void* dst, const void* src, int storage, const int n[3], hipStream_t st);
 // per-sphere force/torque reduction and particle update (Algorithm 1)
 hipError_t launch_reduce_update(DevParticle* parts, int np, const double* slots, double* hist, int* status,
                                 const SweepParams& p, const UpdateParams& u, hipStream_t st);

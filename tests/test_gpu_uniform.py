@@ -505,3 +505,26 @@ def test_set_sphere_motion_errors(env):
     x, u, w = sim.particle(0)
     assert (x == np.array([12.3, 11.8, 12.1])).all() and (u == 0.0).all() and (w == 0.0).all()
     sim.close()
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_stream_pull_reference(env, storage):
+    """The bandwidth reference with the sweep's access pattern moves
+    population q of every cell from its neighbour at x - c_q (periodic),
+    bit for bit, on a ragged box."""
+    import torch
+    pkg, oracle = env
+    n = (37, 5, 3)
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16}[storage]
+    g = torch.Generator().manual_seed(5)
+    src = torch.rand(19, n[2], n[1], n[0], generator=g, dtype=torch.float64).to(dt)
+    want = torch.empty_like(src)
+    c, _, _ = oracle.lattice()
+    for q in range(19):
+        want[q] = torch.roll(src[q], shifts=(int(c[q, 2]), int(c[q, 1]), int(c[q, 0])), dims=(0, 1, 2))
+    d_src = src.cuda().contiguous()
+    d_dst = torch.empty_like(d_src)
+    pkg.stream_pull(d_dst.view(-1), d_src.view(-1), n, storage)
+    torch.cuda.synchronize()
+    assert torch.equal(d_dst.cpu(), want)
