@@ -139,7 +139,8 @@ int vmlbm_step(vmlbm_ctx* ctx, int n);
  * force or torque was flagged, VMLBM_ERANGE if a particle left its range. */
 int vmlbm_sync(vmlbm_ctx* ctx);
 
-/* Particle state after the last step. */
+/* Particle state after the last step: centre, velocity and angular velocity
+ * from the virtual-mass update (Sec. 3.3, Eqs. 16-20; Algorithm 1). */
 int vmlbm_get_particle(vmlbm_ctx* ctx, int id, double x[3], double u[3], double w[3]);
 
 /* Change how sphere id moves from the next step on, its position unchanged
@@ -159,8 +160,11 @@ int vmlbm_get_force_torque(vmlbm_ctx* ctx, int id, double F[3], double T[3]);
  * F^n, T^n, x, u, w after each step.  n <= history and <= steps done. */
 int vmlbm_get_history(vmlbm_ctx* ctx, int id, int n, double* out);
 
-/* Post-collision populations f~(n) of a level (uniform grid: level 0),
- * FP64, host array [19][cells] in the canonical D3Q19 order
+/* Post-collision populations f~(n) of a level (uniform grid: level 0): the
+ * state the next step's streaming pulls from (Sec. 2.1, the collision and
+ * streaming of Eq. 1).  The library stores only this state, not the
+ * pre-collision f(n), which is one pull away.  FP64, host array
+ * [19][cells] in the canonical D3Q19 order
  * (rest; +x,-x,+y,-y,+z,-z; xy, xz, yz diagonals).  Uniform grid: cells in
  * [nz][ny][nx] order.  Refined grid: [block][16][16][16] in the order of
  * vmlbm_level_blocks.  Solid cells read 0. */
@@ -171,11 +175,15 @@ int vmlbm_read_populations(vmlbm_ctx* ctx, int level, double* out);
  * ties to even.  For tests and fault injection. */
 int vmlbm_write_populations(vmlbm_ctx* ctx, int level, const double* in);
 
-/* Particle owner per cell of a level: -1 fluid, else sphere id. */
+/* Particle owner per cell of a level (the mapping of Sec. 2.3: a cell is
+ * solid for the sphere whose centre lies within r of the cell centre):
+ * -1 fluid, else sphere id. */
 int vmlbm_read_owner(vmlbm_ctx* ctx, int level, int* out);
 
-/* Density and velocity (with the forcing shift) per cell of a level;
- * rho [cells], u [3][cells]; solid cells read 0. */
+/* Density and velocity per cell of a level (the moments of Sec. 2.1,
+ * rho = sum f, u = sum c f + F / 2 with the forcing shift of the fluid body
+ * force): rho [cells], u [3][cells], from the post-collision state; solid
+ * cells read 0. */
 int vmlbm_read_fields(vmlbm_ctx* ctx, int level, double* rho, double* u);
 
 /* Cell updates performed and device seconds measured so far by vmlbm_step. */
@@ -198,18 +206,21 @@ int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 /* Bandwidth reference, not part of the method: the memory access pattern of
  * the interior stream-collide sweep (Sec. 2.1, the pull form of Eq. 1)
  * without its arithmetic.  src and dst hold 19 populations of a periodic
- * n[0] x n[1] x n[2] box in the sweep's layout (cell index x fastest,
- * population q at offset q * n[0] n[1] n[2]) in storage format `storage`
- * (VMLBM_F64, VMLBM_F32 or VMLBM_F16); every cell gets
- * dst[q][x] = src[q][x - c_q], with streaming stores, enqueued on `stream`.
+ * n[0] x n[1] x n[2] box in storage format `storage` (VMLBM_F64, VMLBM_F32
+ * or VMLBM_F16) and in the uniform grid's population layout for that
+ * format: element (q, x, y, z) at q n0 n1 + z 19 n0 n1 + y n0 + x for FP16
+ * (the 19 populations of a z-plane side by side), at q n0 n1 n2 + z n0 n1 +
+ * y n0 + x otherwise.  Every cell gets dst[q][x] = src[q][x - c_q], with
+ * streaming stores, enqueued on `stream`.
  * Device pointers, not overlapping, each 19 n[0] n[1] n[2] elements.
  * VMLBM_EINVAL for null pointers or a bad storage, VMLBM_ERANGE for
  * n[1] or n[2] outside 1..65535 or n[0] < 1. */
 int vmlbm_stream_pull(void* dst, const void* src, int storage, const int n[3], void* stream);
 
 /* Totals of the post-collision state over fluid cells: mass sum f~ and
- * momentum sum c f~ (refined grid: every level weighted by its cell volume
- * 8^-l in coarse units).  Deterministic device reduction; synchronises. */
+ * momentum sum c f~, the conserved moments of Sec. 2.1 (refined grid: every
+ * level weighted by its cell volume 8^-l in coarse units, the volume scaling
+ * of Sec. 4.1).  Deterministic device reduction; synchronises. */
 int vmlbm_totals(vmlbm_ctx* ctx, double* mass, double mom[3]);
 
 /* vmlbm_totals for callers that cannot allocate (code under HIP graph
@@ -227,16 +238,19 @@ int vmlbm_totals(vmlbm_ctx* ctx, double* mass, double mom[3]);
  * VMLBM_ESTATE if no workspace is bound. */
 int vmlbm_totals_static(vmlbm_ctx* ctx, double* mass, double mom[3]);
 
-/* Uniform grid: post-collision populations of the cells of a box (periodic
- * wrap), FP64 host array [19][size2][size1][size0]; solid cells read 0. */
+/* Uniform grid: post-collision populations f~(n) (as vmlbm_read_populations,
+ * Sec. 2.1) of the cells of a box (periodic wrap), FP64 host array
+ * [19][size2][size1][size0]; solid cells read 0. */
 int vmlbm_read_box(vmlbm_ctx* ctx, const int lo[3], const int size[3], double* out);
 
 /* Cells of a level that are fluid, and fluid cells without any wall or
- * particle link (those the interior sweep updates). */
+ * particle link (those the interior sweep updates; link cells are those with
+ * a lattice link into a solid cell or a wall, Sec. 2.3). */
 int vmlbm_cell_counts(vmlbm_ctx* ctx, int level, long long* fluid, long long* interior);
 
-/* Block list of a refined level: *count blocks; if origin != NULL it gets
- * [count][3] block origins in that level's cell units. */
+/* Block list of a refined level (the leaf blocks of that level in the
+ * block-structured grid of Sec. 4.1): *count blocks; if origin != NULL it
+ * gets [count][3] block origins in that level's cell units. */
 int vmlbm_level_blocks(vmlbm_ctx* ctx, int level, int* count, int* origin);
 
 /* Number of re-refinements performed so far (Sec. 4.2). */

@@ -411,7 +411,9 @@ def stream_copy(dst, src):
 def stream_pull(dst, src, n, storage):
     """The interior sweep's access pattern without arithmetic on a periodic
     n = (nx, ny, nz) box: dst[q][x] = src[q][x - c_q] (torch tensors of 19
-    nx ny nz elements of the storage format) on torch's current stream."""
+    nx ny nz elements of the storage format, in its population layout:
+    [z][q][y][x] for f16, [q][z][y][x] otherwise) on torch's current
+    stream."""
     import torch
     code = {"f64": 0, "f32": 1, "f16": 2}[storage]
     cells = 19 * n[0] * n[1] * n[2]

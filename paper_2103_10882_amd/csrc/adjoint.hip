@@ -148,8 +148,10 @@ __global__ __launch_bounds__(512) void k_adj_interior(const S* __restrict__ s, c
   double gF = 0.0, gW = 0.0;
   if (x < p.nx && flags[c] == 0) {
     T d[kQ], lam[kQ], nu[kQ];
-    const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz);
-    load_all<S>(s, N, I, x, d, std::make_integer_sequence<int, kQ>{});
+    // the state in its population layout, the adjoint fields [q][z][y][x]
+    const Idx Is = make_idx(x, y, z, p.nx, p.ny, p.nz, p.sz);
+    const Idx I = make_idx(x, y, z, p.nx, p.ny, p.nz, (size_t)p.nx * p.ny);
+    load_all<S>(s, p.sq, Is, x, d, std::make_integer_sequence<int, kQ>{});
 #pragma unroll
     for (int q = 0; q < kQ; ++q) lam[q] = T(lin[(size_t)q * N + c]);
     collide_adjoint<T>(d, lam, T(p.sp), T(p.sm), T(p.F[0]), T(p.F[1]), T(p.F[2]), dsm_dw, nu, gF, gW);
@@ -202,10 +204,8 @@ __global__ __launch_bounds__(256) void k_adj_boundary(const S* __restrict__ s, c
     uint32_t mask = 0;
     int pid = -1;
     double Fl[3] = {0, 0, 0}, Tl[3] = {0, 0, 0}, Kl[3] = {0, 0, 0}, Bl[3] = {0, 0, 0};
-    UAddr ad;
-    ad.n[0] = p.nx; ad.n[1] = p.ny; ad.n[2] = p.nz;
+    UAddr ad = uaddr(p);
     ad.per[0] = ad.per[1] = ad.per[2] = 1;
-    ad.N = p.N;
     boundary_cell<S, UAddr>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, Kl, Bl, status, &mask, kap,
                             pi);
 #pragma unroll

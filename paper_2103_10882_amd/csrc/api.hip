@@ -178,6 +178,9 @@ SweepParams sweep_params(const vmlbm_ctx* c) {
   p.sb = c->sb;
   for (int a = 0; a < 3; ++a) p.F[a] = c->F[a];
   p.N = (uint32_t)((size_t)g.n[0] * g.n[1] * g.n[2]);
+  const PopLayout lay = pop_layout(g.storage, g.n);
+  p.sq = lay.sq;
+  p.sz = lay.sz;
   p.box = c->box;
   p.slot_stride = c->slot_stride;
   return p;
@@ -516,9 +519,11 @@ int vmlbm_read_populations(vmlbm_ctx* c, int level, double* out) {
   HIP_TRY(c, hipMemcpy(raw.data(), c->ws + c->off_pdf[c->cur], raw.size(), hipMemcpyDeviceToHost));
   std::vector<uint8_t> fl(N, 0);
   if (c->use_flags) HIP_TRY(c, hipMemcpy(fl.data(), c->flags(), N, hipMemcpyDeviceToHost));
+  const PopLayout lay = pop_layout(c->cfg.storage, c->cfg.n);
   for (int q = 0; q < 19; ++q)
     for (size_t i = 0; i < N; ++i)
-      out[q * N + i] = (fl[i] & kSolid) ? 0.0 : w_of(q) + dev_to_double(raw.data(), c->cfg.storage, q * N + i);
+      out[q * N + i] =
+          (fl[i] & kSolid) ? 0.0 : w_of(q) + dev_to_double(raw.data(), c->cfg.storage, lay.pop(q, (uint32_t)i));
   return VMLBM_OK;
 }
 
@@ -532,8 +537,10 @@ int vmlbm_write_populations(vmlbm_ctx* c, int level, const double* in) {
   const size_t N = (size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2];
   const size_t S = storage_bytes(c->cfg.storage);
   std::vector<char> raw(19 * N * S);
+  const PopLayout lay = pop_layout(c->cfg.storage, c->cfg.n);
   for (int q = 0; q < 19; ++q)
-    for (size_t i = 0; i < N; ++i) double_to_dev(raw.data(), c->cfg.storage, q * N + i, in[q * N + i] - w_of(q));
+    for (size_t i = 0; i < N; ++i)
+      double_to_dev(raw.data(), c->cfg.storage, lay.pop(q, (uint32_t)i), in[q * N + i] - w_of(q));
   HIP_TRY(c, hipMemcpy(c->ws + c->off_pdf[c->cur], raw.data(), raw.size(), hipMemcpyHostToDevice));
   return VMLBM_OK;
 }
@@ -654,8 +661,8 @@ int vmlbm_cell_counts(vmlbm_ctx* c, int level, long long* fluid, long long* inte
 static int totals_with(vmlbm_ctx* c, double* part, double* h, double* mass, double mom[3]) {
   if (c->cfg.block > 0) return refine_totals(c, part, h, mass, mom);
   const uint32_t N = (uint32_t)((size_t)c->cfg.n[0] * c->cfg.n[1] * c->cfg.n[2]);
-  HIP_TRY(c, launch_totals(c->cfg.storage, c->ws + c->off_pdf[c->cur], c->use_flags ? c->flags() : nullptr, N, N,
-                           nullptr, 0, part, c->stream));
+  HIP_TRY(c, launch_totals(c->cfg.storage, c->ws + c->off_pdf[c->cur], c->use_flags ? c->flags() : nullptr,
+                           pop_layout(c->cfg.storage, c->cfg.n), N, nullptr, 0, part, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpy(h, part, (size_t)kTotalsGroups * 8 * sizeof(double), hipMemcpyDeviceToHost));
   long double n = 0, m = 0, j[3] = {0, 0, 0};
@@ -693,7 +700,7 @@ int vmlbm_read_box(vmlbm_ctx* c, const int lo[3], const int size[3], double* out
   for (int a = 0; a < 3; ++a)
     if (size[a] <= 0 || size[a] > n[a]) return fail(c, VMLBM_EINVAL, "bad box size");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  const size_t N = (size_t)n[0] * n[1] * n[2];
+  const PopLayout lay = pop_layout(c->cfg.storage, n);
   const size_t S = storage_bytes(c->cfg.storage);
   const char* base = c->ws + c->off_pdf[c->cur];
   std::vector<char> row((size_t)size[0] * S);
@@ -706,9 +713,10 @@ int vmlbm_read_box(vmlbm_ctx* c, const int lo[3], const int size[3], double* out
         const int x0 = ((lo[0] % n[0]) + n[0]) % n[0];
         const int first = std::min(size[0], n[0] - x0);
         const size_t r = ((size_t)z * n[1] + y) * n[0];
-        HIP_TRY(c, hipMemcpy(row.data(), base + (q * N + r + x0) * S, first * S, hipMemcpyDeviceToHost));
+        const size_t pr = lay.pop(q, (uint32_t)r);   // population q of the row's first cell
+        HIP_TRY(c, hipMemcpy(row.data(), base + (pr + x0) * S, first * S, hipMemcpyDeviceToHost));
         if (first < size[0])
-          HIP_TRY(c, hipMemcpy(row.data() + first * S, base + (q * N + r) * S, (size[0] - first) * S,
+          HIP_TRY(c, hipMemcpy(row.data() + first * S, base + pr * S, (size[0] - first) * S,
                                hipMemcpyDeviceToHost));
         if (q == 0 && c->use_flags) {
           HIP_TRY(c, hipMemcpy(frow.data(), c->flags() + r + x0, first, hipMemcpyDeviceToHost));

@@ -108,7 +108,8 @@ int uniform_step(vmlbm_ctx* c, int nsteps);
 // deterministic sums over cells: kTotalsGroups workgroup partials of
 // (fluid cells, sum d, sum c d) per call
 constexpr int kTotalsGroups = 1024;
-hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uint32_t N, uint32_t cells,
+// (lay: the uniform grid's population layout; unused with a slot list)
+hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, const PopLayout& lay, uint32_t cells,
                          const int* slot_list, int nslots, double* partials, hipStream_t st);
 int refine_totals(vmlbm_ctx* c, double* part, double* h, double* mass, double mom[3]);
 

@@ -1971,8 +1971,7 @@ int refine_totals(vmlbm_ctx* c, double* part, double* h, double* mass, double mo
     Forest::Lev& V = f.lv[l];
     if (!V.n_int) continue;
     HIP_TRY(c, launch_totals(c->cfg.storage, c->ws + V.off_pdf[V.cur], (const uint8_t*)(c->ws + V.off_flags),
-                             (uint32_t)V.cap * kBlockCells, 0, (const int*)(c->ws + V.off_int), V.n_int, part,
-                             c->stream));
+                             PopLayout{}, 0, (const int*)(c->ws + V.off_int), V.n_int, part, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     HIP_TRY(c, hipMemcpy(h, part, (size_t)kTotalsGroups * 8 * sizeof(double), hipMemcpyDeviceToHost));
     long double n = 0, ml = 0, jl[3] = {0, 0, 0};

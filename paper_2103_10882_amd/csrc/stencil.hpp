@@ -6,48 +6,48 @@
 #include <utility>
 
 #include "common.hpp"
-#include "uniform.hpp"
 
 namespace vm {
 
 struct Idx {
   int xm, xp;            // x-1, x+1 wrapped
   uint32_t rm, r0, rp;   // row offsets of y-1, y, y+1 (wrapped) within a plane
-  uint32_t pm, p0, pp;   // plane offsets of z-1, z, z+1 (wrapped)
+  size_t pm, p0, pp;     // offsets of planes z-1, z, z+1 (wrapped): z times the plane stride
 };
 
-__device__ __forceinline__ Idx make_idx(int x, int y, int z, int nx, int ny, int nz) {
+// plane stride zs: nx ny for cell-indexed arrays, PopLayout::sz for populations
+__device__ __forceinline__ Idx make_idx(int x, int y, int z, int nx, int ny, int nz, size_t zs) {
   Idx I;
   I.xm = x == 0 ? nx - 1 : x - 1;
   I.xp = x + 1 == nx ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y + 1 == ny ? 0 : y + 1;
   const int zm = z == 0 ? nz - 1 : z - 1, zp = z + 1 == nz ? 0 : z + 1;
   I.rm = (uint32_t)ym * nx; I.r0 = (uint32_t)y * nx; I.rp = (uint32_t)yp * nx;
-  const uint32_t plane = (uint32_t)nx * ny;
-  I.pm = (uint32_t)zm * plane; I.p0 = (uint32_t)z * plane; I.pp = (uint32_t)zp * plane;
+  I.pm = (size_t)zm * zs; I.p0 = (size_t)z * zs; I.pp = (size_t)zp * zs;
   return I;
 }
 
-// index of the pull source x - c_q (periodic wrap; walls handled elsewhere)
+// offset of the pull source x - c_q within one population (periodic wrap;
+// walls handled elsewhere)
 template <int Q>
-__device__ __forceinline__ uint32_t pull_index(const Idx& I, int x) {
+__device__ __forceinline__ size_t pull_index(const Idx& I, int x) {
   constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
   const uint32_t xs = cx == 1 ? I.xm : (cx == -1 ? I.xp : x);
   const uint32_t ys = cy == 1 ? I.rm : (cy == -1 ? I.rp : I.r0);
-  const uint32_t zs = cz == 1 ? I.pm : (cz == -1 ? I.pp : I.p0);
+  const size_t zs = cz == 1 ? I.pm : (cz == -1 ? I.pp : I.p0);
   return zs + ys + xs;
 }
 
 template <typename S, int Q>
-__device__ __forceinline__ void load_pull(const S* __restrict__ src, uint32_t N, const Idx& I, int x,
+__device__ __forceinline__ void load_pull(const S* __restrict__ src, uint32_t sq, const Idx& I, int x,
                                           typename Store<S>::T (&d)[kQ]) {
-  d[Q] = Store<S>::load(src[(size_t)Q * N + pull_index<Q>(I, x)]);
+  d[Q] = Store<S>::load(src[(size_t)Q * sq + pull_index<Q>(I, x)]);
 }
 
 template <typename S, int... Qs>
-__device__ __forceinline__ void load_all(const S* __restrict__ src, uint32_t N, const Idx& I, int x,
+__device__ __forceinline__ void load_all(const S* __restrict__ src, uint32_t sq, const Idx& I, int x,
                                          typename Store<S>::T (&d)[kQ], std::integer_sequence<int, Qs...>) {
-  (load_pull<S, Qs>(src, N, I, x, d), ...);
+  (load_pull<S, Qs>(src, sq, I, x, d), ...);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -62,11 +62,26 @@ __device__ __forceinline__ double wave_sum(double v) {
 //
 // Uniform grid: cells [z][y][x], populations SoA [q][z][y][x]; periodic axes
 // wrap, other axes end in walls.
+// Population layout of the uniform grid: element (q, x, y, z) at
+// q sq + z sz + y nx + x.  [q][z][y][x] has sq = N, sz = nx ny; [z][q][y][x]
+// (the 19 populations of a z-plane side by side) has sq = nx ny,
+// sz = 19 nx ny.  Cell indices (flags, owner, rounding streams) stay
+// c = z nx ny + y nx + x in both.
+struct PopLayout {
+  uint32_t sq, plane;
+  size_t sz;
+  // offset of population q of cell c
+  __host__ __device__ __forceinline__ size_t pop(int q, uint32_t c) const {
+    const size_t o = (size_t)q * sq + c;
+    return sz == plane ? o : o + (size_t)(c / plane) * (sz - plane);
+  }
+};
+
 struct UAddr {
   int n[3];
   int per[3];
-  uint32_t N;
-  __device__ __forceinline__ size_t pop(int q, uint32_t c) const { return (size_t)q * N + c; }
+  PopLayout lay;
+  __device__ __forceinline__ size_t pop(int q, uint32_t c) const { return lay.pop(q, c); }
   // 1: stored cell c; 0: outside through the wall (axis wa, side ws)
   __device__ __forceinline__ int locate(int x, int y, int z, uint32_t& c, int& wa, int& ws) const {
     int s[3] = {x, y, z};

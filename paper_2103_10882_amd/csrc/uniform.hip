@@ -3,11 +3,12 @@
 // of uncovered cells, and re-mapping.  The per-particle reduction and update
 // are in motion.hip.
 //
-// Layout: populations SoA [q][z][y][x] as deviations in storage type S, two
-// buffers (pull from src, write dst); flags uint8 [z][y][x]; owner uint16
-// [z][y][x] (read only for solid cells).  One thread per cell, one wave per
-// 64 consecutive x cells of a row, so every population load and store of a
-// wave is a contiguous run shifted by at most one element.
+// Layout: populations as deviations in storage type S, element (q, x, y, z)
+// at q sq + z sz + y nx + x (PopLayout: [q][z][y][x], or [z][q][y][x] for
+// FP16), two buffers (pull from src, write dst); flags uint8 [z][y][x];
+// owner uint16 [z][y][x] (read only for solid cells).  One thread per cell,
+// one wave per 64 consecutive x cells of a row, so every population load and
+// store of a wave is a contiguous run shifted by at most one element.
 #include <type_traits>
 #include <utility>
 
@@ -20,14 +21,6 @@
 namespace vm {
 
 namespace {
-
-__host__ __device__ UAddr uaddr(const SweepParams& p) {
-  UAddr a;
-  a.n[0] = p.nx; a.n[1] = p.ny; a.n[2] = p.nz;
-  for (int i = 0; i < 3; ++i) a.per[i] = p.per[i];
-  a.N = p.N;
-  return a;
-}
 
 // Interior sweep: every fluid cell without a wall or particle link.  Cells
 // with a nonzero flag are left to the boundary kernels below (solid cells are
@@ -47,24 +40,25 @@ __device__ __forceinline__ gchar* uniform_ptr(char* p) {
   return (gchar*)(((uint64_t)hi << 32) | lo);
 }
 
+// sq: population stride; pm, p0, pp: offsets of planes z-1, z, z+1
 template <typename S, int Q>
-__device__ __forceinline__ void pull_row(const S* __restrict__ src, uint32_t N, uint32_t rm, uint32_t r0,
-                                         uint32_t rp, uint32_t pm, uint32_t p0, uint32_t pp, uint32_t xm,
+__device__ __forceinline__ void pull_row(const S* __restrict__ src, uint32_t sq, uint32_t rm, uint32_t r0,
+                                         uint32_t rp, size_t pm, size_t p0, size_t pp, uint32_t xm,
                                          uint32_t x, uint32_t xp, typename Store<S>::T (&d)[kQ]) {
   constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
   const uint32_t ys = cy == 1 ? rm : (cy == -1 ? rp : r0);
-  const uint32_t zs = cz == 1 ? pm : (cz == -1 ? pp : p0);
-  const char* __restrict__ row = reinterpret_cast<const char*>(src + ((size_t)Q * N + zs + ys));
+  const size_t zs = cz == 1 ? pm : (cz == -1 ? pp : p0);
+  const char* __restrict__ row = reinterpret_cast<const char*>(src + ((size_t)Q * sq + zs + ys));
   const uint32_t xb = (cx == 1 ? xm : (cx == -1 ? xp : x)) * (uint32_t)sizeof(S);   // byte offset, 32 bits
   d[Q] = Store<S>::load(*reinterpret_cast<const S*>(row + xb));
 }
 
 template <typename S, int... Qs>
-__device__ __forceinline__ void pull_rows(const S* __restrict__ src, uint32_t N, uint32_t rm, uint32_t r0,
-                                          uint32_t rp, uint32_t pm, uint32_t p0, uint32_t pp, uint32_t xm,
+__device__ __forceinline__ void pull_rows(const S* __restrict__ src, uint32_t sq, uint32_t rm, uint32_t r0,
+                                          uint32_t rp, size_t pm, size_t p0, size_t pp, uint32_t xm,
                                           uint32_t x, uint32_t xp, typename Store<S>::T (&d)[kQ],
                                           std::integer_sequence<int, Qs...>) {
-  (pull_row<S, Qs>(src, N, rm, r0, rp, pm, p0, pp, xm, x, xp, d), ...);
+  (pull_row<S, Qs>(src, sq, rm, r0, rp, pm, p0, pp, xm, x, xp, d), ...);
 }
 
 // A workgroup is RY row segments of BX cells (RY consecutive rows of one
@@ -80,27 +74,27 @@ __global__ __launch_bounds__(BX * RY) void k_sweep(const S* __restrict__ src, S*
                         : (int)__builtin_amdgcn_readfirstlane(blockIdx.y * RY + threadIdx.x / BX);
   const int z = blockIdx.z;
   if (x >= (uint32_t)p.nx || y >= p.ny) return;
-  const uint32_t N = p.N, nx = p.nx;
+  const uint32_t nx = p.nx;
   const uint32_t plane = nx * p.ny;
-  const uint32_t row0 = (uint32_t)z * plane + (uint32_t)y * nx;
-  const uint32_t c = row0 + x;
+  const uint32_t c = (uint32_t)z * plane + (uint32_t)y * nx + x;
   if (FLAGS && flags[c] != 0) return;
   const uint32_t ym = y == 0 ? p.ny - 1 : y - 1, yp = y + 1 == p.ny ? 0 : y + 1;
   const uint32_t zm = z == 0 ? p.nz - 1 : z - 1, zp = z + 1 == p.nz ? 0 : z + 1;
   const uint32_t xm = x == 0 ? nx - 1 : x - 1, xp = x + 1 == nx ? 0 : x + 1;
   T d[kQ];
-  pull_rows<S>(src, N, ym * nx, (uint32_t)y * nx, yp * nx, zm * plane, (uint32_t)z * plane, zp * plane, xm, x, xp,
-               d, std::make_integer_sequence<int, kQ>{});
+  pull_rows<S>(src, p.sq, ym * nx, (uint32_t)y * nx, yp * nx, (size_t)zm * p.sz, (size_t)z * p.sz,
+               (size_t)zp * p.sz, xm, x, xp, d, std::make_integer_sequence<int, kQ>{});
   const T drho = lbm_collide<T, MRT>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   // streaming stores: the new state is not read again within this sweep
   SrBits rb(c, p.seed);
   const uint32_t xb = x * (uint32_t)sizeof(S);
+  const size_t row0 = (size_t)z * p.sz + (uint32_t)y * nx;
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     // the row base is workgroup-uniform; stating it so keeps the compiler
     // from folding it into a per-lane 64-bit address
-    gchar* out = uniform_ptr(reinterpret_cast<char*>(dst + ((size_t)q * N + row0)));
+    gchar* out = uniform_ptr(reinterpret_cast<char*>(dst + ((size_t)q * p.sq + row0)));
     store_nt_g(out + xb, Store<S>::store_sr(d[q], rb.next()));
   }
 }
@@ -137,7 +131,7 @@ __global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ sr
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   SrBits rb(c, p.seed);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store_sr(d[q], rb.next());
+  for (int q = 0; q < kQ; ++q) dst[ad.pop(q, c)] = Store<S>::store_sr(d[q], rb.next());
 }
 
 // ---------------------------------------------------------------------------
@@ -161,8 +155,9 @@ __global__ __launch_bounds__(256) void k_init(S* __restrict__ dst, const uint8_t
   }
   lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   SrBits rb(c, p.seed);
+  const UAddr ad = uaddr(p);
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) dst[(size_t)q * p.N + c] = Store<S>::store_sr(d[q], rb.next());
+  for (int q = 0; q < kQ; ++q) dst[ad.pop(q, c)] = Store<S>::store_sr(d[q], rb.next());
 }
 
 __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
@@ -179,7 +174,7 @@ __global__ __launch_bounds__(256) void k_map_all(uint8_t* __restrict__ flags, ui
 // slots of a block level, whose populations are blocked)
 template <typename S>
 __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ pdf, const uint8_t* __restrict__ flags,
-                                                uint32_t N, uint32_t cells, const int* __restrict__ slots,
+                                                PopLayout lay, uint32_t cells, const int* __restrict__ slots,
                                                 int nslots, double* __restrict__ part) {
   double v[5] = {0, 0, 0, 0, 0};
   const uint32_t total = slots ? (uint32_t)nslots * 4096u : cells;
@@ -188,7 +183,7 @@ __global__ __launch_bounds__(256) void k_totals(const S* __restrict__ pdf, const
     if (flags && (flags[c] & kSolid)) continue;
     v[0] += 1.0;
     for (int q = 0; q < kQ; ++q) {
-      const double d = (double)Store<S>::load(pdf[slots ? bpop(q, c) : (size_t)q * N + c]);
+      const double d = (double)Store<S>::load(pdf[slots ? bpop(q, c) : lay.pop(q, c)]);
       v[1] += d;
       v[2] += cx_of(q) * d;
       v[3] += cy_of(q) * d;
@@ -213,15 +208,14 @@ __global__ __launch_bounds__(256) void k_stream_copy(const vec4f* __restrict__ s
 }
 
 // Bandwidth reference with the interior sweep's memory access pattern and
-// no arithmetic: per cell of a periodic box (x fastest, population q at
-// q * N), population q pulled from the neighbour at x - c_q and stored, one
-// thread per cell, streaming stores.
+// no arithmetic: per cell of a periodic box in the sweep's population layout
+// for this storage format, population q pulled from the neighbour at
+// x - c_q and stored, one thread per cell, streaming stores.
 template <typename S>
 __global__ __launch_bounds__(256) void k_stream_pull(const S* __restrict__ src, S* __restrict__ dst, int nx, int ny,
-                                                     int nz) {
+                                                     int nz, PopLayout lay) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
   if (x >= nx) return;
-  const size_t N = (size_t)nx * ny * nz;
   S d[kQ];
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
@@ -229,11 +223,11 @@ __global__ __launch_bounds__(256) void k_stream_pull(const S* __restrict__ src, 
     xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
     ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
     zs = zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs);
-    d[q] = src[(size_t)q * N + ((size_t)zs * ny + ys) * nx + xs];
+    d[q] = src[(size_t)q * lay.sq + (size_t)zs * lay.sz + (size_t)ys * nx + xs];
   }
-  const size_t c = ((size_t)z * ny + y) * nx + x;
+  const size_t row = (size_t)z * lay.sz + (size_t)y * nx + x;
 #pragma unroll
-  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * N + c], d[q]);
+  for (int q = 0; q < kQ; ++q) store_nt(&dst[(size_t)q * lay.sq + row], d[q]);
 }
 
 // one workgroup per sphere: force/torque reduction and particle update
@@ -245,14 +239,17 @@ __global__ __launch_bounds__(256) void k_reduce_update(DevParticle* __restrict__
 
 }  // namespace
 
-hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, uint32_t N, uint32_t cells,
+hipError_t launch_totals(int storage, const void* pdf, const uint8_t* flags, const PopLayout& lay, uint32_t cells,
                          const int* slot_list, int nslots, double* partials, hipStream_t st) {
   if (storage == 0)
-    k_totals<double><<<kTotalsGroups, 256, 0, st>>>((const double*)pdf, flags, N, cells, slot_list, nslots, partials);
+    k_totals<double><<<kTotalsGroups, 256, 0, st>>>((const double*)pdf, flags, lay, cells, slot_list, nslots,
+                                                    partials);
   else if (storage == 1)
-    k_totals<float><<<kTotalsGroups, 256, 0, st>>>((const float*)pdf, flags, N, cells, slot_list, nslots, partials);
+    k_totals<float><<<kTotalsGroups, 256, 0, st>>>((const float*)pdf, flags, lay, cells, slot_list, nslots,
+                                                   partials);
   else
-    k_totals<__half><<<kTotalsGroups, 256, 0, st>>>((const __half*)pdf, flags, N, cells, slot_list, nslots, partials);
+    k_totals<__half><<<kTotalsGroups, 256, 0, st>>>((const __half*)pdf, flags, lay, cells, slot_list, nslots,
+                                                    partials);
   return hipGetLastError();
 }
 
@@ -356,12 +353,13 @@ hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStrea
 
 hipError_t launch_stream_pull(void* dst, const void* src, int storage, const int n[3], hipStream_t st) {
   const dim3 grid((unsigned)((n[0] + 255) / 256), (unsigned)n[1], (unsigned)n[2]);
+  const PopLayout lay = pop_layout(storage, n);
   if (storage == 0)
-    k_stream_pull<double><<<grid, 256, 0, st>>>((const double*)src, (double*)dst, n[0], n[1], n[2]);
+    k_stream_pull<double><<<grid, 256, 0, st>>>((const double*)src, (double*)dst, n[0], n[1], n[2], lay);
   else if (storage == 1)
-    k_stream_pull<float><<<grid, 256, 0, st>>>((const float*)src, (float*)dst, n[0], n[1], n[2]);
+    k_stream_pull<float><<<grid, 256, 0, st>>>((const float*)src, (float*)dst, n[0], n[1], n[2], lay);
   else
-    k_stream_pull<__half><<<grid, 256, 0, st>>>((const __half*)src, (__half*)dst, n[0], n[1], n[2]);
+    k_stream_pull<__half><<<grid, 256, 0, st>>>((const __half*)src, (__half*)dst, n[0], n[1], n[2], lay);
   return hipGetLastError();
 }
 

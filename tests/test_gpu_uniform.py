@@ -512,7 +512,8 @@ def test_set_sphere_motion_errors(env):
 def test_stream_pull_reference(env, storage):
     """The bandwidth reference with the sweep's access pattern moves
     population q of every cell from its neighbour at x - c_q (periodic),
-    bit for bit, on a ragged box."""
+    bit for bit, on a ragged box, in the storage format's population layout
+    ([z][q][y][x] for FP16, [q][z][y][x] otherwise)."""
     import torch
     pkg, oracle = env
     n = (37, 5, 3)
@@ -523,8 +524,10 @@ def test_stream_pull_reference(env, storage):
     c, _, _ = oracle.lattice()
     for q in range(19):
         want[q] = torch.roll(src[q], shifts=(int(c[q, 2]), int(c[q, 1]), int(c[q, 0])), dims=(0, 1, 2))
-    d_src = src.cuda().contiguous()
+    plane = storage == "f16"
+    d_src = (src.permute(1, 0, 2, 3) if plane else src).contiguous().cuda()
     d_dst = torch.empty_like(d_src)
     pkg.stream_pull(d_dst.view(-1), d_src.view(-1), n, storage)
     torch.cuda.synchronize()
-    assert torch.equal(d_dst.cpu(), want)
+    got = d_dst.cpu()
+    assert torch.equal(got.permute(1, 0, 2, 3) if plane else got, want)
