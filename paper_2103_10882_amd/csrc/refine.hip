@@ -1576,10 +1576,16 @@ void prebuild_next(vmlbm_ctx* c, Forest& f, const std::vector<vmlbm_sphere>& sph
   std::vector<int8_t> t = layout_targets(f, nb);
   f.pre = p;
   f.job = std::thread([p, g, t]() {
-    g->leaf = balance_layout(*g, t);
-    p->rc = build_tables(nullptr, *g);
-    p->leaf = std::move(g->leaf);
-    p->lv = std::move(g->lv);
+    // a failed build (capacity, memory) is left to the check, which then
+    // builds at the check and reports the error itself
+    try {
+      g->leaf = balance_layout(*g, t);
+      p->rc = build_tables(nullptr, *g);
+      p->leaf = std::move(g->leaf);
+      p->lv = std::move(g->lv);
+    } catch (...) {
+      p->rc = VMLBM_ENOMEM;
+    }
   });
 }
 
