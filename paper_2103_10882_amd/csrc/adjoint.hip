@@ -204,9 +204,9 @@ __global__ __launch_bounds__(256) void k_adj_boundary(const S* __restrict__ s, c
     uint32_t mask = 0;
     int pid = -1;
     double Fl[3] = {0, 0, 0}, Tl[3] = {0, 0, 0}, Kl[3] = {0, 0, 0}, Bl[3] = {0, 0, 0};
-    UAddr ad = uaddr(p);
+    UAddrOf<S> ad = uaddr<sizeof(S) == 2>(p);
     ad.per[0] = ad.per[1] = ad.per[2] = 1;
-    boundary_cell<S, UAddr>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, Kl, Bl, status, &mask, kap,
+    boundary_cell<S, UAddrOf<S>>(s, flags, owner, parts, p, ad, x, y, z, c, d, pid, Fl, Tl, Kl, Bl, status, &mask, kap,
                             pi);
 #pragma unroll
     for (int q = 0; q < kQ; ++q) lam[q] = T(lin[(size_t)q * N + c]);

@@ -77,11 +77,29 @@ struct PopLayout {
   }
 };
 
-struct UAddr {
+// Cell addressing of the uniform grid, its population layout fixed at
+// compile time (a runtime choice would carry the plane-interleaved branch and
+// its division into every kernel, and it cost the FP32/FP64 boundary kernels
+// registers and scratch): PLANE = false [q][z][y][x], true [z][q][y][x].
+template <bool PLANE>
+struct UAddrT {
   int n[3];
   int per[3];
   PopLayout lay;
-  __device__ __forceinline__ size_t pop(int q, uint32_t c) const { return lay.pop(q, c); }
+  // z = c / (nx ny) by multiplication with a precomputed magic number
+  // (division by an invariant integer, Granlund and Montgomery 1994): with
+  // l = ceil(log2 d), m = floor(2^32 (2^l - d) / d) + 1, t = hi32(m c),
+  // c / d = (t + ((c - t) >> min(l, 1))) >> max(l - 1, 0) for all c < 2^32
+  uint32_t zm, zs1, zs2;
+  __device__ __forceinline__ size_t pop(int q, uint32_t c) const {
+    if constexpr (PLANE) {
+      const uint32_t t = __umulhi(zm, c);
+      const uint32_t z = (t + ((c - t) >> zs1)) >> zs2;
+      return (size_t)q * lay.sq + c + (size_t)z * (lay.sz - lay.plane);
+    } else {
+      return (size_t)q * lay.sq + c;
+    }
+  }
   // 1: stored cell c; 0: outside through the wall (axis wa, side ws)
   __device__ __forceinline__ int locate(int x, int y, int z, uint32_t& c, int& wa, int& ws) const {
     int s[3] = {x, y, z};
@@ -96,6 +114,10 @@ struct UAddr {
     return 1;
   }
 };
+// the layout of storage type S (FP16: plane-interleaved; see pop_layout)
+template <typename S> using UAddrOf = UAddrT<sizeof(S) == 2>;
+// flags and owner only (no population access)
+using UAddr = UAddrT<false>;
 
 // One level of the block-structured grid: 16^3-cell blocks in slots
 // (cell index = slot * 4096 + local), periodic; a dense table gives the slot

@@ -125,8 +125,9 @@ __global__ __launch_bounds__(256) void k_boundary_walls(const S* __restrict__ sr
   int pid = -1;
   double Fl[3] = {0.0, 0.0, 0.0}, Tl[3] = {0.0, 0.0, 0.0}, Kl[3] = {0.0, 0.0, 0.0}, Bl[3] = {0.0, 0.0, 0.0};
   T d[kQ];
-  const UAddr ad = uaddr(p);
-  boundary_cell<S, UAddr>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, Kl, Bl, status);
+  const UAddrOf<S> ad = uaddr<sizeof(S) == 2>(p);
+  boundary_cell<S, UAddrOf<S>>(src, flags, owner, parts, p, ad, r[0], r[1], r[2], c, d, pid, Fl, Tl, Kl, Bl,
+                               status);
   const T drho = lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   if (!(drho == drho)) status[kStatusUnstable] = 1;
   SrBits rb(c, p.seed);
@@ -155,7 +156,7 @@ __global__ __launch_bounds__(256) void k_init(S* __restrict__ dst, const uint8_t
   }
   lbm_collide<T>(d, T(p.sp), T(p.sm), T(p.sb), T(p.F[0]), T(p.F[1]), T(p.F[2]));
   SrBits rb(c, p.seed);
-  const UAddr ad = uaddr(p);
+  const UAddrOf<S> ad = uaddr<sizeof(S) == 2>(p);
 #pragma unroll
   for (int q = 0; q < kQ; ++q) dst[ad.pop(q, c)] = Store<S>::store_sr(d[q], rb.next());
 }
@@ -317,8 +318,8 @@ hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, con
                            const SweepParams& p, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (np > 0) {
-    k_boundary_particles<S, UAddr><<<dim3(kLinkGroups, np), dim3(256), 0, st>>>(
-        (const S*)src, (S*)dst, flags, owner, parts, ll.links, ll.len, slots, status, p, uaddr(p));
+    k_boundary_particles<S, UAddrOf<S>><<<dim3(kLinkGroups, np), dim3(256), 0, st>>>(
+        (const S*)src, (S*)dst, flags, owner, parts, ll.links, ll.len, slots, status, p, uaddr<sizeof(S) == 2>(p));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -383,7 +384,8 @@ hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, con
                                const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st) {
   const int rb = p.box + 1;
   dim3 grid(2 * ((rb * rb * rb + 255) / 256), np), block(256);
-  k_refill_remap<S, UAddr><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p, uaddr(p), status);
+  k_refill_remap<S, UAddrOf<S>><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p,
+                                                        uaddr<sizeof(S) == 2>(p), status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_link_lists<UAddr>(flags, owner, parts, np, p, uaddr(p), ll.count, ll.links, ll.len, st);
