@@ -44,6 +44,10 @@ constexpr uint8_t kIface = 0x10;   // interior cell with a coalescence pull
 // positions (at most 2^26 of them), which bounds the coarse domain that deep
 // hierarchies can take: one coarse block at 9 levels.
 constexpr int kMaxLevels = 9;
+// words per slot of the neighbour table: the slots of the 27 blocks around
+// it (-1 or -2 where the level stores none), whether all 27 are stored, and
+// padding to 128 bytes
+constexpr int kNbrWords = 32;
 
 struct IfaceEntry {
   int slot, local;      // the coarse cell
@@ -80,6 +84,7 @@ struct Forest {
     std::vector<int> slot_of;         // per block position: slot, -1 coarser, -2 finer
     std::vector<int> interior, ghost; // slot lists
     std::vector<int> pos;             // per slot: x, y, z block position
+    std::vector<int> nbr;             // per slot, kNbrWords: the 27 neighbour slots, then all stored (1/0)
     std::vector<int> explode;         // per ghost slot: ghost slot, parent slot, ox, oy, oz
     std::vector<uint16_t> band;       // ghost cells (local index) of each ghost block, in ghost order
     std::vector<int> band_off;        // per ghost block: start in band; one extra end entry
@@ -87,6 +92,7 @@ struct Forest {
     std::vector<IfaceEntry> iface;
     LevelParams lp{};
     // device
+    size_t off_nbr = 0;
     size_t off_pdf[2] = {0, 0}, off_flags = 0, off_slot_of[2] = {0, 0}, off_pos = 0, off_int = 0, off_ghost = 0,
            off_explode = 0, off_iface = 0, off_band = 0, off_band_off = 0, off_band_dirs = 0, off_vel = 0,
            off_sens = 0;
@@ -652,6 +658,25 @@ int build_tables(vmlbm_ctx* c, Forest& f) {
     if (V.cap && nslots > V.cap)
       return fail(c, VMLBM_ERANGE, "level %d needs %d block slots, capacity %d", l, nslots, V.cap);
   }
+  // neighbour table: per slot, the slots of the 27 blocks around it
+  // (periodic), as the level kernels look them up
+  for (int l = 0; l <= L; ++l) {
+    Forest::Lev& V = f.lv[l];
+    const int nslots = (int)(V.pos.size() / 3);
+    V.nbr.assign((size_t)nslots * kNbrWords, 0);
+    for (int s = 0; s < nslots; ++s) {
+      int* e = V.nbr.data() + (size_t)s * kNbrWords;
+      int all = 1;
+      for (int t = 0; t < 27; ++t) {
+        const int bx = Kinds::wrap1(V.pos[3 * s] + t % 3 - 1, V.nb[0]);
+        const int by = Kinds::wrap1(V.pos[3 * s + 1] + (t / 3) % 3 - 1, V.nb[1]);
+        const int bz = Kinds::wrap1(V.pos[3 * s + 2] + t / 9 - 1, V.nb[2]);
+        e[t] = V.slot_of[((long)bz * V.nb[1] + by) * V.nb[0] + bx];
+        all &= e[t] >= 0;
+      }
+      e[27] = all;
+    }
+  }
   K.tabulate_ghosts();
   // ghost cells of each ghost block
   for (int l = 0; l <= L; ++l) {
@@ -725,18 +750,11 @@ struct LevelArgs {
   int n[3], nb[3];
   const int* slot_of;
   const int* pos;      // per slot: block position x, y, z
+  const int* nbr;      // per slot: neighbour table (kNbrWords)
   uint32_t N;          // population stride (cap * 4096)
   double sp, sm, sb, F[3];
   uint32_t seed;       // stochastic-rounding stream of this sweep
 };
-
-__device__ __forceinline__ int nbr_slot(const LevelArgs& a, const int* pos3, int dx, int dy, int dz) {
-  int x = pos3[0] + dx, y = pos3[1] + dy, z = pos3[2] + dz;
-  x = x < 0 ? x + a.nb[0] : (x >= a.nb[0] ? x - a.nb[0] : x);
-  y = y < 0 ? y + a.nb[1] : (y >= a.nb[1] ? y - a.nb[1] : y);
-  z = z < 0 ? z + a.nb[2] : (z >= a.nb[2] ? z - a.nb[2] : z);
-  return a.slot_of[((long)z * a.nb[1] + y) * a.nb[0] + x];
-}
 
 // population q of local cell (x,y,z) pulled from x - c_q, via the neighbour
 // slot table nb[27]; returns false if the source block is not stored
@@ -775,11 +793,10 @@ __device__ __forceinline__ void ghost_pull(const S* __restrict__ src, const int*
   (ghost_pull_one<S, Qs>(src, nbs, slot, x, y, z, dirs, d[Qs]), ...);
 }
 
+// the 27 neighbour slots of a block and the all-stored word into LDS
+// (nbs[28]), one load per lane from the table the host built with the layout
 __device__ __forceinline__ void load_neighbours(const LevelArgs& a, int slot, int* nbs) {
-  if (threadIdx.x < 27) {
-    const int t = threadIdx.x;
-    nbs[t] = nbr_slot(a, a.pos + 3 * slot, t % 3 - 1, (t / 3) % 3 - 1, t / 9 - 1);
-  }
+  if (threadIdx.x < 28) nbs[threadIdx.x] = a.nbr[(size_t)slot * kNbrWords + threadIdx.x];
   __syncthreads();
 }
 
@@ -847,20 +864,13 @@ template <typename S, bool MRT>
 __device__ __forceinline__ void sweep_role(const S* __restrict__ src, S* __restrict__ dst,
                                            const uint8_t* __restrict__ flags, const int* __restrict__ list,
                                            int* __restrict__ status, const LevelArgs& a, uint32_t lin, uint32_t n) {
-  __shared__ int nbs[27];
-  __shared__ int all_stored;
+  __shared__ int nbs[28];
   const uint32_t item = sizeof(S) < 8 ? xcd_contiguous(lin, n) : lin;
   const int slot = list[item >> 4];
   load_neighbours(a, slot, nbs);
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    for (int t = 0; t < 27; ++t) ok &= nbs[t] >= 0;
-    all_stored = ok;
-  }
-  __syncthreads();
   const int z = (int)(item & 15u);
   // one test per workgroup instead of one per direction and cell
-  if (all_stored) sweep_plane<S, false, MRT>(src, dst, flags, status, a, nbs, slot, z);
+  if (nbs[27]) sweep_plane<S, false, MRT>(src, dst, flags, status, a, nbs, slot, z);
   else sweep_plane<S, true, MRT>(src, dst, flags, status, a, nbs, slot, z);
 }
 
@@ -881,7 +891,7 @@ __device__ __forceinline__ void ghost_role(const S* __restrict__ src, S* __restr
                                            const uint16_t* __restrict__ band, const uint32_t* __restrict__ dirs,
                                            const LevelArgs& a, int g, int part) {
   using T = typename Store<S>::T;
-  __shared__ int nbs[27];
+  __shared__ int nbs[28];
   const int slot = list[g];
   load_neighbours(a, slot, nbs);
   const int b1 = band_off[g + 1];
@@ -1054,7 +1064,7 @@ __global__ __launch_bounds__(256) void k_block_curl(const double* __restrict__ v
                                                     const uint8_t* __restrict__ flags,
                                                     const int* __restrict__ list, int n_int, LevelArgs a,
                                                     double scale, double* __restrict__ out) {
-  __shared__ int nbs[27];
+  __shared__ int nbs[28];
   __shared__ double red[4];
   const int slot = list[blockIdx.x];
   load_neighbours(a, slot, nbs);
@@ -1224,6 +1234,7 @@ LevelArgs level_args(vmlbm_ctx* c, int l, int tab) {
   for (int i = 0; i < 3; ++i) { a.n[i] = V.n[i]; a.nb[i] = V.nb[i]; }
   a.slot_of = (const int*)(c->ws + V.off_slot_of[tab]);
   a.pos = (const int*)(c->ws + V.off_pos);
+  a.nbr = (const int*)(c->ws + V.off_nbr);
   a.N = (uint32_t)V.cap * kBlockCells;
   a.sp = V.lp.sp;
   a.sm = V.lp.sm;
@@ -1269,6 +1280,8 @@ int upload_tables(vmlbm_ctx* c) {
     Forest::Lev& V = f.lv[l];
     HIP_TRY(c, hipMemcpy(c->ws + V.off_slot_of[V.tab], V.slot_of.data(), V.npos * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(c->ws + V.off_pos, V.pos.data(), V.pos.size() * sizeof(int), hipMemcpyHostToDevice));
+    if (!V.nbr.empty())
+      HIP_TRY(c, hipMemcpy(c->ws + V.off_nbr, V.nbr.data(), V.nbr.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!V.interior.empty())
       HIP_TRY(c, hipMemcpy(c->ws + V.off_int, V.interior.data(), V.interior.size() * sizeof(int), hipMemcpyHostToDevice));
     if (!V.ghost.empty())
@@ -1653,6 +1666,7 @@ int check_layout(vmlbm_ctx* c) {
       V.interior = std::move(H.interior);
       V.ghost = std::move(H.ghost);
       V.pos = std::move(H.pos);
+      V.nbr = std::move(H.nbr);
       V.explode = std::move(H.explode);
       V.band = std::move(H.band);
       V.band_off = std::move(H.band_off);
@@ -1761,6 +1775,7 @@ int refine_plan(vmlbm_ctx* c) {
     V.off_flags = take((size_t)V.cap * kBlockCells);
     for (int b = 0; b < 2; ++b) V.off_slot_of[b] = take(V.npos * sizeof(int));
     V.off_pos = take((size_t)V.cap * 3 * sizeof(int));
+    V.off_nbr = take((size_t)V.cap * kNbrWords * sizeof(int));
     V.off_int = take((size_t)V.cap * sizeof(int));
     V.off_ghost = take((size_t)V.cap * sizeof(int));
     V.off_explode = take((size_t)V.cap * 5 * sizeof(int));
