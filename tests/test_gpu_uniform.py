@@ -164,6 +164,53 @@ def test_moving_sphere_walls_parity(env, lb):
     assert np.abs(h[-1, 6:9] - xg).max() == 0.0
 
 
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-4), ("f16", 2e-2)])
+def test_moving_sphere_walls_reduced_storage(env, storage, tol):
+    """The moving-sphere case above in reduced storage (FP16 keeps its
+    populations plane-interleaved, so the link, wall, re-mapping and refill
+    kernels address them through that layout): owner maps equal to the FP64
+    oracle's every step, except at cells whose centre lies within the two
+    trajectories' distance of the surface (rounding moves the sphere by
+    about 1e-6 cells), F/T per step and the populations at the end within
+    the format's rounding (tol of the force scale; 5 tol of the largest
+    population for the state)."""
+    pkg, oracle = env
+    n = (40, 36, 48)
+    cfg = synth.base_config(n, periodic=(1, 1, 0), omega=1.7, gravity=(1e-5, 0.0, -4e-4))
+    s = synth.sphere((20.3, 17.8, 16.2), 5.2, density_ratio=0.5, cv=0.5, fixed=False,
+                     u=(0.004, -0.003, 0.0), w=(0.0, 0.002, -0.001))
+    say(f"case moving40x36x48 {storage}")
+    sim = pkg.Sim(cfg, [s], storage=storage, history=16)
+    sim.init()
+    ref = oracle.Uniform(cfg, [s])
+    ref.init()
+    changed = 0
+    worst = 0.0
+    prev = ref.owner()
+    zz, yy, xx = np.meshgrid(*[np.arange(m) + 0.5 for m in (n[2], n[1], n[0])], indexing="ij")
+    for k in range(1, 121):
+        sim.step(1)
+        ref.step(1)
+        og, oo = sim.owner(), ref.owner()
+        diff = og != oo
+        if diff.any():
+            xg, _, _ = sim.particle(0)
+            xo, _, _ = ref.particle(0)
+            gap = np.abs(xg - xo).max()
+            dist = np.sqrt((xx - xo[0]) ** 2 + (yy - xo[1]) ** 2 + (zz - xo[2]) ** 2)
+            near = np.abs(dist - 5.2) <= 2.0 * np.sqrt(3.0) * gap + 1e-12
+            assert np.all(near[diff]), f"step {k}: mapping differs away from the surface (gap {gap:.2e})"
+        changed += int((oo != prev).sum())
+        prev = oo
+        worst = max(worst, check_ft(sim, ref, 1, 5.2, tol=tol, where=f"step {k}"))
+    sim.sync()
+    fo = ref.post_collision()
+    err = np.abs(sim.populations() - fo).max()
+    say(f"  cells re-mapped {changed}; worst F/T error {worst:.2e}; population error {err:.2e}")
+    assert changed > 50
+    assert err <= 5 * tol * np.abs(fo).max()
+
+
 def test_several_fixed_spheres(env):
     """Reduced precision-sweep geometry: seeded fixed spheres, body force."""
     pkg, oracle = env
