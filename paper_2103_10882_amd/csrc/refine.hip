@@ -1011,14 +1011,11 @@ struct LevelRoles {
   const uint32_t* dirs;             // direction masks of this sub-step
 };
 
-#ifndef VM_LEVEL_WAVES
-#define VM_LEVEL_WAVES 8
-#endif
-// FP16: 8 waves per SIMD (the role arguments would otherwise hold the
-// scalar registers of a wave above the 8-wave budget; 6 % on the 3-level
-// workload); FP32 measured no better for it (2 scalar registers spilled)
+// About 60 vector and 72 scalar registers in FP16 and FP32: 8 waves per
+// SIMD (FP64: 114 and 4).  The scalar count matters: with the neighbour
+// lookups done in the prologue it was 104, which held FP16 and FP32 at 7.
 template <typename S, bool MRT>
-__global__ __launch_bounds__(256, sizeof(S) == 2 ? VM_LEVEL_WAVES : 1) void k_level(
+__global__ __launch_bounds__(256) void k_level(
     const S* __restrict__ src, S* __restrict__ dst, const uint8_t* __restrict__ flags,
     const int* __restrict__ list, int* __restrict__ status, LevelArgs a, LevelRoles r) {
   uint32_t b = blockIdx.x;
