@@ -298,6 +298,53 @@ def test_five_levels_moving_sphere_oracle(env):
     sim.close()
 
 
+def test_reversed_sphere_unpredicted_layout(env):
+    """Layout tables are built ahead for the block ranges predicted from the
+    spheres' velocities; a change that was not predicted is built at the
+    check.  A heavy sphere moves up, is turned around after the first check
+    (whose prediction was a crossing above), and its grown box then crosses
+    a level-1 node boundary below: the re-refinement takes the check's own
+    build, and F/T, layout, particle and populations follow the oracle."""
+    pkg, oracle = env
+    n0 = (32, 32, 48)
+    c = cfg_of(n0, 3, omega=1.8)
+    # lower face of the grown box (sphere box minus one finest block) 0.05
+    # cells above the level-1 node boundary at z = 64; up 0.4 cells in the
+    # first coarse step, down 0.6 in the second, so the crossing happens
+    # before any check has seen the sphere move down
+    s = synth.sphere((64.2, 63.7, 64.05 + 5.5 + 16.0), 5.5, density_ratio=1e3, cv=0.5, fixed=False,
+                     u=(0.0, 0.0, 0.1))
+    u0 = synth.velocity_perturbation(n0, seed=13)
+    say("case refined32x32x48 L3 sphere reversed after the first check, f64")
+    sim = pkg.Sim(c, [s], storage="f64", history=8, check_every=1)
+    sim.init(1.0, u0)
+    ref = oracle.Refined(c, spheres=[s], check_every=1)
+    ref.init(1.0, u0)
+    for k in range(1, 7):
+        if k == 2:
+            sim.set_sphere_motion(0, u=(0.0, 0.0, -0.15), fixed=0)
+            ref.set_sphere_motion(0, u=(0.0, 0.0, -0.15), fixed=0)
+        sim.step(1)
+        ref.step(1)
+        Fg, Tg = sim.force_torque(0)
+        Fo, To = ref.force_torque(0)
+        assert np.abs(Fg - Fo).max() <= 1e-10 * np.abs(Fo).max(), (k, Fg, Fo)
+        assert np.abs(Tg - To).max() <= 1e-10 * max(np.abs(To).max(), 5.5 * np.abs(Fo).max()), (k, Tg, To)
+    sim.sync()
+    nref, npre = sim.refinements(), sim.prebuilt_layouts()
+    _, _, nref_o = ref.counters()
+    say(f"  refinements gpu {nref} oracle {nref_o}, of which tables built ahead {npre}")
+    assert nref == nref_o and nref >= 1
+    assert npre < nref
+    xg, _, _ = sim.particle(0)
+    xo, _, _ = ref.particle(0)
+    assert np.abs(xg - xo).max() < 1e-11
+    rel = compare_levels(sim, ref, 3)
+    say(f"  population rel err {rel:.2e}")
+    assert rel <= 1e-12
+    sim.close()
+
+
 def write_from_oracle(sim, ref, levels):
     """Copy the oracle's interior populations of every level into the GPU
     grid, block by block in the GPU's slot order (same layout on both)."""
