@@ -1,7 +1,7 @@
 // Uniform-grid kernels: fused pull stream-collide sweep with the moving-wall
 // CLI boundary and momentum-exchange link forces on particle links, refill
 // of uncovered cells, and re-mapping.  The per-particle reduction and update
-// are in motion.hip.
+// are in motion.hpp.
 //
 // Layout: populations as deviations in storage type S, element (q, x, y, z)
 // at q sq + z sz + y nx + x (PopLayout: [q][z][y][x], or [z][q][y][x] for
