@@ -1,7 +1,7 @@
 // Block-structured 2:1 refined grid (Sec. 4.1-4.2) with sub-cycled levels.
 //
 // Every level stores 16^3-cell blocks in slots, populations blocked
-// [slot][q][16][16][16] (post-collision deviations, storage type S), two
+// [slot][z][q][16][16] (post-collision deviations, storage type S), two
 // buffers per level.  Level l holds its leaf blocks ("interior") and ghost
 // blocks: block positions of level l inside level-(l-1) leaves next to a
 // level-l leaf; their cells within two level-l cells of the level-l region

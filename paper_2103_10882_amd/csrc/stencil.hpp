@@ -120,15 +120,21 @@ template <typename S> using UAddrOf = UAddrT<sizeof(S) == 2>;
 using UAddr = UAddrT<false>;
 
 // One level of the block-structured grid: 16^3-cell blocks in slots
-// (cell index = slot * 4096 + local), periodic; a dense table gives the slot
-// of every block position of the level (negative: not stored at this level).
-// Populations are blocked, [slot][q][16][16][16]: the 19 populations of a
-// block are one contiguous range, so a sweep of a block and its neighbours
-// touches a few contiguous regions instead of 19 widely separated arrays.
+// (cell index = slot * 4096 + local, local = (z * 16 + y) * 16 + x),
+// periodic; a dense table gives the slot of every block position of the
+// level (negative: not stored at this level).  Populations are blocked and
+// plane-interleaved, [slot][z][q][16][16]: the 19 populations of a block
+// are one contiguous range, and within it the 19 populations of one plane
+// of the block sit side by side, so the sweep of a plane reads three
+// contiguous runs of 19 x 256 elements (planes z-1, z, z+1) and writes one.
+// Against [slot][q][16][16][16] this took the 3-level refined step from
+// 27.6k to 28.4k MLUPS in FP16 and 20.8k to 21.1k in FP32 (FP64 within its
+// run-to-run spread).
 constexpr int kBlock = 16;
 constexpr int kBlockCells = kBlock * kBlock * kBlock;
 __host__ __device__ __forceinline__ size_t bpop(int q, uint32_t c) {
-  return (size_t)(c >> 12) * (kQ * kBlockCells) + (size_t)q * kBlockCells + (c & (kBlockCells - 1));
+  return (size_t)(c >> 12) * (kQ * kBlockCells) + (size_t)((c >> 8) & 15u) * (kQ * 256) + (size_t)q * 256 +
+         (c & 255u);
 }
 struct BAddr {
   int n[3];            // cells of the level per axis
