@@ -545,88 +545,114 @@ __device__ void map_cell(int x, int y, int z, uint32_t c, uint8_t* __restrict__ 
 // (xold), so the refill reads no flags and can share a kernel with the
 // re-mapping that rewrites them.
 // ---------------------------------------------------------------------------
+// One wave refills one cell (the cell is the same in every lane).  Lanes
+// 0-17 take the D3Q19 neighbour q = lane + 1 for the density, lanes 32-34
+// the two axis neighbours of axis lane - 32 for the strain rate; each lane
+// reads its neighbours' 19 populations.  The partial results meet by
+// shuffles, and every lane then sums them in the order a single thread would
+// (neighbours 1 to 18 one after another, the rolled loop keeping one value
+// live at a time), so the refilled state does not depend on the split; lane
+// 0 stores it.  One thread per cell held 18 x 19 loads in flight and about
+// 400 registers, which held the whole re-mapping kernel at one wave per SIMD.
 template <typename S, typename A>
-__device__ void refill_cell(S* __restrict__ state, const DevParticle* __restrict__ parts, int np,
-                            const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
-                            const DevParticle& P, int* __restrict__ status) {
-  using T = typename Store<S>::T;
-  int wa = 0, ws = 0;
-  // density from old-fluid neighbours.  Each stage issues its loads for all
-  // neighbours before the first use; a neighbour that does not count reads
-  // the cell itself and is dropped afterwards.
-  uint32_t nc[kQ];
-  bool nok[kQ];
+__device__ __forceinline__ void axis_velocity(const S* __restrict__ state, const DevParticle* __restrict__ parts,
+                                              int np, const SweepParams& p, const A& ad, int x, int y, int z,
+                                              uint32_t c, const DevParticle& P, int* __restrict__ status, int a,
+                                              int side, double (&V)[3]) {
+  int s[3] = {x, y, z};
+  s[a] += side ? 1 : -1;
+  uint32_t sc = c;
+  int wa2 = 0, ws2 = 0;
+  const int st = ad.locate(s[0], s[1], s[2], sc, wa2, ws2);
+  const uint32_t src = st == 1 ? sc : c;
+  const int ow = st == 1 ? cell_owner<true>(s[0], s[1], s[2], parts, np, p) : -1;
+  double j[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-  for (int q = 1; q < kQ; ++q) {
-    uint32_t sc = c;
-    nok[q] = ad.locate(x + cx_of(q), y + cy_of(q), z + cz_of(q), sc, wa, ws) == 1;
-    nc[q] = nok[q] ? sc : c;
+  for (int q = 0; q < kQ; ++q) {
+    const double dq = (double)Store<S>::load(state[ad.pop(q, src)]);
+    j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
   }
-  double rsum = 0.0;
-  int cnt = 0;
-#pragma unroll
-  for (int q = 1; q < kQ; ++q) {
-    const bool use = nok[q] && cell_owner<true>(x + cx_of(q), y + cy_of(q), z + cz_of(q), parts, np, p) < 0;
+  if (st == 0) {
+    for (int b = 0; b < 3; ++b) V[b] = (wa2 == p.wall_axis) ? p.wall_v[ws2][b] : 0.0;
+  } else if (st < 0) {
+    status[kStatusRange] = 5;
+    double off[3];
+    sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
+    V[0] = P.u[0] + (P.w[1] * off[2] - P.w[2] * off[1]);
+    V[1] = P.u[1] + (P.w[2] * off[0] - P.w[0] * off[2]);
+    V[2] = P.u[2] + (P.w[0] * off[1] - P.w[1] * off[0]);
+  } else if (ow < 0) {
+    // post-collision momentum minus F/2 is the macroscopic velocity
+    for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
+  } else {
+    const DevParticle& Q = parts[ow];
+    double o2[3];
+    sphere_offset(Q.x, s[0] + 0.5, s[1] + 0.5, s[2] + 0.5, p.nx, p.ny, p.nz, p.per, o2);
+    V[0] = Q.u[0] + (Q.w[1] * o2[2] - Q.w[2] * o2[1]);
+    V[1] = Q.u[1] + (Q.w[2] * o2[0] - Q.w[0] * o2[2]);
+    V[2] = Q.u[2] + (Q.w[0] * o2[1] - Q.w[1] * o2[0]);
+  }
+}
+
+template <typename S, typename A>
+__device__ void refill_cell_wave(S* __restrict__ state, const DevParticle* __restrict__ parts, int np,
+                                 const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
+                                 const DevParticle& P, int* __restrict__ status) {
+  using T = typename Store<S>::T;
+  const int lane = threadIdx.x & 63;
+  // density part: 1 + sum of the deviations of an old-fluid neighbour
+  double t = 0.0;
+  int use = 0;
+  if (lane < kQ - 1) {
+    const int q = lane + 1;
+    const int qx = x + cx_of(q), qy = y + cy_of(q), qz = z + cz_of(q);
+    int wa = 0, ws = 0;
+    uint32_t sc = c;
+    const bool ok = ad.locate(qx, qy, qz, sc, wa, ws) == 1;
+    const uint32_t nc = ok ? sc : c;
+    use = ok && cell_owner<true>(qx, qy, qz, parts, np, p) < 0;
     double r = 0.0;
 #pragma unroll
-    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[ad.pop(r2, nc[q])]);
-    rsum = use ? rsum + (1.0 + r) : rsum;
-    cnt += use ? 1 : 0;
+    for (int r2 = 0; r2 < kQ; ++r2) r += (double)Store<S>::load(state[ad.pop(r2, nc)]);
+    t = 1.0 + r;
   }
+  // velocity difference across axis a between the neighbours at +1 and -1
+  // (fluid momentum, the rigid-body velocity of a solid neighbour's sphere,
+  // or the wall velocity)
+  double G[3] = {0.0, 0.0, 0.0};
+  if (lane >= 32 && lane < 35) {
+    double V0[3], V1[3];
+    axis_velocity<S, A>(state, parts, np, p, ad, x, y, z, c, P, status, lane - 32, 0, V0);
+    axis_velocity<S, A>(state, parts, np, p, ad, x, y, z, c, P, status, lane - 32, 1, V1);
+    for (int b = 0; b < 3; ++b) G[b] = V1[b] - V0[b];
+  }
+  // every lane gathers the partials and computes the same refilled cell
+  double rsum = 0.0;
+  int cnt = 0;
+#pragma unroll 1
+  for (int k = 0; k < kQ - 1; ++k) {
+    const double tk = __shfl(t, k, 64);
+    const int uk = __shfl(use, k, 64);
+    rsum = uk ? rsum + tk : rsum;
+    cnt += uk;
+  }
+  double Ga[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Ga[a][b] = __shfl(G[b], 32 + a, 64);
   const double rho = cnt ? rsum / cnt : 1.0;
   double off[3];
   sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, off);
   const double v[3] = {P.u[0] + (P.w[1] * off[2] - P.w[2] * off[1]),
                        P.u[1] + (P.w[2] * off[0] - P.w[0] * off[2]),
                        P.u[2] + (P.w[0] * off[1] - P.w[1] * off[0])};
-  // velocity at the six axis neighbours: fluid momentum, the rigid-body
-  // velocity of a solid neighbour's sphere, or the wall velocity; every
-  // source is read for every neighbour (the cell itself where it does not
-  // apply) and the applicable one is selected
-  double Vn[3][2][3];
-  bool unstored = false;
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      int s[3] = {x, y, z};
-      s[a] += side ? 1 : -1;
-      double* V = Vn[a][side];
-      uint32_t sc = c;
-      int wa2 = 0, ws2 = 0;
-      const int st = ad.locate(s[0], s[1], s[2], sc, wa2, ws2);
-      const uint32_t src = st == 1 ? sc : c;
-      const int ow = st == 1 ? cell_owner<true>(s[0], s[1], s[2], parts, np, p) : -1;
-      const DevParticle& Q = parts[ow >= 0 ? ow : 0];
-      double j[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        const double dq = (double)Store<S>::load(state[ad.pop(q, src)]);
-        j[0] += cx_of(q) * dq; j[1] += cy_of(q) * dq; j[2] += cz_of(q) * dq;
-      }
-      if (st == 0) {
-        for (int b = 0; b < 3; ++b) V[b] = (wa2 == p.wall_axis) ? p.wall_v[ws2][b] : 0.0;
-      } else if (st < 0) {
-        unstored = true;
-        for (int b = 0; b < 3; ++b) V[b] = v[b];
-      } else if (ow < 0) {
-        // post-collision momentum minus F/2 is the macroscopic velocity
-        for (int b = 0; b < 3; ++b) V[b] = j[b] - 0.5 * p.F[b];
-      } else {
-        double o2[3];
-        sphere_offset(Q.x, s[0] + 0.5, s[1] + 0.5, s[2] + 0.5, p.nx, p.ny, p.nz, p.per, o2);
-        V[0] = Q.u[0] + (Q.w[1] * o2[2] - Q.w[2] * o2[1]);
-        V[1] = Q.u[1] + (Q.w[2] * o2[0] - Q.w[0] * o2[2]);
-        V[2] = Q.u[2] + (Q.w[0] * o2[1] - Q.w[1] * o2[0]);
-      }
-    }
-  if (unstored) status[kStatusRange] = 5;
   double Sab[3][3];
   for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b)
-      Sab[a][b] = 0.25 * ((Vn[a][1][b] - Vn[a][0][b]) + (Vn[b][1][a] - Vn[b][0][a]));
+    for (int b = 0; b < 3; ++b) Sab[a][b] = 0.25 * (Ga[a][b] + Ga[b][a]);
   const double trS = Sab[0][0] + Sab[1][1] + Sab[2][2];
   const double usq = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+  if (lane != 0) return;
   T d[kQ];
   for (int q = 0; q < kQ; ++q) {
     const int cq[3] = {cx_of(q), cy_of(q), cz_of(q)};
@@ -642,15 +668,32 @@ __device__ void refill_cell(S* __restrict__ state, const DevParticle* __restrict
   for (int q = 0; q < kQ; ++q) state[ad.pop(q, c)] = Store<S>::store_sr(d[q], sr.next());
 }
 
+// the box cell k of the re-mapping region and whether its centre lies within
+// 1.6 cells of the sphere's surface at the old or the new position: a cell
+// farther off at both keeps its flags, since neither it nor any of its
+// neighbours (at most sqrt 2 away) changes side
+template <typename A>
+__device__ __forceinline__ bool remap_cell(const DevParticle& P, int k, int rb, const SweepParams& p, const A& ad,
+                                           int& x, int& y, int& z, uint32_t& c) {
+  int wa = 0, ws = 0;
+  if (k >= rb * rb * rb || !box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1)
+    return false;
+  double dn[3], dd[3];
+  sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, dn);
+  sphere_offset(P.xold, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, dd);
+  const double an = sqrt(dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2]);
+  const double ao = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
+  constexpr double kMargin = 1.6;
+  return !((an > P.r + kMargin && ao > P.r + kMargin) || (an < P.r - kMargin && ao < P.r - kMargin));
+}
+
 // Re-mapping of a moving sphere's region (its box around the old and the new
 // position) and refill of the cells it uncovered.  The two are independent
 // (the refill reads populations and the positions, the re-mapping writes
-// flags), so the first half of the workgroups re-maps and the second half
-// refills, one thread per cell each, and the kernel lasts as long as the
-// slower of the two instead of their sum.  A cell whose centre lies more
-// than 1.6 cells off the sphere's surface at both positions keeps its
-// flags: neither it nor any of its neighbours (at most sqrt 2 away)
-// changes side.
+// flags), so the first half of the workgroups re-maps, one thread per cell,
+// and the second half refills: each of its workgroups collects the
+// uncovered cells among its 256 box cells in LDS, and its four waves take
+// them one cell per wave.  The kernel lasts as long as the slower half.
 template <typename S, typename A>
 __global__ __launch_bounds__(256) void k_refill_remap(
     S* __restrict__ state, uint8_t* __restrict__ flags, uint16_t* __restrict__ owner,
@@ -662,20 +705,32 @@ __global__ __launch_bounds__(256) void k_refill_remap(
   const int half = (int)gridDim.x / 2;
   const bool refill = (int)blockIdx.x >= half;
   const int k = (refill ? (int)blockIdx.x - half : (int)blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= rb * rb * rb) return;
-  int x, y, z, wa = 0, ws = 0;
+  int x = 0, y = 0, z = 0;
   uint32_t c = 0;
-  if (!box_cell(P.remap_lo, k, rb, p, x, y, z) || ad.locate(x, y, z, c, wa, ws) != 1) return;
-  double dn[3], dd[3];
-  sphere_offset(P.x, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, dn);
-  sphere_offset(P.xold, x + 0.5, y + 0.5, z + 0.5, p.nx, p.ny, p.nz, p.per, dd);
-  const double an = sqrt(dn[0] * dn[0] + dn[1] * dn[1] + dn[2] * dn[2]);
-  const double ao = sqrt(dd[0] * dd[0] + dd[1] * dd[1] + dd[2] * dd[2]);
-  constexpr double kMargin = 1.6;
-  if ((an > P.r + kMargin && ao > P.r + kMargin) || (an < P.r - kMargin && ao < P.r - kMargin)) return;
-  if (!refill) map_cell<A>(x, y, z, c, flags, owner, parts, np, p, ad, status);
-  else if (cell_owner<true>(x, y, z, parts, np, p) == pi && cell_owner(x, y, z, parts, np, p) < 0)
-    refill_cell<S, A>(state, parts, np, p, ad, x, y, z, c, P, status);
+  const bool near = remap_cell<A>(P, k, rb, p, ad, x, y, z, c);
+  if (!refill) {
+    if (near) map_cell<A>(x, y, z, c, flags, owner, parts, np, p, ad, status);
+    return;
+  }
+  __shared__ int list[256];
+  __shared__ int wcount[4];
+  const bool todo = near && cell_owner<true>(x, y, z, parts, np, p) == pi && cell_owner(x, y, z, parts, np, p) < 0;
+  const unsigned long long m = __ballot(todo);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) wcount[wave] = __popcll(m);
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wave; ++w) base += wcount[w];
+  if (todo) list[base + __popcll(m & ((1ull << lane) - 1ull))] = k;
+  __syncthreads();
+  const int len = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+  for (int i = wave; i < len; i += 4) {
+    int rx = 0, ry = 0, rz = 0, wa = 0, ws = 0;
+    uint32_t rc = 0;
+    box_cell(P.remap_lo, list[i], rb, p, rx, ry, rz);
+    ad.locate(rx, ry, rz, rc, wa, ws);
+    refill_cell_wave<S, A>(state, parts, np, p, ad, rx, ry, rz, rc, P, status);
+  }
 }
 
 }  // namespace vm
