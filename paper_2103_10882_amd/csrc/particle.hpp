@@ -357,10 +357,13 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
   using T = typename Store<S>::T;
   constexpr int kCells = 256 / kLinkLanes;
   __shared__ T din[kCells][kQ];
-  __shared__ uint32_t list[256];
+  __shared__ int lx[256], ly[256], lz[256];
+  __shared__ uint32_t lc[256];
   __shared__ int wcount[4];
   const int pi = blockIdx.y;
-  // link cells among this workgroup's box cells, in box order
+  // link cells among this workgroup's box cells, in box order, with their
+  // coordinates and cell index (no flag is written during the pass, so the
+  // rounds below take them from here instead of locating them again)
   {
     const int k = blockIdx.x + threadIdx.x * gridDim.x;
     int x, y, z;
@@ -372,7 +375,10 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
     __syncthreads();
     int base = 0;
     for (int w = 0; w < wave; ++w) base += wcount[w];
-    if (in) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)k;
+    if (in) {
+      const int at = base + __popcll(m & ((1ull << lane) - 1ull));
+      lx[at] = x; ly[at] = y; lz[at] = z; lc[at] = c;
+    }
     __syncthreads();
   }
   const int len = wcount[0] + wcount[1] + wcount[2] + wcount[3];
@@ -386,9 +392,9 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
   // rounds are uniform over the workgroup
   for (int base = 0; base < len; base += kCells) {
     const int i = base + g;
-    int x = 0, y = 0, z = 0;
-    uint32_t c = 0;
-    const bool active = i < len && link_cell<A>(flags, owner, parts, pi, (int)list[i], p, ad, x, y, z, c);
+    const bool active = i < len;
+    const int x = active ? lx[i] : 0, y = active ? ly[i] : 0, z = active ? lz[i] : 0;
+    const uint32_t c = active ? lc[i] : 0;
     if (active) {
       if (s == 0) din[g][0] = Store<S>::load(src[ad.pop(0, c)]);
 #pragma unroll
