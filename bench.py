@@ -214,6 +214,18 @@ def run_refined(pkg, coarse_steps=500):
                    "refinements": sim.refinements(), "prebuilt_layouts": sim.prebuilt_layouts(),
                    "z_rise": float(h[-1, 8] - w["spheres"][0]["x"][2]),
                    "uz_final": float(h[-1, 11])}
+        # the coarse level's access pattern without arithmetic (vmlbm_level_pull:
+        # 19 pulls and 19 streaming stores per leaf cell), after the run
+        nb0 = int(sim.level_blocks(0).shape[0])
+        sim.level_pull(0, 2)
+        sim.sync()
+        reps = 50
+        t0 = time.perf_counter()
+        sim.level_pull(0, reps)
+        sim.sync()
+        tp = (time.perf_counter() - t0) / reps
+        out[st]["coarse_level_pull"] = {"blocks": nb0, "us": round(1e6 * tp, 1),
+                                        "gbs": round(nb0 * 4096 * 38 * BYTES[st] / tp / 1e9, 1)}
         sim.close()
         del sim
         torch.cuda.empty_cache()

@@ -217,6 +217,21 @@ int vmlbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
  * n[1] or n[2] outside 1..65535 or n[0] < 1. */
 int vmlbm_stream_pull(void* dst, const void* src, int storage, const int n[3], void* stream);
 
+/* Bandwidth reference, not part of the method: the memory access pattern of
+ * one level's sweep on the block-structured grid (Sec. 4.1; the pull form
+ * of Eq. 1 in 16^3-cell blocks) without its arithmetic.  Every cell of the
+ * level's leaf blocks takes population q from x - c_q (periodic, through the
+ * level's blocks as the sweep reads them; a source in a block the level does
+ * not store gives 0) and stores it unchanged, with the sweep's workgroup
+ * numbering and streaming stores; no flags, collision or rounding.  The
+ * pulled state becomes the level's current state; `reps` such pulls are
+ * enqueued on the context's stream (asynchronous, like vmlbm_step).  On a
+ * single-level periodic grid one pull is the exact periodic shift of each
+ * population by c_q.  VMLBM_ESTATE on a uniform grid, without a workspace or
+ * before vmlbm_init_equilibrium; VMLBM_EINVAL for a level outside 0..L or
+ * reps < 1. */
+int vmlbm_level_pull(vmlbm_ctx* ctx, int level, int reps);
+
 /* Totals of the post-collision state over fluid cells: mass sum f~ and
  * momentum sum c f~, the conserved moments of Sec. 2.1 (refined grid: every
  * level weighted by its cell volume 8^-l in coarse units, the volume scaling

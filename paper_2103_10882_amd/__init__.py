@@ -26,7 +26,7 @@ EXPORTS = [
     "vmlbm_get_force_torque", "vmlbm_get_history", "vmlbm_read_populations",
     "vmlbm_write_populations", "vmlbm_read_owner", "vmlbm_read_fields", "vmlbm_stats",
     "vmlbm_profile", "vmlbm_sweep_time", "vmlbm_totals", "vmlbm_read_box", "vmlbm_cell_counts", "vmlbm_level_blocks",
-    "vmlbm_refinements", "vmlbm_prebuilt_layouts",
+    "vmlbm_refinements", "vmlbm_prebuilt_layouts", "vmlbm_level_pull",
     "vmlbm_set_params", "vmlbm_forward_ckpt", "vmlbm_adjoint", "vmlbm_destroy", "vmlbm_last_error",
     "vmlbm_stream_copy", "vmlbm_stream_pull", "vmlbm_totals_static",
 ]
@@ -95,6 +95,7 @@ def lib():
             "vmlbm_level_blocks": [vp, ctypes.c_int, vp, vp],
             "vmlbm_refinements": [vp, vp],
             "vmlbm_prebuilt_layouts": [vp, vp],
+            "vmlbm_level_pull": [vp, ctypes.c_int, ctypes.c_int],
             "vmlbm_set_params": [vp, ctypes.c_double, ctypes.c_double],
             "vmlbm_forward_ckpt": [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp],
             "vmlbm_adjoint": [vp, ctypes.c_double, vp],
@@ -331,6 +332,12 @@ class Sim:
         c = ctypes.c_int()
         self._check(self.L.vmlbm_prebuilt_layouts(self.h, ctypes.byref(c)), "prebuilt_layouts")
         return c.value
+
+    def level_pull(self, level, reps=1):
+        """Block-structured grid: the level sweep's access pattern without
+        arithmetic (a bandwidth reference), `reps` times on the context's
+        stream; each pulled state becomes the level's current state."""
+        self._check(self.L.vmlbm_level_pull(self.h, int(level), int(reps)), "level_pull")
 
     # --- differentiation ------------------------------------------------------
     def set_params(self, body_force_z, omega):

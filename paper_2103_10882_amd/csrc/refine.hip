@@ -1031,6 +1031,48 @@ __global__ __launch_bounds__(256) void k_level(
   if ((int)b < r.n_iface_wg) iface_role<S>(src, dst, (const S*)r.fine, r.iface, r.n_iface, status, a, (int)b);
 }
 
+// The level sweep's access pattern without arithmetic: every cell of the
+// level's leaf blocks takes population q from x - c_q through the sweep's
+// numbering, neighbour table and block addressing, and stores it, raw, with
+// the sweep's streaming stores; no flags, collision or rounding.  A source in
+// a block that is not stored gives 0.  A reference for the bandwidth the
+// 16^3-block pattern alone reaches.
+template <typename S, int Q, bool CHECK>
+__device__ __forceinline__ S pull_raw(const S* __restrict__ src, const int* nbs, int slot, int x, int y, int z) {
+  constexpr int cx = cx_of(Q), cy = cy_of(Q), cz = cz_of(Q);
+  const int xs = x - cx, ys = y - cy, zs = z - cz;
+  const int bx = xs < 0 ? -1 : (xs > 15 ? 1 : 0), by = ys < 0 ? -1 : (ys > 15 ? 1 : 0),
+            bz = zs < 0 ? -1 : (zs > 15 ? 1 : 0);
+  int s = (bx | by | bz) ? nbs[(bz + 1) * 9 + (by + 1) * 3 + (bx + 1)] : slot;
+  const bool missing = CHECK && s < 0;
+  s = missing ? slot : s;
+  const uint32_t c = (uint32_t)s * kBlockCells + (uint32_t)(((zs & 15) * 16 + (ys & 15)) * 16 + (xs & 15));
+  const S v = src[bpop(Q, c)];
+  return missing ? Store<S>::store(typename Store<S>::T(0)) : v;
+}
+
+template <typename S, bool CHECK, int... Qs>
+__device__ __forceinline__ void pull_raw_cell(const S* __restrict__ src, S* __restrict__ dst, const int* nbs,
+                                              int slot, int x, int y, int z, uint32_t c,
+                                              std::integer_sequence<int, Qs...>) {
+  const S v[kQ] = {pull_raw<S, Qs, CHECK>(src, nbs, slot, x, y, z)...};
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) store_nt(&dst[bpop(q, c)], v[q]);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void k_level_pull(const S* __restrict__ src, S* __restrict__ dst,
+                                                    const int* __restrict__ list, LevelArgs a, uint32_t n) {
+  __shared__ int nbs[28];
+  const uint32_t item = sizeof(S) < 8 ? xcd_contiguous(blockIdx.x, n) : blockIdx.x;
+  const int slot = list[item >> 4];
+  load_neighbours(a, slot, nbs);
+  const int z = (int)(item & 15u), x = threadIdx.x & 15, y = (threadIdx.x >> 4) & 15;
+  const uint32_t c = (uint32_t)slot * kBlockCells + (uint32_t)((z * 16 + y) * 16 + x);
+  if (nbs[27]) pull_raw_cell<S, false>(src, dst, nbs, slot, x, y, z, c, std::make_integer_sequence<int, kQ>{});
+  else pull_raw_cell<S, true>(src, dst, nbs, slot, x, y, z, c, std::make_integer_sequence<int, kQ>{});
+}
+
 // stored post-collision velocity of every interior cell of a level:
 // u = sum_q c_q d_q - F_l / 2, as vel[a * N + c]
 template <typename S>
@@ -2030,6 +2072,31 @@ int refine_add_region(vmlbm_ctx* c, const int lo[3], const int hi[3], int level)
   return VMLBM_OK;
 }
 
+// the level's pull without arithmetic (k_level_pull) `reps` times, each
+// making the pulled state current
+int refine_level_pull(vmlbm_ctx* c, int l, int reps) {
+  Forest& f = *c->forest;
+  int rc = join_side(c);
+  if (rc) return rc;
+  Forest::Lev& V = f.lv[l];
+  const uint32_t n = (uint32_t)V.n_int * kBlock;
+  const LevelArgs a = level_args(c, l, V.tab);
+  for (int r = 0; r < reps; ++r) {
+    if (n) {
+      rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
+        using S = std::remove_pointer_t<decltype(tag)>;
+        k_level_pull<S><<<n, 256, 0, c->stream>>>((const S*)(c->ws + V.off_pdf[V.cur]), (S*)(c->ws + V.off_pdf[1 - V.cur]),
+                                                  (const int*)(c->ws + V.off_int), a, n);
+        HIP_TRY(c, hipGetLastError());
+        return VMLBM_OK;
+      });
+      if (rc) return rc;
+    }
+    V.cur = 1 - V.cur;
+  }
+  return VMLBM_OK;
+}
+
 }  // namespace vm
 
 using namespace vm;
@@ -2066,6 +2133,16 @@ int vmlbm_prebuilt_layouts(vmlbm_ctx* c, int* count) {
   if (!c || !count) return VMLBM_EINVAL;
   *count = c->forest ? c->forest->prebuilt_taken : 0;
   return VMLBM_OK;
+}
+
+int vmlbm_level_pull(vmlbm_ctx* c, int level, int reps) {
+  if (!c) return VMLBM_EINVAL;
+  if (c->cfg.block <= 0 || !c->forest) return fail(c, VMLBM_ESTATE, "not a block-structured grid");
+  if (!c->ws) return fail(c, VMLBM_ESTATE, "workspace not bound");
+  if (!c->initialized) return fail(c, VMLBM_ESTATE, "vmlbm_init_equilibrium not called");
+  if (level < 0 || level > c->forest->L) return fail(c, VMLBM_EINVAL, "bad level");
+  if (reps < 1) return fail(c, VMLBM_EINVAL, "reps must be at least 1");
+  return refine_level_pull(c, level, reps);
 }
 
 }  // extern "C"

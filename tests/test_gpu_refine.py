@@ -669,3 +669,75 @@ def test_large_sphere_refined(env):
     rel = compare_levels(sim, ref, 2)
     say(f"  population rel err {rel:.2e}")
     assert rel <= 1e-12
+
+
+
+def _level_field(sim, level, n):
+    """A level's interior populations on its full cell grid (0 outside its
+    leaf blocks) and the mask of its leaf cells."""
+    org = sim.level_blocks(level)
+    f = sim.populations(level).reshape(19, len(org), 16, 16, 16)
+    full = np.zeros((19, n[2], n[1], n[0]))
+    mask = np.zeros((n[2], n[1], n[0]), dtype=bool)
+    for b, (x, y, z) in enumerate(org):
+        full[:, z:z + 16, y:y + 16, x:x + 16] = f[:, b]
+        mask[z:z + 16, y:y + 16, x:x + 16] = True
+    return full, mask
+
+
+def _blocks_of(full, org):
+    """Populations of a full level grid in the level's slot order."""
+    f = np.empty((19, len(org), 16, 16, 16))
+    for b, (x, y, z) in enumerate(org):
+        f[:, b] = full[:, z:z + 16, y:y + 16, x:x + 16]
+    return f.reshape(19, -1)
+
+
+def _shift(a, c, k=1):
+    """a moved by k c along (x, y, z): out[x] = a[x - k c], periodic."""
+    return np.roll(a, shift=(k * int(c[2]), k * int(c[1]), k * int(c[0])), axis=(0, 1, 2))
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_level_pull_reference(env, storage):
+    """The bandwidth reference with the level sweep's access pattern moves
+    population q of every leaf cell from x - c_q through the level's blocks,
+    bit for bit: on a single-level grid one pull is the periodic shift of
+    each population by c_q and two pulls the shift by 2 c_q; on the coarse
+    level of a 3-level grid a source inside the refined region, which the
+    level does not store, gives 0."""
+    pkg, oracle = env
+    c_lat, _, _ = oracle.lattice()
+    rng = np.random.default_rng(11)
+
+    say(f"case level pull single level 48x32x16 {storage}")
+    n0 = (48, 32, 16)
+    sim = pkg.Sim(cfg_of(n0, 1), [], storage=storage, check_every=0)
+    sim.init()
+    org = sim.level_blocks(0)
+    sim.write_populations(rng.uniform(-0.02, 0.02, size=(19, len(org) * 4096)), 0)
+    f0, mask = _level_field(sim, 0, n0)
+    assert mask.all()
+    for reps in (1, 2):
+        sim.write_populations(_blocks_of(f0, org), 0)
+        sim.level_pull(0, reps)
+        sim.sync()
+        got, _ = _level_field(sim, 0, n0)
+        want = np.stack([_shift(f0[q], c_lat[q], reps) for q in range(19)])
+        assert np.array_equal(got, want), f"{reps} pull(s)"
+    sim.close()
+
+    say(f"case level pull coarse level of 3, 32^3 {storage}")
+    n0 = (32, 32, 32)
+    sim = pkg.Sim(cfg_of(n0, 3), [], storage=storage, regions=REGIONS, check_every=0)
+    sim.init()
+    org = sim.level_blocks(0)
+    sim.write_populations(rng.uniform(-0.02, 0.02, size=(19, len(org) * 4096)), 0)
+    f0, mask = _level_field(sim, 0, n0)
+    assert not mask.all()
+    sim.level_pull(0, 1)
+    sim.sync()
+    got, _ = _level_field(sim, 0, n0)
+    want = np.stack([np.where(_shift(mask, c_lat[q]), _shift(f0[q], c_lat[q]), 0.0) for q in range(19)])
+    assert np.array_equal(got[:, mask], want[:, mask])
+    sim.close()
