@@ -418,9 +418,12 @@ __global__ __launch_bounds__(256) void k_link_cells(const S* __restrict__ src, S
         const T v = Store<S>::load(src[ad.pop(q, si)]);
         const T own_q = Store<S>::load(src[ad.pop(q, c)]);
         const T own_qq = Store<S>::load(src[ad.pop(qq, c)]);
+        // the second node's population is read before its flag decides
+        // whether it is used (ti is the cell itself where it is not stored)
+        const T sec_t = Store<S>::load(src[ad.pop(qq, ti)]);
         const bool wall = st == 0, link = wall || (sf & kSolid);
         const bool tok = link && !wall && st2 == 1 && !(tf & kSolid);
-        const T sec = Store<S>::load(src[ad.pop(qq, tok ? ti : c)]);
+        const T sec = tok ? sec_t : own_qq;
         T out = v;
         if (link && wall) {
           // halfway wall: delta = 1/2 -> kappa0 = 0, alpha = 2
