@@ -911,18 +911,40 @@ __device__ __forceinline__ void ghost_role(const S* __restrict__ src, S* __restr
 
 // explosion: every ghost cell of level l+1 takes its parent's populations
 // (level l, current state), those of its explosion mask (dirs, stride 3);
-// ghost block g is explode entry g
+// ghost block g is explode entry g.  The explosions that follow each other
+// with no sweep between them (those of levels l, l+1, ... at the start of a
+// level-l step) run as one launch: explosion l writes level l+1's ghost
+// blocks and explosion l+1 reads its leaf blocks, so they touch disjoint
+// slots.  Set k covers workgroups first .. the next set's first - 1.
+struct ExplodeSet {
+  const void* coarse;
+  void* fine;
+  const int* ex;
+  const int* band_off;
+  const uint16_t* band;
+  const uint32_t* dirs;
+  int first;
+};
+struct ExplodeChain {
+  ExplodeSet set[kMaxLevels - 1];
+  int n;
+};
+
 template <typename S>
-__global__ __launch_bounds__(256) void k_explode(const S* __restrict__ coarse, S* __restrict__ fine,
-                                                 const int* __restrict__ ex, const int* __restrict__ band_off,
-                                                 const uint16_t* __restrict__ band, const uint32_t* __restrict__ dirs) {
-  const int* e = ex + 5 * blockIdx.x;
-  const int gs = e[0], ps = e[1], ox = e[2], oy = e[3], oz = e[4];
-  const int b1 = band_off[blockIdx.x + 1];
-  for (int i = band_off[blockIdx.x] + blockIdx.y * blockDim.x + threadIdx.x; i < b1; i += gridDim.y * blockDim.x) {
-    const uint32_t m = dirs[3 * i];
+__global__ __launch_bounds__(256) void k_explode(ExplodeChain ch) {
+  int k = 0;
+  while (k + 1 < ch.n && (int)blockIdx.x >= ch.set[k + 1].first) ++k;
+  const ExplodeSet& e = ch.set[k];
+  const S* __restrict__ coarse = (const S*)e.coarse;
+  S* __restrict__ fine = (S*)e.fine;
+  const int g = (int)blockIdx.x - e.first;
+  const int* en = e.ex + 5 * g;
+  const int gs = en[0], ps = en[1], ox = en[2], oy = en[3], oz = en[4];
+  const int b1 = e.band_off[g + 1];
+  for (int i = e.band_off[g] + blockIdx.y * blockDim.x + threadIdx.x; i < b1; i += gridDim.y * blockDim.x) {
+    const uint32_t m = e.dirs[3 * i];
     if (!m) continue;
-    const int local = band[i];
+    const int local = e.band[i];
     const int x = local & 15, y = (local >> 4) & 15, z = local >> 8;
     const uint32_t cf = (uint32_t)gs * kBlockCells + (uint32_t)local;
     const uint32_t cc = (uint32_t)ps * kBlockCells +
@@ -1370,17 +1392,29 @@ int mark_flags(vmlbm_ctx* c) {
   return VMLBM_OK;
 }
 
-int explode(vmlbm_ctx* c, int l) {
+// explosions of levels l .. L-1 into the next finer level, one launch
+int explode_chain(vmlbm_ctx* c, int l) {
   Forest& f = *c->forest;
-  Forest::Lev& C = f.lv[l];
-  Forest::Lev& F = f.lv[l + 1];
-  if (!F.n_ghost) return VMLBM_OK;
+  ExplodeChain ch{};
+  int total = 0;
+  for (int k = l; k < f.L; ++k) {
+    Forest::Lev& C = f.lv[k];
+    Forest::Lev& F = f.lv[k + 1];
+    if (!F.n_ghost) continue;
+    ExplodeSet& e = ch.set[ch.n++];
+    e.coarse = c->ws + C.off_pdf[C.cur];
+    e.fine = c->ws + F.off_pdf[F.cur];
+    e.ex = (const int*)(c->ws + F.off_explode);
+    e.band_off = (const int*)(c->ws + F.off_band_off);
+    e.band = (const uint16_t*)(c->ws + F.off_band);
+    e.dirs = (const uint32_t*)(c->ws + F.off_band_dirs);
+    e.first = total;
+    total += F.n_ghost;
+  }
+  if (!total) return VMLBM_OK;
   return dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
-    k_explode<S><<<dim3(F.n_ghost, kBandSplit), 256, 0, c->stream>>>(
-        (const S*)(c->ws + C.off_pdf[C.cur]), (S*)(c->ws + F.off_pdf[F.cur]), (const int*)(c->ws + F.off_explode),
-        (const int*)(c->ws + F.off_band_off), (const uint16_t*)(c->ws + F.off_band),
-        (const uint32_t*)(c->ws + F.off_band_dirs));
+    k_explode<S><<<dim3(total, kBandSplit), 256, 0, c->stream>>>(ch);
     HIP_TRY(c, hipGetLastError());
     return VMLBM_OK;
   });
@@ -1509,12 +1543,14 @@ int sweep_level(vmlbm_ctx* c, int l, int sub) {
   return VMLBM_OK;
 }
 
-int step_level(vmlbm_ctx* c, int l, int sub) {
+// exploded: the explosion of level l (into l + 1) has already run, in the
+// launch of the coarser level's step that also covered it
+int step_level(vmlbm_ctx* c, int l, int sub, bool exploded = false) {
   Forest& f = *c->forest;
   if (l < f.L) {
-    int rc = explode(c, l);
+    int rc = exploded ? VMLBM_OK : explode_chain(c, l);
     if (rc) return rc;
-    rc = step_level(c, l + 1, 0);
+    rc = step_level(c, l + 1, 0, true);
     if (rc) return rc;
     rc = step_level(c, l + 1, 1);
     if (rc) return rc;
