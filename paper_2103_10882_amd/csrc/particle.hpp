@@ -554,15 +554,9 @@ __device__ void map_cell(int x, int y, int z, uint32_t c, uint8_t* __restrict__ 
 // (xold), so the refill reads no flags and can share a kernel with the
 // re-mapping that rewrites them.
 // ---------------------------------------------------------------------------
-// One wave refills one cell (the cell is the same in every lane).  Lanes
-// 0-17 take the D3Q19 neighbour q = lane + 1 for the density, lanes 32-34
-// the two axis neighbours of axis lane - 32 for the strain rate; each lane
-// reads its neighbours' 19 populations.  The partial results meet by
-// shuffles, and every lane then sums them in the order a single thread would
-// (neighbours 1 to 18 one after another, the rolled loop keeping one value
-// live at a time), so the refilled state does not depend on the split; lane
-// 0 stores it.  One thread per cell held 18 x 19 loads in flight and about
-// 400 registers, which held the whole re-mapping kernel at one wave per SIMD.
+// velocity at the neighbour of cell (x, y, z) across axis a on side `side`
+// (0: -1, 1: +1): fluid momentum, the rigid-body velocity of a solid
+// neighbour's sphere, or the wall velocity
 template <typename S, typename A>
 __device__ __forceinline__ void axis_velocity(const S* __restrict__ state, const DevParticle* __restrict__ parts,
                                               int np, const SweepParams& p, const A& ad, int x, int y, int z,
@@ -603,6 +597,15 @@ __device__ __forceinline__ void axis_velocity(const S* __restrict__ state, const
   }
 }
 
+// One wave refills one cell (the cell is the same in every lane).  Lanes
+// 0-17 take the D3Q19 neighbour q = lane + 1 for the density, lanes 32-34
+// the two axis neighbours of axis lane - 32 for the strain rate; each lane
+// reads its neighbours' 19 populations.  The partial results meet by
+// shuffles, and every lane then sums them in the order a single thread would
+// (neighbours 1 to 18 one after another, the rolled loop keeping one value
+// live at a time), so the refilled state does not depend on the split; lane
+// 0 stores it.  One thread per cell held 18 x 19 loads in flight and about
+// 400 registers, which held the whole re-mapping kernel at one wave per SIMD.
 template <typename S, typename A>
 __device__ void refill_cell_wave(S* __restrict__ state, const DevParticle* __restrict__ parts, int np,
                                  const SweepParams& p, const A& ad, int x, int y, int z, uint32_t c,
