@@ -54,12 +54,32 @@ def test_host_only_calls(pkg):
     assert b"workspace" in L.vmlbm_last_error(h)
     zero = (ctypes.c_double * 3)()
     assert L.vmlbm_set_sphere_motion(h, 0, zero, zero, 2) == -4
+    # the level-pull bandwidth reference needs a block-structured grid
+    assert L.vmlbm_level_pull(h, 0, 1) == -4
+    assert b"block-structured" in L.vmlbm_last_error(h)
+    assert L.vmlbm_level_pull(None, 0, 1) == -1
     # sphere parameters outside their ranges
     bad = pkg.make_sphere(synth.sphere((4.0, 4.0, 4.0), 2.0))
     bad.fixed = 3
     assert L.vmlbm_add_sphere(h, ctypes.byref(bad), ctypes.byref(i)) == -1
     bad = pkg.make_sphere(synth.sphere((4.0, 4.0, 4.0), 2.0, vm_scheme=3))
     assert L.vmlbm_add_sphere(h, ctypes.byref(bad), ctypes.byref(i)) == -1
+    assert L.vmlbm_destroy(h) == 0
+
+
+def test_level_pull_refused_before_workspace(pkg):
+    """vmlbm_level_pull on a block-structured grid: no workspace is an
+    ordering error; levels outside 0..L and reps < 1 are rejected once one is
+    bound (checked on the GPU)."""
+    L = pkg.lib()
+    cfg = synth.base_config((32, 32, 32))
+    cfg["levels"] = 2
+    cfg["block"] = 16
+    c = pkg.make_config(cfg, "f32")
+    h = ctypes.c_void_p()
+    assert L.vmlbm_create(ctypes.byref(c), ctypes.byref(h)) == 0
+    assert L.vmlbm_level_pull(h, 0, 1) == -4
+    assert b"workspace" in L.vmlbm_last_error(h)
     assert L.vmlbm_destroy(h) == 0
 
 

@@ -725,6 +725,10 @@ def test_level_pull_reference(env, storage):
         got, _ = _level_field(sim, 0, n0)
         want = np.stack([_shift(f0[q], c_lat[q], reps) for q in range(19)])
         assert np.array_equal(got, want), f"{reps} pull(s)"
+    # a level the grid does not have, and no pull at all, are refused
+    for level, reps in ((1, 1), (-1, 1), (0, 0)):
+        with pytest.raises(pkg.VmlbmError):
+            sim.level_pull(level, reps)
     sim.close()
 
     say(f"case level pull coarse level of 3, 32^3 {storage}")
