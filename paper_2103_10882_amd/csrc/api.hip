@@ -196,8 +196,13 @@ UpdateParams update_params(const vmlbm_ctx* c, long long step) {
 }
 
 // one sweep src -> dst: boundary cells on the side stream, concurrently with
-// the interior sweep; joined back into the main stream
-int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1) {
+// the interior sweep; joined back into the main stream.  With `up`, the
+// force/torque reduction and particle update follow the boundary cells on
+// the side stream (they read the link pass's slots and the particle
+// records, which the interior sweep does not touch), so they too run
+// beside the interior sweep.
+int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1,
+               const UpdateParams* up) {
   const int np = (int)c->spheres.size();
   const bool flags = c->use_flags;
   if (flags) {
@@ -206,9 +211,12 @@ int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEven
   }
   int rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
     using S = std::remove_pointer_t<decltype(tag)>;
-    if (flags)
+    if (flags) {
       HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->links(), c->slots(),
                                     c->status(), p, c->side));
+      if (up && np > 0)
+        HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, *up, c->side));
+    }
     HIP_TRY(c, launch_interior<S>(src, dst, c->flags(), c->status(), p, flags, c->stream, e0, e1));
     return VMLBM_OK;
   });
@@ -233,11 +241,10 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
       HIP_TRY(c, hipEventCreate(&e1));
       c->sweep_events.emplace_back(e0, e1);
     }
-    int rc = sweep_once(c, p, src, dst, e0, e1);
+    const UpdateParams up = update_params(c, c->steps_done);
+    int rc = sweep_once(c, p, src, dst, e0, e1, &up);
     if (rc) return rc;
     if (np > 0) {
-      HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p,
-                                      update_params(c, c->steps_done), c->stream));
       if (c->moving) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;

@@ -96,7 +96,8 @@ int dispatch(int storage, F&& f) {
 
 struct SweepParams;
 SweepParams sweep_params(const vmlbm_ctx* c);
-int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1);
+int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEvent_t e0, hipEvent_t e1,
+               const UpdateParams* up = nullptr);
 // particle-update parameters of finest step / uniform step `step`
 UpdateParams update_params(const vmlbm_ctx* c, long long step);
 size_t storage_bytes(int storage);
