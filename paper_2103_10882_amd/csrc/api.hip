@@ -93,8 +93,10 @@ void plan_uniform(vmlbm_ctx* c) {
   int box = 0;
   for (const auto& s : c->spheres) box = std::max(box, (int)std::ceil(2.0 * s.radius) + 7);
   c->box = box;
-  // one force slot per workgroup of the link-cell pass of a sphere
-  c->slot_stride = (size_t)kLinkGroups * kSlotWords;
+  // one force slot per workgroup of the link-cell pass of a sphere: with
+  // moving spheres the pass scans each sphere's box (no link lists to
+  // rebuild after every re-mapping), with fixed ones it reads the lists
+  c->slot_stride = (size_t)(c->moving ? link_chunks(box) : kLinkGroups) * kSlotWords;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
   c->off_status = take(kStatusWords * sizeof(int));
@@ -213,7 +215,7 @@ int sweep_once(vmlbm_ctx* c, const SweepParams& p, void* src, void* dst, hipEven
     using S = std::remove_pointer_t<decltype(tag)>;
     if (flags) {
       HIP_TRY(c, launch_boundary<S>(src, dst, c->flags(), c->owner(), c->parts(), np, c->links(), c->slots(),
-                                    c->status(), p, c->side));
+                                    c->status(), p, c->side, c->moving));
       if (up && np > 0)
         HIP_TRY(c, launch_reduce_update(c->parts(), np, c->slots(), c->hist(), c->status(), p, *up, c->side));
     }
@@ -249,7 +251,7 @@ int uniform_step(vmlbm_ctx* c, int nsteps) {
         rc = dispatch(c->cfg.storage, [&](auto* tag) -> int {
           using S = std::remove_pointer_t<decltype(tag)>;
           HIP_TRY(c, launch_refill_remap<S>(dst, c->flags(), c->owner(), c->parts(), np, c->links(), p, c->status(),
-                                            c->stream));
+                                            c->stream, true));
           return VMLBM_OK;
         });
         if (rc) return rc;

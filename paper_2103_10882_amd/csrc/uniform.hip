@@ -315,9 +315,14 @@ hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int
 template <typename S>
 hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
                            const DevParticle* parts, int np, const LinkLists& ll, double* slots, int* status,
-                           const SweepParams& p, hipStream_t st) {
+                           const SweepParams& p, hipStream_t st, bool scan) {
   hipError_t e = hipSuccess;
-  if (np > 0) {
+  if (np > 0 && scan) {
+    k_link_cells<S, UAddrOf<S>><<<dim3(link_chunks(p.box), np), dim3(256), 0, st>>>(
+        (const S*)src, (S*)dst, flags, owner, parts, slots, status, p, uaddr<sizeof(S) == 2>(p));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  } else if (np > 0) {
     k_boundary_particles<S, UAddrOf<S>><<<dim3(kLinkGroups, np), dim3(256), 0, st>>>(
         (const S*)src, (S*)dst, flags, owner, parts, ll.links, ll.len, slots, status, p, uaddr<sizeof(S) == 2>(p));
     e = hipGetLastError();
@@ -381,36 +386,36 @@ hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* pa
 
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                               const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st) {
+                               const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st, bool scan) {
   const int rb = p.box + 1;
   dim3 grid(2 * ((rb * rb * rb + 255) / 256), np), block(256);
   k_refill_remap<S, UAddrOf<S>><<<grid, block, 0, st>>>((S*)state, flags, owner, parts, np, p,
                                                         uaddr<sizeof(S) == 2>(p), status);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || scan) return e;
   return launch_link_lists<UAddr>(flags, owner, parts, np, p, uaddr(p), ll.count, ll.links, ll.len, st);
 }
 
 template hipError_t launch_interior<double>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<double>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
+                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t, bool);
 template hipError_t launch_interior<float>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<float>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                           int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
+                                           int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t, bool);
 template hipError_t launch_interior<__half>(const void*, void*, const uint8_t*, int*, const SweepParams&, bool,
                                             hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_boundary<__half>(const void*, void*, const uint8_t*, const uint16_t*, const DevParticle*,
-                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t);
+                                            int, const LinkLists&, double*, int*, const SweepParams&, hipStream_t, bool);
 template hipError_t launch_init<double>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_init<float>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_init<__half>(void*, const uint8_t*, const double*, double, const SweepParams&, hipStream_t);
 template hipError_t launch_refill_remap<double>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                                const LinkLists&, const SweepParams&, int*, hipStream_t);
+                                                const LinkLists&, const SweepParams&, int*, hipStream_t, bool);
 template hipError_t launch_refill_remap<float>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                               const LinkLists&, const SweepParams&, int*, hipStream_t);
+                                               const LinkLists&, const SweepParams&, int*, hipStream_t, bool);
 template hipError_t launch_refill_remap<__half>(void*, uint8_t*, uint16_t*, const DevParticle*, int,
-                                                const LinkLists&, const SweepParams&, int*, hipStream_t);
+                                                const LinkLists&, const SweepParams&, int*, hipStream_t, bool);
 
 }  // namespace vm

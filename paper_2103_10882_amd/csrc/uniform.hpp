@@ -90,19 +90,24 @@ template <typename S>
 hipError_t launch_interior(const void* src, void* dst, const uint8_t* flags, int* status, const SweepParams& p,
                            bool with_flags, hipStream_t st, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // particle-link and wall-link cells; writes cells disjoint from the
-// interior sweep, so both may run concurrently
+// interior sweep, so both may run concurrently.  scan: find the particle
+// link cells in each sphere's box (k_link_cells, one force slot per 256 box
+// cells) instead of reading the link lists (kLinkGroups slots per sphere)
 template <typename S>
 hipError_t launch_boundary(const void* src, void* dst, const uint8_t* flags, const uint16_t* owner,
                            const DevParticle* parts, int np, const LinkLists& ll, double* slots, int* status,
-                           const SweepParams& p, hipStream_t st);
+                           const SweepParams& p, hipStream_t st, bool scan = false);
 template <typename S>
 hipError_t launch_init(void* dst, const uint8_t* flags, const double* u0, double drho, const SweepParams& p,
                        hipStream_t st);
 hipError_t launch_map_all(uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
                           const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st);
+// re-mapping and refill; the link lists are rebuilt unless the boundary
+// pass scans the boxes (scan)
 template <typename S>
 hipError_t launch_refill_remap(void* state, uint8_t* flags, uint16_t* owner, const DevParticle* parts, int np,
-                               const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st);
+                               const LinkLists& ll, const SweepParams& p, int* status, hipStream_t st,
+                               bool scan = false);
 // plain device copy of bytes (a multiple of 16): the bandwidth reference
 hipError_t launch_stream_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 // the interior sweep's access pattern without arithmetic (a bandwidth
